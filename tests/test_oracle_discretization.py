@@ -1,0 +1,186 @@
+"""Pins of the oracle's residual and Jacobian assembly (paper Sec. 2.1-2.2):
+conservation, lake at rest (well-balancing, dry cells included), brute-force
+finite-difference Jacobians on tiny grids, and the pinning rules."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_06721_amd import workloads as W
+
+
+def tiny(dim, nx, ny, seed, bc, flux=W.LLF, **kw):
+    z, U = W.random_state(dim, nx, ny, seed)
+    p = W.default_params(dim, flux=flux, **kw)
+    return W.Problem("tiny", dim, nx, ny, 0.0, 1.0 * nx / 4, 0.0, 1.0 * ny / 4 if dim == 2 else 1.0,
+                     bc, p, z, np.zeros_like(U)), U
+
+
+WALLS = [W.wall(), W.wall(), W.wall(), W.wall()]
+CHAN = [W.open_q(0.8, 0.0), W.open_h(1.1), W.wall(), W.wall(W.SLIP)]
+
+
+@pytest.mark.parametrize("dim,nx,ny", [(1, 9, 1), (2, 7, 5), (2, 8, 8)])
+@pytest.mark.parametrize("flux", [W.HLL, W.LLF])
+def test_mass_conservation_with_walls(dim, nx, ny, flux):
+    """With walls on every side no mass crosses the boundary, so the mass
+    components of the residual sum to zero for any state (each face flux
+    enters two cells with opposite signs)."""
+    for seed in range(5):
+        prob, U = tiny(dim, nx, ny, seed, WALLS, flux)
+        R, _ = oracle.residual(prob, U)
+        scale = np.abs(R[0]).max()
+        assert abs(R[0].sum()) <= 1e-14 * max(scale, 1e-300) * R[0].size
+
+
+def test_lake_at_rest_2d_residual():
+    """Lake at rest with a dry island: R vanishes to roundoff on wet cells
+    and exactly on dry cells (well-balanced, eq:GNeqsSTEEADY2)."""
+    prob = W.lake_island(64)
+    R, tot = oracle.residual(prob, prob.U0)
+    dry = prob.U0[0] == 0
+    assert dry.sum() > 0
+    assert (R[:, dry] == 0).all()
+    assert np.abs(R).max() < 1e-16
+    iso = oracle.isolated(prob, prob.U0)
+    assert (iso == dry).all()
+
+
+def test_lake_at_rest_1d_exact():
+    """1D lake at rest with an emerged bump, h = max(0.1 - z, 0): the
+    residual is exactly zero."""
+    prob = W.wetdry_1d(256)
+    U = np.zeros((2, 1, 256))
+    U[0, 0] = np.maximum(0.1 - prob.z[0], 0.0)
+    R, tot = oracle.residual(prob, U)
+    assert tot == 0.0
+
+
+@pytest.mark.parametrize("order", [W.REDBLACK, W.LEX])
+def test_lake_at_rest_preserved_by_newton(order):
+    """Five forced Newton steps (tol = 0) keep u = 0, h + z = 0.5 on wet
+    cells and h = 0 on dry cells, to roundoff."""
+    prob = W.lake_island(32, order=order, n_levels=3, max_newton=5)
+    U, st = oracle.newton_solve(prob, tol=0.0)
+    assert st["status"] == "NOT_CONVERGED" and st["newton_steps"] == 5
+    wet = prob.U0[0] > 0
+    assert np.abs(U[1:]).max() < 1e-13
+    assert np.abs((U[0] + prob.z)[wet] - 0.5).max() < 1e3 * np.finfo(float).eps
+    assert (U[:, ~wet] == 0).all()
+
+
+def global_fd_jacobian(prob, U, eps):
+    """Dense d(R)/d(U) by perturbing one global unknown at a time and
+    differencing the whole residual (brute force)."""
+    nc, ny, nx = U.shape
+    n = nc * nx * ny
+    J = np.zeros((n, n))
+    R0, _ = oracle.residual(prob, U)
+    r0 = R0.reshape(nc, -1).T.reshape(-1)
+    for c in range(nx * ny):
+        for k in range(nc):
+            Up = U.copy()
+            Up[k].reshape(-1)[c] += eps
+            R1, _ = oracle.residual(prob, Up)
+            J[:, c * nc + k] = (R1.reshape(nc, -1).T.reshape(-1) - r0) / eps
+    return J
+
+
+def central_jacobian(prob, U, h):
+    nc, ny, nx = U.shape
+    n = nc * nx * ny
+    J = np.zeros((n, n))
+    for c in range(nx * ny):
+        for k in range(nc):
+            Up, Um = U.copy(), U.copy()
+            Up[k].reshape(-1)[c] += h
+            Um[k].reshape(-1)[c] -= h
+            Rp, _ = oracle.residual(prob, Up)
+            Rm, _ = oracle.residual(prob, Um)
+            J[:, c * nc + k] = (Rp - Rm).reshape(nc, -1).T.reshape(-1) / (2 * h)
+    return J
+
+
+@pytest.mark.parametrize("dim,nx,ny,bc", [(1, 6, 1, CHAN), (2, 4, 4, WALLS), (2, 5, 3, CHAN),
+                                          (2, 3, 4, CHAN)])
+@pytest.mark.parametrize("flux", [W.HLL, W.LLF])
+def test_assembled_jacobian_matches_brute_force(dim, nx, ny, bc, flux):
+    """The assembled blocks (alpha = 0, so A = dR/dU) equal the brute-force
+    global forward difference with the same step, and approximate the
+    central difference with step 1e-5."""
+    from blockmat import dense
+    for seed in range(3):
+        prob, U = tiny(dim, nx, ny, 10 + seed, bc, flux, alpha=0.0)
+        A, b, tot = oracle.assemble(prob, U)
+        Jd = dense(A)
+        scale = np.abs(Jd).max(axis=1, keepdims=True)
+        Jfd = global_fd_jacobian(prob, U, prob.params["fd_eps"])
+        assert np.abs(Jd - Jfd).max() <= 1e-6 * scale.max()
+        assert (np.abs(Jd - Jfd) <= 2e-6 * scale + 1e-12).all()
+        Jc = central_jacobian(prob, U, 1e-5)
+        assert (np.abs(Jd - Jc) <= 2e-5 * scale + 1e-10).all()
+        R, _ = oracle.residual(prob, U)
+        np.testing.assert_array_equal(b, -R)
+
+
+def test_regularization_on_the_diagonal():
+    """A_ii = alpha ||R_i||_1 I + dR_i/dU_i (eq:NewtonREG)."""
+    prob, U = tiny(2, 5, 4, 3, CHAN, W.LLF)
+    A3, _, _ = oracle.assemble(prob, U)
+    A0, _, _ = oracle.assemble(prob, U, dict(prob.params, alpha=0.0))
+    R, _ = oracle.residual(prob, U)
+    nrm = np.abs(R).sum(axis=0)
+    for r in range(3):
+        np.testing.assert_allclose(A3[0, r, r] - A0[0, r, r], 3.0 * nrm, rtol=1e-12, atol=1e-16)
+    off = np.ones((3, 3), bool)
+    np.fill_diagonal(off, False)
+    np.testing.assert_array_equal(A3[0][off], A0[0][off])
+    np.testing.assert_array_equal(A3[1:], A0[1:])
+
+
+def puddle_problem():
+    """A 5x5 walled basin: the centre cell is a puddle sunk below a dry rim,
+    the corner cell is a dry peak, the rest is a lake."""
+    z = np.full((5, 5), 0.0)
+    z[1:4, 1:4] = 1.0
+    z[2, 2] = 0.5
+    z[0, 0] = 2.0
+    U = np.zeros((3, 5, 5))
+    U[0] = np.maximum(0.0, 0.6 - z)
+    U[0, 2, 2] = 0.3          # puddle surface 0.8, below the rim at 1.0
+    U[1, 2, 2] = 0.05
+    prob = W.Problem("puddle", 2, 5, 5, 0, 1, 0, 1, WALLS, W.default_params(2), z, U)
+    return prob, U
+
+
+def test_isolation_pin():
+    """Isolated cells (no face with water on either side) get a zero
+    diagonal block, zero row, zero right-hand side and a zero column in the
+    rows of their neighbours."""
+    prob, U = puddle_problem()
+    iso = oracle.isolated(prob, U)
+    assert iso[2, 2] and iso[0, 0] and iso[1, 1] and not iso[0, 2]
+    A, b, _ = oracle.assemble(prob, U)
+    for (j, i) in zip(*np.nonzero(iso)):
+        assert (A[:, :, :, j, i] == 0).all() and (b[:, j, i] == 0).all()
+        for blk, (di, dj) in ((1, (1, 0)), (2, (-1, 0)), (3, (0, 1)), (4, (0, -1))):
+            jj, ii = j + dj, i + di
+            if 0 <= ii < 5 and 0 <= jj < 5:
+                assert (A[blk, :, :, jj, ii] == 0).all()
+
+
+def test_dry_momentum_pin():
+    """An exactly dry cell next to higher water gets water from the mass
+    row, and its momentum unknowns are held at zero: momentum rows equal
+    the mass diagonal entry times the identity and their right-hand side
+    is zero."""
+    z = np.zeros((1, 6))
+    z[0, 3:] = 0.3
+    U = np.zeros((2, 1, 6))
+    U[0, 0, :3] = 0.5          # surface 0.5 above the dry step at 0.3
+    prob = W.Problem("step", 1, 6, 1, 0, 6, 0, 1, WALLS, W.default_params(1, flux=W.LLF), z, U)
+    A, b, _ = oracle.assemble(prob, U)
+    assert b[0, 0, 3] > 0                       # water flows into cell 3
+    assert A[0, 1, 1, 0, 3] == A[0, 0, 0, 0, 3] > 0
+    assert A[0, 1, 0, 0, 3] == 0 and b[1, 0, 3] == 0 and (A[1:, 1, :, 0, 3] == 0).all()
+    A2, b2, _ = oracle.assemble(prob, U, dict(prob.params, dry_pin=0))
+    assert A2[0, 1, 1, 0, 3] != A2[0, 0, 0, 0, 3]

@@ -1,0 +1,119 @@
+"""Pins of the oracle's linear multigrid pieces (paper Sec. 2.3) against
+dense linear algebra: Galerkin coarse blocks = P^T A P, restriction =
+P^T (b - A x), prolongation = x + P x_c, block SGS = the (D+L)^-1 / (D+U)^-1
+formulas in lexicographic and red-black orders, V-cycles converge to the
+dense solution."""
+import numpy as np
+import pytest
+
+import oracle
+from blockmat import block_split, dense, prolongation, unvec, vec
+from paper_1608_06721_amd import workloads as W
+
+SHAPES = [(1, 8, 1), (2, 4, 4), (2, 8, 8), (2, 16, 8), (2, 6, 10)]
+
+
+@pytest.mark.parametrize("dim,nx,ny", SHAPES)
+def test_galerkin_is_ptap(dim, nx, ny):
+    A, b = W.random_system(dim, nx, ny, seed=nx * 31 + ny)
+    Ac = oracle.galerkin(A)
+    nc = A.shape[1]
+    P = prolongation(nc, ny, nx, dim)
+    ref = P.T @ dense(A) @ P
+    np.testing.assert_allclose(dense(Ac), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("dim,nx,ny", SHAPES)
+def test_restrict_and_prolong(dim, nx, ny):
+    A, b = W.random_system(dim, nx, ny, seed=7)
+    r = np.random.Generator(np.random.PCG64(8))
+    nc = A.shape[1]
+    x = r.uniform(-1, 1, b.shape)
+    P = prolongation(nc, ny, nx, dim)
+    bc = oracle.restrict(A, b, x)
+    ref = P.T @ (vec(b) - dense(A) @ vec(x))
+    np.testing.assert_allclose(vec(bc), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    xc = r.uniform(-1, 1, bc.shape)
+    np.testing.assert_allclose(vec(oracle.prolong(xc, x)), vec(x) + P @ vec(xc), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(vec(oracle.lin_residual(A, b, x)), vec(b) - dense(A) @ vec(x),
+                               rtol=0, atol=1e-13)
+
+
+def sgs_dense(M, bv, x, nc, order):
+    D, L, U = block_split(M, nc, order)
+    x = np.linalg.solve(D + L, bv - U @ x)
+    return np.linalg.solve(D + U, bv - L @ x)
+
+
+def rb_order(nx, ny):
+    cells = [(j * nx + i) for j in range(ny) for i in range(nx)]
+    red = [c for c in cells if ((c % nx) + (c // nx)) % 2 == 0]
+    black = [c for c in cells if ((c % nx) + (c // nx)) % 2 == 1]
+    return red + black
+
+
+@pytest.mark.parametrize("dim,nx,ny", SHAPES)
+def test_sgs_matches_dense_formulas(dim, nx, ny):
+    A, b = W.random_system(dim, nx, ny, seed=3)
+    nc = A.shape[1]
+    M = dense(A)
+    r = np.random.Generator(np.random.PCG64(4))
+    x0 = r.uniform(-1, 1, b.shape)
+    lex = list(range(nx * ny))
+    got = oracle.sgs(A, b, x0, 1, order=W.LEX)
+    np.testing.assert_allclose(vec(got), sgs_dense(M, vec(b), vec(x0), nc, lex), rtol=0, atol=1e-12)
+    got = oracle.sgs(A, b, x0, 1, order=W.REDBLACK)
+    np.testing.assert_allclose(vec(got), sgs_dense(M, vec(b), vec(x0), nc, rb_order(nx, ny)),
+                               rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim,nx,ny", SHAPES)
+def test_redblack_halfsweeps(dim, nx, ny):
+    """A red-black SGS iteration is the half sweeps red, black, black, red;
+    a repeated half sweep of one color changes nothing (it reads only the
+    other color), so red, black, red gives the same bits."""
+    A, b = W.random_system(dim, nx, ny, seed=5)
+    r = np.random.Generator(np.random.PCG64(6))
+    x0 = r.uniform(-1, 1, b.shape)
+    x = oracle.sgs_half(A, b, x0, 0)
+    x = oracle.sgs_half(A, b, x, 1)
+    xb = oracle.sgs_half(A, b, x, 1)
+    np.testing.assert_array_equal(xb, x)
+    x = oracle.sgs_half(A, b, x, 0)
+    np.testing.assert_array_equal(x, oracle.sgs(A, b, x0, 1, order=W.REDBLACK))
+
+
+def test_two_grid_cycle_matches_dense_operator():
+    """One level below the finest with many coarse sweeps: the cycle equals
+    S2 (x + P Ac^-1 P^T (b - A x)) with x = S1(x0), Ac = P^T A P."""
+    dim, nx, ny = 2, 8, 8
+    A, b = W.random_system(dim, nx, ny, seed=9)
+    nc = A.shape[1]
+    M = dense(A)
+    P = prolongation(nc, ny, nx, dim)
+    p = W.default_params(2, n_levels=1, nu1=1, nu2=1, nu_coarse=200, order=W.LEX)
+    r = np.random.Generator(np.random.PCG64(10))
+    x0 = r.uniform(-1, 1, b.shape)
+    got = oracle.vcycles(A, b, x0, p, 1)
+    lex = list(range(nx * ny))
+    x = sgs_dense(M, vec(b), vec(x0), nc, lex)
+    Ac = P.T @ M @ P
+    x = x + P @ np.linalg.solve(Ac, P.T @ (vec(b) - M @ x))
+    x = sgs_dense(M, vec(b), x, nc, lex)
+    np.testing.assert_allclose(vec(got), x, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("order", [W.LEX, W.REDBLACK])
+@pytest.mark.parametrize("dim,nx,ny,nl", [(1, 32, 1, 3), (2, 16, 16, 3), (2, 32, 16, 2)])
+def test_vcycles_converge(order, dim, nx, ny, nl):
+    A, b = W.random_system(dim, nx, ny, seed=11)
+    M = dense(A)
+    xs = np.linalg.solve(M, vec(b))
+    p = W.default_params(dim, n_levels=nl, order=order)
+    x = np.zeros_like(b)
+    errs = []
+    for _ in range(6):
+        x = oracle.vcycles(A, b, x, p, 1)
+        errs.append(np.abs(vec(x) - xs).max())
+    assert errs[-1] < 1e-10 * np.abs(xs).max()
+    assert all(e2 < 0.2 * e1 or e2 < 1e-12 for e1, e2 in zip(errs, errs[1:]))

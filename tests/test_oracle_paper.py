@@ -1,0 +1,145 @@
+"""Pins of the oracle against numbers and closed forms the paper prints:
+block-SGS spectral radii (Tables 3.1 and 3.4), the Bernoulli solution of
+Example 3.1, the wet/dry lake at rest of Example 3.3, and convergence of the
+Newton multigrid loop (Algorithm 1) on the 1D bump and the 2D dry hill."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from blockmat import block_split, dense
+from paper_1608_06721_amd import workloads as W
+
+
+def read_golden(golden_dir, name):
+    rows = []
+    with open(os.path.join(golden_dir, name)) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def sgs_rho(prob, U):
+    """Spectral radius of the lexicographic block SGS iteration matrix
+    (D+U)^-1 L (D+L)^-1 U of the Jacobian (alpha = 0, i.e. at a steady
+    state), over the cells that carry unknowns (pinned cells dropped)."""
+    A, _, _ = oracle.assemble(prob, U, dict(prob.params, alpha=0.0))
+    M = dense(A)
+    nc = A.shape[1]
+    n = M.shape[0] // nc
+    keep = [c for c in range(n) if np.abs(M[c * nc:(c + 1) * nc, c * nc:(c + 1) * nc]).sum() > 0]
+    idx = np.array([c * nc + k for c in keep for k in range(nc)])
+    Mr = M[np.ix_(idx, idx)]
+    D, L, Up = block_split(Mr, nc, list(range(len(keep))))
+    S = np.linalg.solve(D + Up, L) @ np.linalg.solve(D + L, Up)
+    return np.abs(np.linalg.eigvals(S)).max()
+
+
+def test_ex33_rho_matches_table(golden_dir):
+    """Example 3.3 at its exact steady state: all printed digits agree."""
+    for N, ref in read_golden(golden_dir, "ex33_block_sgs_rho.txt"):
+        N, ref = int(N), float(ref)
+        prob = W.wetdry_1d(N)
+        U = np.zeros((2, 1, N))
+        U[0, 0] = np.maximum(0.1 - prob.z[0], 0.0)
+        assert round(sgs_rho(prob, U), 5) == ref
+
+
+@pytest.mark.slow
+def test_ex31_rho_matches_table(golden_dir):
+    """Example 3.1 at the converged steady state (HLL and LLF): within 0.5 %
+    of Table 3.1 (the paper's steady-state tolerance is not stated)."""
+    for N, flux, ref in read_golden(golden_dir, "ex31_block_sgs_rho.txt"):
+        N, ref = int(N), float(ref)
+        if N > 256:
+            continue
+        prob = W.smooth_1d(N, flux=W.HLL if flux == "HLL" else W.LLF, order=W.LEX,
+                           n_levels=int(math.log2(N)) - 2)
+        U, st = oracle.newton_solve(prob, tol=1e-12)
+        assert st["status"] == "OK"
+        assert abs(sgs_rho(prob, U) - ref) <= 5e-3 * ref
+
+
+def bernoulli_depth(z, q=1.0, g=9.81, h_ref=1.0):
+    """Subcritical depth with discharge q and energy q^2/(2 g h_ref^2) + h_ref
+    (the closed form of Example 3.1: u^3 + (2gz - 2g - 1)u + 2g = 0 for
+    q = h_ref = 1)."""
+    E = q * q / (2 * g * h_ref ** 2) + h_ref
+    out = np.empty_like(z)
+    for k, zk in enumerate(z):
+        h = h_ref
+        for _ in range(60):
+            f = q * q / (2 * g * h * h) + h + zk - E
+            h -= f / (1 - q * q / (g * h ** 3))
+        out[k] = h
+    return out
+
+
+def test_ex31_bernoulli_first_order():
+    """The converged depth of Example 3.1 approaches the Bernoulli solution
+    at first order."""
+    errs = []
+    for N in (128, 256, 512):
+        prob = W.smooth_1d(N, order=W.LEX, n_levels=int(math.log2(N)) - 2)
+        U, st = oracle.newton_solve(prob, tol=1e-11)
+        assert st["status"] == "OK"
+        x = W.cell_centres(-10, 10, N)
+        z = 0.2 * np.exp(-((x + 1) ** 2) / 2) + 0.3 * np.exp(-((x - 1.5) ** 2))
+        # Bernoulli residual of the cubic u^3 + (2gz - 2g - 1)u + 2g = 0 at hu = 1
+        h = bernoulli_depth(z)
+        u = 1.0 / h
+        assert np.abs(u ** 3 + (2 * 9.81 * z - 2 * 9.81 - 1) * u + 2 * 9.81).max() < 1e-9
+        errs.append(np.abs(U[0, 0] - h).max())
+    assert errs[0] < 2e-2
+    assert 1.6 < errs[0] / errs[1] < 2.6 and 1.6 < errs[1] / errs[2] < 2.6
+
+
+def invariants(U, h_eps=1e-6):
+    h = U[0]
+    assert (h >= 0).all()
+    assert (U[1:, h == 0] == 0).all()
+    assert (h[h > 0] >= h_eps).all()
+
+
+def test_bump_1d_converges():
+    """Config of the 1D subcritical bump (HLL, N_L = 3, V(2,2), N_mg = 2)."""
+    prob = W.bump_1d(200)
+    U, st = oracle.newton_solve(prob, tol=1e-10)
+    assert st["status"] == "OK" and st["newton_steps"] <= 30
+    assert st["res_l1"] < 1e-10
+    _, tot = oracle.residual(prob, U)
+    assert tot < 1e-10
+    invariants(U)
+    # steady discharge: interior mass fluxes all equal q up to the tolerance
+    assert np.abs(U[1, 0] - 4.42).max() < 0.05
+
+
+@pytest.mark.parametrize("order,levels", [(W.LEX, 3), (W.REDBLACK, 5)])
+def test_ex33_wetdry_lake_recovered(order, levels):
+    """Example 3.3: from h = 0.22 - z the solver drains to the lake at rest
+    h = max(0.1 - z, 0), u = 0, with the dry crest, to roundoff."""
+    prob = W.wetdry_1d(128, order=order, n_levels=levels)
+    U, st = oracle.newton_solve(prob, tol=1e-10)
+    assert st["status"] == "OK"
+    ex = np.maximum(0.1 - prob.z[0], 0.0)
+    assert np.abs(U[0, 0] - ex).max() < 1e-9
+    assert np.abs(U[1]).max() < 1e-9
+    invariants(U)
+    assert ((U[0, 0] == 0) == (ex == 0)).all()
+
+
+@pytest.mark.slow
+def test_dry_hill_2d_converges():
+    """Example 3.7 set-up (LLF, dry hill top), 128 x 64, deep hierarchy."""
+    prob = W.dry_hill(128, 64, n_levels=5)
+    U, st = oracle.newton_solve(prob, tol=1e-10)
+    assert st["status"] == "OK", st
+    invariants(U)
+    assert (U[0] == 0).sum() > 100
+    # the hill top above every wet surface stays dry
+    assert (U[0][prob.z > 0.25] == 0).all()
+    assert ((U[0] + prob.z)[U[0] > 0] < 0.25).all()
