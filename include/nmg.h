@@ -1,0 +1,183 @@
+/*
+ * nmg.h -- C ABI of the MI355X (gfx950) Newton multigrid library for steady
+ * shallow water equations with topography and wet/dry areas, after
+ * K. Wu and H. Tang, "A Newton multigrid method for steady-state shallow
+ * water equations with topography and dry areas" (arXiv:1608.06721).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Arrays.  Every array argument is a DEVICE pointer to caller-owned FP64
+ * memory (for example a torch.cuda tensor) unless its name ends in _host.
+ * Cell vectors use the layout v[c][ny][nx] (x fastest, component-major),
+ * c < NC with NC = 2 in 1D (h, hu) and NC = 3 in 2D (h, hu, hv); the bed is
+ * z[ny][nx].  Block matrices use A[b][r][c][ny][nx]: block b in the order
+ * D, W, E, S, N (1D: D, W, E) couples cell (i, j) to itself or to its west,
+ * east, south or north neighbour; A[b][r][c] at cell (i, j) is the
+ * derivative of row r of cell (i, j)'s equation with respect to component c
+ * of that neighbour's unknown.  Blocks that point out of the grid are zero.
+ *
+ * Ownership.  The library never frees caller memory.  It owns only the
+ * workspace inside the opaque context (the multigrid hierarchy in a
+ * colour-split layout, about 1.33 x 2 x (45 + 6) x 8 bytes per 2D cell).
+ *
+ * Streams.  All work is enqueued on the HIP stream given to nmg_create and
+ * is stream-ordered with the caller's work on that stream.  Entry points
+ * that return values to host memory (res_l1_host, stats) synchronize that
+ * stream.  A context must not be used from two threads at once.
+ *
+ * Errors.  Every function returns NMG_OK (0) or a status below; no
+ * exception crosses the ABI.  nmg_last_error gives a message for the last
+ * failure on a context.  On NMG_EHIP the context should be destroyed.
+ *
+ * Floating point.  All arithmetic is IEEE FP64 without contraction; each
+ * expression is evaluated in a fixed documented order, so results are
+ * deterministic run to run and for any launch shape.
+ */
+#ifndef NMG_H
+#define NMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmg_ctx nmg_ctx;
+
+enum {
+    NMG_OK = 0,
+    NMG_NOT_CONVERGED = 1,   /* max_newton reached; U holds the last iterate */
+    NMG_EINVAL = -1,         /* bad argument (grid, BC, params, level, null pointer) */
+    NMG_ENOMEM = -2,         /* device allocation failed */
+    NMG_EHIP = -3,           /* a HIP runtime call failed */
+    NMG_ENONFINITE = -4,     /* a residual became NaN/Inf; U holds the last finite iterate */
+    NMG_EDIVERGED = -5       /* sum ||R_i||_1 grew beyond 1e8 x its first value */
+};
+
+enum { NMG_FLUX_HLL = 0, NMG_FLUX_LLF = 1 };
+enum { NMG_BC_REFLECT = 0, NMG_BC_SLIP = 1, NMG_BC_OPEN = 2 };
+
+/* Uniform Cartesian grid (paper Sec. 2, partition of the domain).  dim is 1
+ * or 2; in 1D ny must be 1 and every face length |e| is 1; in 2D the faces
+ * normal to x have length (y1-y0)/ny and those normal to y (x1-x0)/nx.
+ * nx (and ny in 2D) must be divisible by 2^n_levels. */
+typedef struct {
+    int dim, nx, ny;
+    double x0, x1, y0, y1;
+} nmg_grid;
+
+/* Boundary condition of one side (Remark on boundary conditions, Sec. 2.1).
+ * kind REFLECT: ghost depth = interior depth, normal velocity reversed.
+ * kind SLIP: normal velocity zero.  kind OPEN: the regime follows the
+ * interior cell's local Froude number; qn is the discharge per unit width
+ * flowing INTO the domain (> 0), h the ghost depth (> 0), ut the tangential
+ * velocity (the physical v on the W/E sides, u on S/N).  NaN = not
+ * prescribed; an OPEN side needs qn or h. */
+typedef struct {
+    int kind;
+    double h, qn, ut;
+} nmg_side;
+
+typedef struct {
+    nmg_side side[4];        /* W, E, S, N (1D uses W and E) */
+} nmg_bc;
+
+/* Method parameters.  Paper values: g = 9.81, alpha = 3 (eq:NewtonREG),
+ * fd_eps = 1e-8 (eq:NumerDiff), tau = 1 (eq:NewtonREG-12), h_eps = 1e-6
+ * (dry-cell remark), eps_r = 0.03 (LLF wave speed at wet/dry fronts),
+ * N_L = n_levels = 3, n_mg = 2 (1D) / 3 (2D) cycles per Newton step, one
+ * BLU-SGS pre-smoothing sweep per step (Algorithm 1, Step 2.1).  nu1/nu2
+ * are the pre/post block-SGS iterations of Algorithm 0; nu_coarse the SGS
+ * iterations that stand for the coarsest-level solve.  dry_pin (0/1) holds
+ * the momentum of exactly dry cells at zero in the step that wets them;
+ * pos_theta (>= 0, < 1) limits the per-cell relaxation so that no step
+ * removes more than that fraction of a cell's depth (0 = tau everywhere). */
+typedef struct {
+    int flux;
+    double g, alpha, fd_eps, tau, h_eps, eps_r;
+    int n_levels, nu1, nu2, nu_coarse, n_mg;
+    int blu_sweeps, max_newton;
+    int dry_pin;
+    double pos_theta;
+} nmg_params;
+
+/* Solve statistics (host memory).  res_hist (optional, host) receives the
+ * sum of ||R_i||_1 at each Newton step, up to hist_cap entries. */
+typedef struct {
+    int newton_steps;        /* number of multigrid updates performed */
+    int status;
+    int n_pinned;            /* isolated cells at the returned state */
+    double res_l1;           /* sum_i ||R_i||_1 of the returned state */
+    double *res_hist;
+    int hist_cap;
+} nmg_stats;
+
+/* Create a context for one grid / BC / parameter set on HIP stream `stream`
+ * (hipStream_t, may be NULL for the null stream).  Allocates the
+ * hierarchy.  Errors: EINVAL (inconsistent grid, BC or params), ENOMEM,
+ * EHIP. */
+int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
+               void *stream, nmg_ctx **out);
+void nmg_destroy(nmg_ctx *ctx);
+const char *nmg_last_error(const nmg_ctx *ctx);
+
+/* Local residuals R_i (eq:Res: sum over the cell's faces of |e| times the
+ * edge term of eq:totalFlux) of state U over bed z.  R_out (device, nullable)
+ * receives R in the cell-vector layout; res_l1_host (host, nullable) the sum
+ * over cells of ||R_i||_1 (synchronizes the stream). */
+int nmg_residual(nmg_ctx *ctx, const double *z, const double *U, double *R_out,
+                 double *res_l1_host);
+
+/* Assembly of the level-0 Newton system eq:MatrixForm at state U: right-hand
+ * side -R and blocks A_ii = alpha ||R_i||_1 I + sum_e |e| dF/dU_i,
+ * A_ij = |e| dF/dU_j by forward differences (eq:NumerDiff, ghosts
+ * re-evaluated on boundary faces), with isolated cells pinned, then the
+ * Galerkin coarse levels (eq:ProjectAR, left).  The system stays in the
+ * context for nmg_mg_vcycle.  R_out / res_l1_host as in nmg_residual. */
+int nmg_assemble_residual_jacobian(nmg_ctx *ctx, const double *z, const double *U,
+                                   double *R_out, double *res_l1_host);
+
+/* n_cycles multigrid V-cycles (Algorithm 0, gamma = 1, red-black block SGS
+ * smoother) on the system last assembled or loaded, starting from and
+ * returning dU (device, cell-vector layout, in/out). */
+int nmg_mg_vcycle(nmg_ctx *ctx, double *dU, int n_cycles);
+
+/* `iters` red-black block SGS iterations (red, black, black, red half
+ * sweeps) on level `level` of the current hierarchy with that level's
+ * right-hand side; dU in/out in the cell-vector layout of that level. */
+int nmg_sgs(nmg_ctx *ctx, int level, double *dU, int iters);
+
+/* One symmetric BLU-SGS sweep (Algorithm 1, Step 2.1; red, black, black,
+ * red) on U in place, with the dry threshold after every cell update. */
+int nmg_blu_sweep(nmg_ctx *ctx, const double *z, double *U);
+
+/* Newton multigrid solve (Algorithm 1, Steps 2-3) from U (in: U0, out: the
+ * returned iterate).  Each step: BLU-SGS sweeps, assembly, stop test
+ * sum ||R_i||_1 < tol (the returned U is then the tested state), n_mg
+ * V-cycles from dU = 0, relaxed update and dry threshold.  Returns OK,
+ * NOT_CONVERGED, ENONFINITE, EDIVERGED or an error.  stats (host) nullable. */
+int nmg_newton_mg_solve(nmg_ctx *ctx, const double *z, double *U, double tol,
+                        nmg_stats *stats);
+
+/* Load a level-0 system (A in the block layout, b) into the context and
+ * build the Galerkin coarse levels from it.  For testing the linear
+ * multigrid on its own. */
+int nmg_load_system(nmg_ctx *ctx, const double *A0, const double *b0);
+
+/* Copy level `level`'s blocks (nullable) and right-hand side (nullable) out
+ * in the block / cell-vector layouts of that level (nx >> level,
+ * ny >> level in 2D).  Coarse right-hand sides are those of the last cycle. */
+int nmg_get_system(nmg_ctx *ctx, int level, double *A, double *b);
+
+/* Measurement hooks.  With enable = 1 the library records a pair of
+ * hipEvents on its stream around each finest-level block SGS half sweep,
+ * for at most `cap` launches (older records are dropped when re-enabled);
+ * enable = 0 stops recording.  nmg_timing_read synchronizes the stream and
+ * returns, over the recorded launches, the summed kernel milliseconds, the
+ * number of launches and the number of cell updates they performed. */
+int nmg_timing_enable(nmg_ctx *ctx, int enable, int cap);
+int nmg_timing_read(nmg_ctx *ctx, double *sgs_ms_host, int *sgs_launches_host,
+                    long long *sgs_cells_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMG_H */

@@ -1,0 +1,524 @@
+// Host driver of the MI355X Newton multigrid library: the C ABI of
+// include/nmg.h, the multigrid hierarchy, Algorithm 0 (V-cycle) and
+// Algorithm 1 Steps 2-3 (Newton loop) of Wu & Tang (arXiv:1608.06721).
+#include "nmg.h"
+#include "nmg_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+using namespace nmg;
+
+namespace {
+
+// State of one colour of a level's correction vector x.
+enum ColorState {
+    ST_VALID = 0,       // stored values are the current ones
+    ST_ZERO = 1,        // current value is 0 (not materialized)
+    ST_VALID_PP = 2,    // stored values + pending prolongation of the coarse correction
+    ST_ZERO_PP = 3      // 0 + pending prolongation
+};
+
+struct Level {
+    LevelGeom G;
+    double *A = nullptr, *b = nullptr, *x = nullptr;
+    int st[2] = {ST_ZERO, ST_ZERO};
+    int last = -1;      // colour of the last half sweep if nothing changed since, else -1
+};
+
+}  // namespace
+
+struct nmg_ctx {
+    nmg_grid grid;
+    nmg_bc bc;
+    nmg_params prm;
+    hipStream_t stream = nullptr;
+    Phys P;
+    int dim = 0, nc = 0, nb = 0, ne = 0, NL = 0;
+    Level L[16];
+    unsigned char *iso = nullptr;
+    double *partial = nullptr;    // per-block partial sums
+    double *scal = nullptr;       // device scalars
+    double *h_scal = nullptr;     // pinned host mirror
+    double *Ulast = nullptr;      // U before the current Newton step
+    std::string err;
+    // measurement hooks
+    bool timing = false;
+    int tcap = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<long long> ev_cells;
+};
+
+namespace {
+
+int fail(nmg_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, NMG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+long cells(const LevelGeom &G) { return (long)G.nx * G.ny; }
+
+int check_params(const nmg_grid *g, const nmg_bc *bc, const nmg_params *p, std::string &msg)
+{
+    if (!g || !bc || !p) { msg = "null grid/bc/params"; return NMG_EINVAL; }
+    if (g->dim != 1 && g->dim != 2) { msg = "dim must be 1 or 2"; return NMG_EINVAL; }
+    if (g->nx < 2 || g->ny < 1 || (g->dim == 1 && g->ny != 1) || (g->dim == 2 && g->ny < 2)) {
+        msg = "bad grid size";
+        return NMG_EINVAL;
+    }
+    if (!(g->x1 > g->x0) || (g->dim == 2 && !(g->y1 > g->y0))) { msg = "empty domain"; return NMG_EINVAL; }
+    if (p->n_levels < 0 || p->n_levels > 15) { msg = "n_levels out of range"; return NMG_EINVAL; }
+    long div = 1L << p->n_levels;
+    if (g->nx % div || (g->dim == 2 && g->ny % div)) {
+        msg = "nx (and ny) must be divisible by 2^n_levels";
+        return NMG_EINVAL;
+    }
+    if (p->flux != NMG_FLUX_HLL && p->flux != NMG_FLUX_LLF) { msg = "unknown flux"; return NMG_EINVAL; }
+    if (!(p->g > 0) || !(p->fd_eps > 0) || !(p->alpha >= 0) || !(p->h_eps >= 0) || !(p->tau > 0) ||
+        !(p->eps_r >= 0) || !(p->pos_theta >= 0 && p->pos_theta < 1)) {
+        msg = "bad scalar parameter";
+        return NMG_EINVAL;
+    }
+    if (p->nu1 < 0 || p->nu2 < 0 || p->nu_coarse < 0 || p->n_mg < 0 || p->blu_sweeps < 0 ||
+        p->max_newton < 0) {
+        msg = "negative iteration count";
+        return NMG_EINVAL;
+    }
+    int nsides = g->dim == 1 ? 2 : 4;
+    for (int f = 0; f < nsides; ++f) {
+        const nmg_side &s = bc->side[f];
+        if (s.kind < 0 || s.kind > 2) { msg = "bad boundary kind"; return NMG_EINVAL; }
+        if (s.kind == NMG_BC_OPEN) {
+            bool hq = !std::isnan(s.qn), hh = !std::isnan(s.h);
+            if (!hq && !hh) { msg = "open side needs qn or h"; return NMG_EINVAL; }
+            if (hq && !(s.qn > 0)) { msg = "inflow discharge qn must be > 0"; return NMG_EINVAL; }
+            if (hh && !(s.h > 0)) { msg = "prescribed depth h must be > 0"; return NMG_EINVAL; }
+        }
+    }
+    return NMG_OK;
+}
+
+// ---- multigrid on the colour-split hierarchy -----------------------------
+
+int halfsweep(nmg_ctx *c, int l, int color)
+{
+    Level &Lv = c->L[l];
+    if (Lv.last == color) return NMG_OK;   // same colour again: result identical, elide
+    int oc = color ^ 1;
+    int mode;
+    switch (Lv.st[oc]) {
+    case ST_VALID: mode = MODE_NORMAL; break;
+    case ST_ZERO: mode = MODE_ZERO; break;
+    case ST_VALID_PP: mode = MODE_PROLONG; break;
+    default: mode = MODE_PROLONG_ZERO; break;
+    }
+    const Level &Lc = c->L[l + 1 <= c->NL ? l + 1 : l];
+    bool rec = c->timing && l == 0 && (int)c->ev.size() < c->tcap;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rec) {
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    HIPCHK(c, launch_sgs_half(c->dim, mode, Lv.G, Lv.A, Lv.b, Lv.x, color, Lc.G, Lc.x, c->stream));
+    if (rec) {
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        c->ev.emplace_back(e0, e1);
+        int W = Lv.G.W;
+        long n = 0;
+        for (int j = 0; j < Lv.G.ny; ++j) {
+            int first = (j + color) & 1;
+            n += (Lv.G.nx - first + 1) / 2;
+        }
+        (void)W;
+        c->ev_cells.push_back(n);
+    }
+    Lv.st[color] = ST_VALID;
+    Lv.last = color;
+    return NMG_OK;
+}
+
+int smooth(nmg_ctx *c, int l, int iters)
+{
+    for (int it = 0; it < iters; ++it) {
+        int rc;
+        if ((rc = halfsweep(c, l, 0)) || (rc = halfsweep(c, l, 1)) || (rc = halfsweep(c, l, 1)) ||
+            (rc = halfsweep(c, l, 0)))
+            return rc;
+    }
+    return NMG_OK;
+}
+
+// Bring both colours of level l's x to stored, current values.
+int materialize(nmg_ctx *c, int l)
+{
+    Level &Lv = c->L[l];
+    const Level &Lc = c->L[l + 1 <= c->NL ? l + 1 : l];
+    for (int color = 0; color < 2; ++color) {
+        int op = -1;
+        if (Lv.st[color] == ST_ZERO) op = 0;
+        else if (Lv.st[color] == ST_VALID_PP) op = 1;
+        else if (Lv.st[color] == ST_ZERO_PP) op = 2;
+        if (op < 0) continue;
+        HIPCHK(c, launch_fix_color(c->dim, op, Lv.G, Lv.x, color, Lc.G, Lc.x, c->stream));
+        Lv.st[color] = ST_VALID;
+        Lv.last = -1;
+    }
+    return NMG_OK;
+}
+
+void set_zero(nmg_ctx *c, int l)
+{
+    c->L[l].st[0] = c->L[l].st[1] = ST_ZERO;
+    c->L[l].last = -1;
+}
+
+// Algorithm 0 with gamma = 1 (V-cycle) on level l.
+int cycle(nmg_ctx *c, int l)
+{
+    const nmg_params &p = c->prm;
+    int rc;
+    if ((rc = smooth(c, l, p.nu1))) return rc;
+    if (l == c->NL) {
+        if ((rc = smooth(c, l, p.nu_coarse))) return rc;
+    } else {
+        if ((rc = materialize(c, l))) return rc;
+        Level &Lv = c->L[l];
+        Level &Lc = c->L[l + 1];
+        HIPCHK(c, launch_restrict(c->dim, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b, c->stream));
+        set_zero(c, l + 1);
+        if ((rc = cycle(c, l + 1))) return rc;
+        if ((rc = materialize(c, l + 1))) return rc;
+        for (int color = 0; color < 2; ++color)
+            Lv.st[color] = (Lv.st[color] == ST_ZERO) ? ST_ZERO_PP : ST_VALID_PP;
+        Lv.last = -1;
+    }
+    return smooth(c, l, p.nu2);
+}
+
+int build_coarse(nmg_ctx *c)
+{
+    for (int l = 1; l <= c->NL; ++l)
+        HIPCHK(c, launch_galerkin(c->dim, c->L[l - 1].G, c->L[l - 1].A, c->L[l].G, c->L[l].A,
+                                  c->stream));
+    for (int l = 0; l <= c->NL; ++l) set_zero(c, l);
+    return NMG_OK;
+}
+
+int reduce_to_host(nmg_ctx *c, int nparts, double *out)
+{
+    HIPCHK(c, launch_reduce(c->partial, nparts, c->scal, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_scal, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *out = c->h_scal[0];
+    return NMG_OK;
+}
+
+int assemble(nmg_ctx *c, const double *z, const double *U, double *R_out, double *res)
+{
+    Level &L0 = c->L[0];
+    HIPCHK(c, launch_isolated(c->P, z, U, c->iso, c->stream));
+    HIPCHK(c, launch_assemble(c->P, L0.G, z, U, c->iso, L0.A, L0.b, R_out, c->partial, c->stream));
+    int rc = build_coarse(c);
+    if (rc) return rc;
+    if (res) return reduce_to_host(c, nblocks(cells(L0.G)), res);
+    return NMG_OK;
+}
+
+int count_pinned(nmg_ctx *c, const double *z, const double *U, int *n)
+{
+    long N = cells(c->L[0].G);
+    HIPCHK(c, launch_isolated(c->P, z, U, c->iso, c->stream));
+    HIPCHK(c, launch_count_u8(c->iso, N, c->partial, c->stream));
+    double v = 0;
+    int rc = reduce_to_host(c, nblocks(N), &v);
+    *n = (int)v;
+    return rc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params, void *stream,
+               nmg_ctx **out)
+{
+    if (!out) return NMG_EINVAL;
+    *out = nullptr;
+    std::string msg;
+    int rc = check_params(grid, bc, params, msg);
+    if (rc) return rc;
+    nmg_ctx *c = new (std::nothrow) nmg_ctx();
+    if (!c) return NMG_ENOMEM;
+    c->grid = *grid;
+    c->bc = *bc;
+    c->prm = *params;
+    c->stream = (hipStream_t)stream;
+    c->dim = grid->dim;
+    c->nc = grid->dim == 1 ? 2 : 3;
+    c->nb = grid->dim == 1 ? 3 : 5;
+    c->ne = c->nb * c->nc * c->nc;
+    c->NL = params->n_levels;
+
+    Phys &P = c->P;
+    P.dim = grid->dim;
+    P.nx = grid->nx;
+    P.ny = grid->ny;
+    P.flux = params->flux;
+    P.dry_pin = params->dry_pin;
+    P.g = params->g;
+    P.alpha = params->alpha;
+    P.eps = params->fd_eps;
+    P.h_eps = params->h_eps;
+    P.eps_r = params->eps_r;
+    P.tau = params->tau;
+    P.pos_theta = params->pos_theta;
+    if (grid->dim == 1) {
+        P.elen[0] = P.elen[1] = P.elen[2] = P.elen[3] = 1.0;
+    } else {
+        double dx = (grid->x1 - grid->x0) / grid->nx, dy = (grid->y1 - grid->y0) / grid->ny;
+        P.elen[0] = P.elen[1] = dy;
+        P.elen[2] = P.elen[3] = dx;
+    }
+    for (int f = 0; f < 4; ++f) {
+        const nmg_side &s = bc->side[f];
+        P.bc[f].kind = s.kind;
+        P.bc[f].h = s.h;
+        P.bc[f].qn = s.qn;
+        P.bc[f].ut = s.ut;
+        P.bc[f].hasq = !std::isnan(s.qn);
+        P.bc[f].hash = !std::isnan(s.h);
+        P.bc[f].hast = !std::isnan(s.ut);
+    }
+
+    size_t total = 0;
+    for (int l = 0; l <= c->NL; ++l) {
+        int nx = grid->nx >> l, ny = grid->dim == 1 ? 1 : grid->ny >> l;
+        c->L[l].G = make_geom(nx, ny);
+        total += (size_t)2 * (c->ne + 2 * c->nc) * c->L[l].G.plane;
+    }
+    double *pool = nullptr;
+    if (hipMalloc(&pool, total * sizeof(double)) != hipSuccess) {
+        delete c;
+        return NMG_ENOMEM;
+    }
+    size_t off = 0;
+    for (int l = 0; l <= c->NL; ++l) {
+        Level &Lv = c->L[l];
+        Lv.A = pool + off; off += (size_t)2 * c->ne * Lv.G.plane;
+        Lv.b = pool + off; off += (size_t)2 * c->nc * Lv.G.plane;
+        Lv.x = pool + off; off += (size_t)2 * c->nc * Lv.G.plane;
+    }
+    long N = cells(c->L[0].G);
+    int nparts = nblocks(N);
+    bool ok = hipMemsetAsync(pool, 0, total * sizeof(double), c->stream) == hipSuccess &&
+              hipMalloc(&c->iso, N) == hipSuccess &&
+              hipMalloc(&c->partial, sizeof(double) * (nparts + 1)) == hipSuccess &&
+              hipMalloc(&c->scal, sizeof(double) * 4) == hipSuccess &&
+              hipHostMalloc(&c->h_scal, sizeof(double) * 4, hipHostMallocDefault) == hipSuccess &&
+              hipMalloc(&c->Ulast, sizeof(double) * c->nc * N) == hipSuccess;
+    if (!ok) {
+        nmg_destroy(c);
+        return NMG_ENOMEM;
+    }
+    *out = c;
+    return NMG_OK;
+}
+
+void nmg_destroy(nmg_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &e : c->ev) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    if (c->L[0].A) (void)hipFree(c->L[0].A);
+    if (c->iso) (void)hipFree(c->iso);
+    if (c->partial) (void)hipFree(c->partial);
+    if (c->scal) (void)hipFree(c->scal);
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->Ulast) (void)hipFree(c->Ulast);
+    delete c;
+}
+
+const char *nmg_last_error(const nmg_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int nmg_residual(nmg_ctx *c, const double *z, const double *U, double *R_out, double *res_l1_host)
+{
+    if (!c) return NMG_EINVAL;
+    if (!z || !U) return fail(c, NMG_EINVAL, "null z or U");
+    HIPCHK(c, launch_residual(c->P, z, U, R_out, c->partial, c->stream));
+    if (res_l1_host) return reduce_to_host(c, nblocks(cells(c->L[0].G)), res_l1_host);
+    return NMG_OK;
+}
+
+int nmg_assemble_residual_jacobian(nmg_ctx *c, const double *z, const double *U, double *R_out,
+                                   double *res_l1_host)
+{
+    if (!c) return NMG_EINVAL;
+    if (!z || !U) return fail(c, NMG_EINVAL, "null z or U");
+    return assemble(c, z, U, R_out, res_l1_host);
+}
+
+int nmg_mg_vcycle(nmg_ctx *c, double *dU, int n_cycles)
+{
+    if (!c) return NMG_EINVAL;
+    if (!dU || n_cycles < 0) return fail(c, NMG_EINVAL, "null dU or negative cycle count");
+    Level &L0 = c->L[0];
+    HIPCHK(c, launch_vec_to_split(c->nc, L0.G, dU, L0.x, c->stream));
+    L0.st[0] = L0.st[1] = ST_VALID;
+    L0.last = -1;
+    for (int k = 0; k < n_cycles; ++k) {
+        int rc = cycle(c, 0);
+        if (rc) return rc;
+    }
+    int rc = materialize(c, 0);
+    if (rc) return rc;
+    HIPCHK(c, launch_vec_from_split(c->nc, L0.G, L0.x, dU, c->stream));
+    return NMG_OK;
+}
+
+int nmg_sgs(nmg_ctx *c, int level, double *dU, int iters)
+{
+    if (!c) return NMG_EINVAL;
+    if (!dU || iters < 0 || level < 0 || level > c->NL)
+        return fail(c, NMG_EINVAL, "bad level, dU or iteration count");
+    Level &Lv = c->L[level];
+    HIPCHK(c, launch_vec_to_split(c->nc, Lv.G, dU, Lv.x, c->stream));
+    Lv.st[0] = Lv.st[1] = ST_VALID;
+    Lv.last = -1;
+    int rc = smooth(c, level, iters);
+    if (rc) return rc;
+    HIPCHK(c, launch_vec_from_split(c->nc, Lv.G, Lv.x, dU, c->stream));
+    return NMG_OK;
+}
+
+int nmg_blu_sweep(nmg_ctx *c, const double *z, double *U)
+{
+    if (!c) return NMG_EINVAL;
+    if (!z || !U) return fail(c, NMG_EINVAL, "null z or U");
+    const int order[4] = {0, 1, 1, 0};
+    for (int k = 0; k < 4; ++k) HIPCHK(c, launch_blu_half(c->P, z, U, order[k], c->stream));
+    return NMG_OK;
+}
+
+int nmg_load_system(nmg_ctx *c, const double *A0, const double *b0)
+{
+    if (!c) return NMG_EINVAL;
+    if (!A0 || !b0) return fail(c, NMG_EINVAL, "null A0 or b0");
+    Level &L0 = c->L[0];
+    HIPCHK(c, launch_mat_to_split(c->ne, L0.G, A0, L0.A, c->stream));
+    HIPCHK(c, launch_vec_to_split(c->nc, L0.G, b0, L0.b, c->stream));
+    return build_coarse(c);
+}
+
+int nmg_get_system(nmg_ctx *c, int level, double *A, double *b)
+{
+    if (!c) return NMG_EINVAL;
+    if (level < 0 || level > c->NL) return fail(c, NMG_EINVAL, "level out of range");
+    Level &Lv = c->L[level];
+    if (A) HIPCHK(c, launch_mat_from_split(c->ne, Lv.G, Lv.A, A, c->stream));
+    if (b) HIPCHK(c, launch_vec_from_split(c->nc, Lv.G, Lv.b, b, c->stream));
+    return NMG_OK;
+}
+
+int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_stats *st)
+{
+    if (!c) return NMG_EINVAL;
+    if (!z || !U) return fail(c, NMG_EINVAL, "null z or U");
+    const nmg_params &p = c->prm;
+    Level &L0 = c->L[0];
+    const long N = cells(L0.G);
+    const size_t vbytes = sizeof(double) * c->nc * N;
+    int status = NMG_NOT_CONVERGED, n = 0, rc;
+    double res = 0.0, res0 = 0.0;
+    HIPCHK(c, launch_threshold(c->P, U, c->stream));
+    for (n = 0; n < p.max_newton; ++n) {
+        HIPCHK(c, hipMemcpyAsync(c->Ulast, U, vbytes, hipMemcpyDeviceToDevice, c->stream));
+        for (int s = 0; s < p.blu_sweeps; ++s)
+            if ((rc = nmg_blu_sweep(c, z, U))) return rc;
+        if ((rc = assemble(c, z, U, nullptr, &res))) return rc;
+        if (st && st->res_hist && n < st->hist_cap) st->res_hist[n] = res;
+        if (n == 0) res0 = res;
+        if (!std::isfinite(res)) {
+            HIPCHK(c, hipMemcpyAsync(U, c->Ulast, vbytes, hipMemcpyDeviceToDevice, c->stream));
+            status = NMG_ENONFINITE;
+            break;
+        }
+        if (res < tol) { status = NMG_OK; break; }
+        if (res > 1e8 * res0) { status = NMG_EDIVERGED; break; }
+        set_zero(c, 0);
+        for (int m = 0; m < p.n_mg; ++m)
+            if ((rc = cycle(c, 0))) return rc;
+        if ((rc = materialize(c, 0))) return rc;
+        HIPCHK(c, launch_update(c->P, L0.G, L0.x, U, c->stream));
+    }
+    if (status == NMG_NOT_CONVERGED) {
+        HIPCHK(c, launch_residual(c->P, z, U, nullptr, c->partial, c->stream));
+        if ((rc = reduce_to_host(c, nblocks(N), &res))) return rc;
+    }
+    if (st) {
+        int np = 0;
+        if ((rc = count_pinned(c, z, U, &np))) return rc;
+        st->n_pinned = np;
+        st->newton_steps = n;
+        st->status = status;
+        st->res_l1 = res;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return status;
+}
+
+int nmg_timing_enable(nmg_ctx *c, int enable, int cap)
+{
+    if (!c) return NMG_EINVAL;
+    if (enable) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (auto &e : c->ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        c->ev.clear();
+        c->ev_cells.clear();
+        c->tcap = cap > 0 ? cap : 0;
+    }
+    c->timing = enable != 0;
+    return NMG_OK;
+}
+
+int nmg_timing_read(nmg_ctx *c, double *ms_host, int *launches_host, long long *cells_host)
+{
+    if (!c) return NMG_EINVAL;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    long long cl = 0;
+    for (size_t k = 0; k < c->ev.size(); ++k) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[k].first, c->ev[k].second));
+        tot += ms;
+        cl += c->ev_cells[k];
+    }
+    if (ms_host) *ms_host = tot;
+    if (launches_host) *launches_host = (int)c->ev.size();
+    if (cells_host) *cells_host = cl;
+    return NMG_OK;
+}
+
+}  // extern "C"

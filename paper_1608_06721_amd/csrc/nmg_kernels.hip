@@ -1,0 +1,1033 @@
+// gfx950 kernels of the Newton multigrid method for steady shallow water
+// equations (Wu & Tang, arXiv:1608.06721).
+//
+// All arithmetic is FP64 and must be compiled with -ffp-contract=off: the
+// order of every floating-point expression below is fixed (it is part of the
+// method's definition in this library), so that results are deterministic
+// and independent of launch shapes.
+//
+// Discretization (Sec. 2.1): hydrostatic reconstruction, HLL or LLF face
+// flux evaluated once per face in the +x / +y orientation (exactly
+// conservative), edge term F - S(h_own) on the lower-coordinate side and
+// -F + S(h_own) on the other, ghost states from the Remark on boundary
+// conditions.  Linearization (Sec. 2.2): forward differences with an
+// absolute step, alpha ||R_i||_1 on the diagonal.  Multigrid (Sec. 2.3):
+// Galerkin sums of child blocks, restriction of the linear residual,
+// piecewise-constant prolongation, red-black block Gauss-Seidel.
+#include "nmg_internal.h"
+
+#include <hip/hip_runtime.h>
+
+namespace nmg {
+namespace {
+
+enum { FW = 0, FE = 1, FS = 2, FN = 3 };
+
+__device__ __forceinline__ double dmax(double a, double b) { return a > b ? a : b; }
+__device__ __forceinline__ double dmin(double a, double b) { return a < b ? a : b; }
+__device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ bool finite(double x) { return __builtin_isfinite(x); }
+
+// One side of a face: depth, velocity components, bed.
+struct Side {
+    double h, u, v, z;
+};
+
+template <int NC>
+struct Cell {
+    double q[NC];
+};
+
+// ---------------------------------------------------------------------------
+// Physical flux along axis 0 (x) or 1 (y): m = h u_n, p = 0.5 g h h,
+// (m, m u [+ p], m v [+ p]).
+template <int NC>
+__device__ __forceinline__ void phys_flux(int axis, double g, double h, double u, double v,
+                                          double *F)
+{
+    double un = (axis == 0) ? u : v;
+    double m = h * un;
+    double p = 0.5 * g * h * h;
+    F[0] = m;
+    F[1] = (axis == 0) ? m * u + p : m * u;
+    if (NC == 3) F[2] = (axis == 1) ? m * v + p : m * v;
+}
+
+// Face flux in the +axis orientation between reconstructed left and right
+// states (Remark on numerical fluxes: HLL with two-rarefaction star
+// estimates, or LLF with the eps_r-enlarged wave speed).
+template <int NC>
+__device__ __forceinline__ void num_flux(const Phys &P, int axis, double hL, double uL, double vL,
+                                         double hR, double uR, double vR, double *out)
+{
+    const double g = P.g;
+    double FL[3], FR[3], UL[3], UR[3];
+    phys_flux<NC>(axis, g, hL, uL, vL, FL);
+    phys_flux<NC>(axis, g, hR, uR, vR, FR);
+    UL[0] = hL; UL[1] = hL * uL; UL[2] = hL * vL;
+    UR[0] = hR; UR[1] = hR * uR; UR[2] = hR * vR;
+    double unL = (axis == 0) ? uL : vL;
+    double unR = (axis == 0) ? uR : vR;
+    double cL = dsqrt(g * hL), cR = dsqrt(g * hR);
+    if (P.flux == 1) {
+        double s = dmax(dabs(unL) + cL, dabs(unR) + cR) + P.eps_r * dsqrt(g * dmax(hL, hR));
+#pragma unroll
+        for (int k = 0; k < NC; ++k) out[k] = 0.5 * ((FL[k] + FR[k]) - s * (UR[k] - UL[k]));
+        return;
+    }
+    double us = ((unL + unR) * 0.5 + cL) - cR;
+    double a = (cL + cR) + (unL - unR) * 0.5;
+    double hs = (a * a) / (4.0 * g);
+    double cs = dsqrt(g * hs);
+    double sL = (hL == 0.0) ? unR - 2.0 * cR : dmin(unL - cL, us - cs);
+    double sR = (hR == 0.0) ? unL + 2.0 * cL : dmax(unR + cR, us + cs);
+    if (sL >= 0.0) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) out[k] = FL[k];
+    } else if (sR <= 0.0) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) out[k] = FR[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            out[k] = ((sR * FL[k] - sL * FR[k]) + (sL * sR) * (UR[k] - UL[k])) / (sR - sL);
+    }
+}
+
+// Positive root of 2c^3 - K c^2 - gq = 0 by monotone Newton from above.
+__device__ double inflow_celerity(double K, double gq)
+{
+    double c = dmax(K, 0.0) + dmax(1.0, gq);
+    for (int it = 0; it < 100; ++it) {
+        double f = (2.0 * c - K) * c * c - gq;
+        double fp = (6.0 * c - 2.0 * K) * c;
+        double cn = c - f / fp;
+        if (!(cn < c)) break;
+        c = cn;
+    }
+    return c;
+}
+
+// Ghost cell state behind side f for the interior side `in`.
+__device__ Side ghost(const Phys &P, int f, const Side &in)
+{
+    const SideDev &bc = P.bc[f];
+    const double g = P.g;
+    int axis = (f == FW || f == FE) ? 0 : 1;
+    double sgn = (f == FW || f == FS) ? -1.0 : 1.0;
+    double un_in = sgn * (axis == 0 ? in.u : in.v);
+    double ut_in = (axis == 0) ? in.v : in.u;
+    double hg, ung, utg;
+    if (bc.kind == 0) {
+        hg = in.h; ung = -un_in; utg = ut_in;
+    } else if (bc.kind == 1) {
+        hg = in.h; ung = 0.0; utg = ut_in;
+    } else {
+        bool super = (in.h > P.h_eps) && (in.u * in.u + in.v * in.v >= g * in.h);
+        bool outflow = un_in >= 0.0;
+        if (super && outflow) {
+            hg = in.h; ung = un_in; utg = ut_in;
+        } else if (super && bc.hasq && bc.hash && bc.hast) {
+            hg = bc.h; ung = -bc.qn / bc.h; utg = bc.ut;
+        } else if (bc.hasq && (!bc.hash || !outflow)) {
+            double K = un_in + 2.0 * dsqrt(g * in.h);
+            double c = inflow_celerity(K, g * bc.qn);
+            hg = c * c / g;
+            ung = -bc.qn / hg;
+            utg = bc.hast ? bc.ut : 0.0;
+        } else {
+            hg = bc.h;
+            ung = (un_in + 2.0 * dsqrt(g * in.h)) - 2.0 * dsqrt(g * hg);
+            utg = ut_in;
+        }
+    }
+    Side o;
+    o.h = hg;
+    o.z = in.z;
+    if (axis == 0) { o.u = sgn * ung; o.v = utg; }
+    else           { o.u = utg;       o.v = sgn * ung; }
+    return o;
+}
+
+__device__ __forceinline__ double vel(const Phys &P, double h, double m)
+{
+    return h > P.h_eps ? m / h : 0.0;
+}
+
+template <int NC>
+__device__ __forceinline__ Side cell_side(const Phys &P, const double *q, double z)
+{
+    Side s;
+    s.h = q[0];
+    s.u = vel(P, q[0], q[1]);
+    s.v = (NC == 3) ? vel(P, q[0], q[2]) : 0.0;
+    s.z = z;
+    return s;
+}
+
+// Edge term of eq:totalFlux for the cell on side `own` of face f.
+template <int NC>
+__device__ __forceinline__ void edge_term(const Phys &P, int f, const Side &own, const Side &oth,
+                                          double *T)
+{
+    int axis = (f == FW || f == FE) ? 0 : 1;
+    bool own_left = (f == FE || f == FN);
+    const Side &L = own_left ? own : oth;
+    const Side &R = own_left ? oth : own;
+    double zM = dmax(L.z, R.z);
+    double hL = dmax(0.0, L.h + L.z - zM);
+    double hR = dmax(0.0, R.h + R.z - zM);
+    double F[3];
+    num_flux<NC>(P, axis, hL, L.u, L.v, hR, R.u, R.v, F);
+    double ho = own_left ? hL : hR;
+    double po = 0.5 * P.g * ho * ho;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) T[k] = own_left ? F[k] : -F[k];
+    if (own_left) T[1 + axis] = F[1 + axis] - po;
+    else          T[1 + axis] = -F[1 + axis] + po;
+}
+
+__device__ __forceinline__ bool neighbour(const Phys &P, int i, int j, int f, int &ni, int &nj)
+{
+    ni = i;
+    nj = j;
+    if (f == FW) { ni = i - 1; return i > 0; }
+    if (f == FE) { ni = i + 1; return i + 1 < P.nx; }
+    if (f == FS) { nj = j - 1; return j > 0; }
+    nj = j + 1;
+    return j + 1 < P.ny;
+}
+
+template <int NC>
+__device__ __forceinline__ void load_state(const Phys &P, const double *U, long idx, double *q)
+{
+    const long N = (long)P.nx * P.ny;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) q[k] = U[k * N + idx];
+}
+
+// Solve the NC x NC block system D x = r: adjugate (cofactors along row 0)
+// times the reciprocal determinant; x = 0 when that reciprocal is not finite.
+template <int NC>
+__device__ __forceinline__ void solve_block(const double *D, const double *r, double *x)
+{
+    if (NC == 2) {
+        double det = D[0] * D[3] - D[1] * D[2];
+        double idet = 1.0 / det;
+        if (!finite(idet)) { x[0] = 0.0; x[1] = 0.0; return; }
+        x[0] = (D[3] * r[0] - D[1] * r[1]) * idet;
+        x[1] = (D[0] * r[1] - D[2] * r[0]) * idet;
+        return;
+    }
+    double d00 = D[0], d01 = D[1], d02 = D[2];
+    double d10 = D[3], d11 = D[4], d12 = D[5];
+    double d20 = D[6], d21 = D[7], d22 = D[8];
+    double C00 = d11 * d22 - d12 * d21, C01 = d12 * d20 - d10 * d22, C02 = d10 * d21 - d11 * d20;
+    double C10 = d02 * d21 - d01 * d22, C11 = d00 * d22 - d02 * d20, C12 = d01 * d20 - d00 * d21;
+    double C20 = d01 * d12 - d02 * d11, C21 = d02 * d10 - d00 * d12, C22 = d00 * d11 - d01 * d10;
+    double det = d00 * C00 + d01 * C01 + d02 * C02;
+    double idet = 1.0 / det;
+    if (!finite(idet)) { x[0] = 0.0; x[1] = 0.0; x[2] = 0.0; return; }
+    x[0] = (C00 * r[0] + C10 * r[1] + C20 * r[2]) * idet;
+    x[1] = (C01 * r[0] + C11 * r[1] + C21 * r[2]) * idet;
+    x[2] = (C02 * r[0] + C12 * r[1] + C22 * r[2]) * idet;
+}
+
+// Deterministic block reduction of one double per thread; thread 0 of the
+// block receives the sum.  Fixed pairing order, so the result depends only
+// on the block size, never on timing.
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double sh[kBlock];
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] = sh[t] + sh[t + s];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// Residual and forward-difference blocks of one cell.  D receives
+// sum_e |e| dT/dU_i, Off[f] receives |e| dT/dU_j for interior faces.
+template <int NC, bool WANT_OFF>
+__device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, const double *U, int i,
+                                              int j, double *Rc, double (*D)[NC],
+                                              double (*Off)[NC][NC])
+{
+    const int NF = (NC == 2) ? 2 : 4;
+    const long idx = (long)j * P.nx + i;
+    const double eps = P.eps;
+    double qi[NC];
+    load_state<NC>(P, U, idx, qi);
+    const double zi = z[idx];
+    Side own = cell_side<NC>(P, qi, zi);
+    Side ownp[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        double qp[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) qp[c] = qi[c];
+        qp[k] = qp[k] + eps;
+        ownp[k] = cell_side<NC>(P, qp, zi);
+    }
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        Rc[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
+    }
+    for (int f = 0; f < NF; ++f) {
+        const double e = P.elen[f];
+        int ni, nj;
+        bool inner = neighbour(P, i, j, f, ni, nj);
+        double T0[NC], Tk[NC];
+        if (inner) {
+            long nidx = (long)nj * P.nx + ni;
+            double qj[NC];
+            load_state<NC>(P, U, nidx, qj);
+            double zj = z[nidx];
+            Side oth = cell_side<NC>(P, qj, zj);
+            edge_term<NC>(P, f, own, oth, T0);
+#pragma unroll
+            for (int r = 0; r < NC; ++r) Rc[r] = Rc[r] + e * T0[r];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                edge_term<NC>(P, f, ownp[k], oth, Tk);
+#pragma unroll
+                for (int r = 0; r < NC; ++r) D[r][k] = D[r][k] + e * ((Tk[r] - T0[r]) / eps);
+            }
+            if (WANT_OFF) {
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    double qp[NC];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) qp[c] = qj[c];
+                    qp[k] = qp[k] + eps;
+                    Side othp = cell_side<NC>(P, qp, zj);
+                    edge_term<NC>(P, f, own, othp, Tk);
+#pragma unroll
+                    for (int r = 0; r < NC; ++r) Off[f][r][k] = e * ((Tk[r] - T0[r]) / eps);
+                }
+            }
+        } else {
+            Side gh = ghost(P, f, own);
+            edge_term<NC>(P, f, own, gh, T0);
+#pragma unroll
+            for (int r = 0; r < NC; ++r) Rc[r] = Rc[r] + e * T0[r];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                Side ghp = ghost(P, f, ownp[k]);
+                edge_term<NC>(P, f, ownp[k], ghp, Tk);
+#pragma unroll
+                for (int r = 0; r < NC; ++r) D[r][k] = D[r][k] + e * ((Tk[r] - T0[r]) / eps);
+            }
+            if (WANT_OFF) {
+#pragma unroll
+                for (int r = 0; r < NC; ++r)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) Off[f][r][c] = 0.0;
+            }
+        }
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ double l1norm(const double *Rc)
+{
+    double s = dabs(Rc[0]) + dabs(Rc[1]);
+    if (NC == 3) s = s + dabs(Rc[2]);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels on the natural (public) layout.
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_isolated(Phys P, const double *__restrict__ z,
+                                                     const double *__restrict__ U,
+                                                     unsigned char *__restrict__ iso)
+{
+    const int NF = (NC == 2) ? 2 : 4;
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (long)P.nx * P.ny) return;
+    int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
+    double qi[NC];
+    load_state<NC>(P, U, idx, qi);
+    Side own = cell_side<NC>(P, qi, z[idx]);
+    unsigned char res = 1;
+    for (int f = 0; f < NF; ++f) {
+        int ni, nj;
+        Side oth;
+        if (neighbour(P, i, j, f, ni, nj)) {
+            long nidx = (long)nj * P.nx + ni;
+            double qj[NC];
+            load_state<NC>(P, U, nidx, qj);
+            oth = cell_side<NC>(P, qj, z[nidx]);
+        } else {
+            oth = ghost(P, f, own);
+        }
+        double zM = dmax(own.z, oth.z);
+        double h1 = dmax(0.0, own.h + own.z - zM);
+        double h2 = dmax(0.0, oth.h + oth.z - zM);
+        if (h1 != 0.0 || h2 != 0.0) res = 0;
+    }
+    iso[idx] = res;
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
+                                                     const double *__restrict__ z,
+                                                     const double *__restrict__ U,
+                                                     const unsigned char *__restrict__ iso,
+                                                     double *__restrict__ A,
+                                                     double *__restrict__ b,
+                                                     double *__restrict__ R_out,
+                                                     double *__restrict__ partial)
+{
+    const int NF = (NC == 2) ? 2 : 4;
+    const int NE = (NF + 1) * NC * NC;
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long N = (long)P.nx * P.ny;
+    double nrm = 0.0;
+    if (idx < N) {
+        int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
+        double Rc[NC], D[NC][NC], Off[4][NC][NC];
+        cell_jacobian<NC, true>(P, z, U, i, j, Rc, D, Off);
+        if (R_out) {
+#pragma unroll
+            for (int r = 0; r < NC; ++r) R_out[r * N + idx] = Rc[r];
+        }
+        nrm = l1norm<NC>(Rc);
+#pragma unroll
+        for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
+        const bool me_iso = iso[idx] != 0;
+        if (me_iso) {
+#pragma unroll
+            for (int r = 0; r < NC; ++r)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    D[r][c] = 0.0;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) Off[f][r][c] = 0.0;
+                }
+        } else if (P.dry_pin && U[idx] == 0.0) {
+#pragma unroll
+            for (int r = 1; r < NC; ++r) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    D[r][c] = 0.0;
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) Off[f][r][c] = 0.0;
+                }
+                D[r][r] = D[0][0];
+                Rc[r] = 0.0;
+            }
+        }
+        for (int f = 0; f < NF; ++f) {
+            int ni, nj;
+            if (neighbour(P, i, j, f, ni, nj) && iso[(long)nj * P.nx + ni]) {
+#pragma unroll
+                for (int r = 0; r < NC; ++r)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) Off[f][r][c] = 0.0;
+            }
+        }
+        // colour-split store
+        const int color = (i + j) & 1;
+        const long slot = (long)j * G.W + (i >> 1);
+        double *Ac = A + (long)color * NE * G.plane + slot;
+        double *bc = b + (long)color * NC * G.plane + slot;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            bc[r * G.plane] = me_iso ? 0.0 : -Rc[r];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                Ac[(long)(r * NC + c) * G.plane] = D[r][c];
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+                    Ac[(long)(((f + 1) * NC + r) * NC + c) * G.plane] = Off[f][r][c];
+            }
+        }
+    }
+    double s = block_sum(nrm);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_residual(Phys P, const double *__restrict__ z,
+                                                     const double *__restrict__ U,
+                                                     double *__restrict__ R_out,
+                                                     double *__restrict__ partial)
+{
+    const int NF = (NC == 2) ? 2 : 4;
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long N = (long)P.nx * P.ny;
+    double nrm = 0.0;
+    if (idx < N) {
+        int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
+        double qi[NC];
+        load_state<NC>(P, U, idx, qi);
+        Side own = cell_side<NC>(P, qi, z[idx]);
+        double Rc[NC];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) Rc[r] = 0.0;
+        for (int f = 0; f < NF; ++f) {
+            int ni, nj;
+            Side oth;
+            if (neighbour(P, i, j, f, ni, nj)) {
+                long nidx = (long)nj * P.nx + ni;
+                double qj[NC];
+                load_state<NC>(P, U, nidx, qj);
+                oth = cell_side<NC>(P, qj, z[nidx]);
+            } else {
+                oth = ghost(P, f, own);
+            }
+            double T[NC];
+            edge_term<NC>(P, f, own, oth, T);
+#pragma unroll
+            for (int r = 0; r < NC; ++r) Rc[r] = Rc[r] + P.elen[f] * T[r];
+        }
+        if (R_out) {
+#pragma unroll
+            for (int r = 0; r < NC; ++r) R_out[r * N + idx] = Rc[r];
+        }
+        nrm = l1norm<NC>(Rc);
+    }
+    double s = block_sum(nrm);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ partial, int n,
+                                                   double *__restrict__ out)
+{
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += kBlock) v = v + partial[k];
+    double s = block_sum(v);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_count_u8(const unsigned char *__restrict__ v, long n,
+                                                     double *__restrict__ partial)
+{
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    double c = (idx < n && v[idx]) ? 1.0 : 0.0;
+    double s = block_sum(c);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// One BLU-SGS cell update for every cell of one colour (Algorithm 1,
+// Step 2.1): U_i -= (alpha ||R_i||_1 I + dR_i/dU_i)^-1 R_i, then the dry
+// threshold.  Cells of one colour only read the other colour.
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__restrict__ z,
+                                                     double *__restrict__ U, int color)
+{
+    const int W = (P.nx + 1) / 2;
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)W * P.ny) return;
+    int j = (int)(t / W), k = (int)(t % W);
+    int i = 2 * k + ((j + color) & 1);
+    if (i >= P.nx) return;
+    const long N = (long)P.nx * P.ny;
+    const long idx = (long)j * P.nx + i;
+    double Rc[NC], D[NC][NC];
+    cell_jacobian<NC, false>(P, z, U, i, j, Rc, D, nullptr);
+    double nrm = l1norm<NC>(Rc);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
+    if (P.dry_pin && U[idx] == 0.0) {
+#pragma unroll
+        for (int r = 1; r < NC; ++r) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
+            D[r][r] = D[0][0];
+            Rc[r] = 0.0;
+        }
+    }
+    double M[NC * NC], d[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) M[r * NC + c] = D[r][c];
+    solve_block<NC>(M, Rc, d);
+    double q[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q[c] = U[c * N + idx] - d[c];
+    if (q[0] < P.h_eps) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
+}
+
+// Relaxed update U += tau_i dU (positivity-limited tau_i) and dry threshold.
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_update(Phys P, LevelGeom G,
+                                                   const double *__restrict__ x,
+                                                   double *__restrict__ U)
+{
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long N = (long)P.nx * P.ny;
+    if (idx >= N) return;
+    int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
+    const int color = (i + j) & 1;
+    const double *xs = x + (long)color * NC * G.plane + (long)j * G.W + (i >> 1);
+    double dq[NC], q[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        dq[c] = xs[c * G.plane];
+        q[c] = U[c * N + idx];
+    }
+    const double th = P.pos_theta, tau = P.tau;
+    double t = tau;
+    double h = q[0], dh = dq[0];
+    if (th > 0.0 && dh < 0.0 && h + tau * dh < (1.0 - th) * h) t = th * h / (-dh);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q[c] = q[c] + t * dq[c];
+    if (q[0] < P.h_eps) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_threshold(Phys P, double *__restrict__ U)
+{
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long N = (long)P.nx * P.ny;
+    if (idx >= N) return;
+    if (U[idx] < P.h_eps) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) U[c * N + idx] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Linear multigrid kernels on the colour-split layout.
+
+// Value of the other-colour neighbour at fine cell (ni, nj) under `mode`.
+template <int NC, int MODE>
+__device__ __forceinline__ void read_other(const LevelGeom &G, const double *xo, int ni, int nj,
+                                           const LevelGeom &Gc, const double *xc, double *v)
+{
+    if (MODE == MODE_ZERO) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = 0.0;
+        return;
+    }
+    double base[NC];
+    if (MODE == MODE_NORMAL || MODE == MODE_PROLONG) {
+        const double *p = xo + (long)nj * G.W + (ni >> 1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) base[c] = p[c * G.plane];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) base[c] = 0.0;
+    }
+    if (MODE == MODE_NORMAL) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = base[c];
+        return;
+    }
+    int I = ni >> 1, J = nj >> 1;
+    int cc = (I + J) & 1;
+    const double *p = xc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = base[c] + p[c * Gc.plane];
+}
+
+// Block Gauss-Seidel half sweep of one colour: x_i = D_i^-1 (b_i - sum_j
+// A_ij x_j), the sum over existing neighbours in W, E, S, N order and then
+// components.  One thread per cell of the colour, coalesced along x.
+template <int NC, int MODE>
+__global__ void __launch_bounds__(kBlock) k_sgs_half(LevelGeom G, const double *__restrict__ A,
+                                                     const double *__restrict__ b,
+                                                     double *__restrict__ x, int color,
+                                                     LevelGeom Gc, const double *__restrict__ xc)
+{
+    const int NF = (NC == 2) ? 2 : 4;
+    const int NE = (NF + 1) * NC * NC;
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= G.plane) return;
+    const int j = (int)(t / G.W), k = (int)(t % G.W);
+    const int i = 2 * k + ((j + color) & 1);
+    if (i >= G.nx) return;
+    const int oc = color ^ 1;
+    const double *Am = A + (long)color * NE * G.plane + t;
+    const double *bm = b + (long)color * NC * G.plane + t;
+    const double *xo = x + (long)oc * NC * G.plane;
+    double acc[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) acc[r] = 0.0;
+    if (MODE != MODE_ZERO) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            int ni = i, nj = j;
+            bool ok;
+            if (f == FW) { ni = i - 1; ok = i > 0; }
+            else if (f == FE) { ni = i + 1; ok = i + 1 < G.nx; }
+            else if (f == FS) { nj = j - 1; ok = j > 0; }
+            else { nj = j + 1; ok = j + 1 < G.ny; }
+            if (!ok) continue;
+            double v[NC];
+            read_other<NC, MODE>(G, xo, ni, nj, Gc, xc, v);
+#pragma unroll
+            for (int r = 0; r < NC; ++r)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[r] = acc[r] + Am[(long)(((f + 1) * NC + r) * NC + c) * G.plane] * v[c];
+        }
+    }
+    double rhs[NC], D[NC * NC], xi[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        rhs[r] = bm[r * G.plane] - acc[r];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) D[r * NC + c] = Am[(long)(r * NC + c) * G.plane];
+    }
+    solve_block<NC>(D, rhs, xi);
+    double *xm = x + (long)color * NC * G.plane + t;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) xm[r * G.plane] = xi[r];
+}
+
+// Linear residual of fine cell (i, j): b - (D x_i + sum_nbr A x_nbr).
+template <int NC>
+__device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const double *A,
+                                                  const double *b, const double *x, int i, int j,
+                                                  double *r)
+{
+    const int NF = (NC == 2) ? 2 : 4;
+    const int NE = (NF + 1) * NC * NC;
+    const int color = (i + j) & 1;
+    const long slot = (long)j * G.W + (i >> 1);
+    const double *Am = A + (long)color * NE * G.plane + slot;
+    const double *bm = b + (long)color * NC * G.plane + slot;
+    const double *xm = x + (long)color * NC * G.plane + slot;
+    const double *xo = x + (long)(color ^ 1) * NC * G.plane;
+    double xi[NC], acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xi[c] = xm[c * G.plane];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        acc[q] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[q] = acc[q] + Am[(long)(q * NC + c) * G.plane] * xi[c];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        int ni = i, nj = j;
+        bool ok;
+        if (f == FW) { ni = i - 1; ok = i > 0; }
+        else if (f == FE) { ni = i + 1; ok = i + 1 < G.nx; }
+        else if (f == FS) { nj = j - 1; ok = j > 0; }
+        else { nj = j + 1; ok = j + 1 < G.ny; }
+        if (!ok) continue;
+        const double *p = xo + (long)nj * G.W + (ni >> 1);
+        double v[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = p[c * G.plane];
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                acc[q] = acc[q] + Am[(long)(((f + 1) * NC + q) * NC + c) * G.plane] * v[c];
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) r[q] = bm[q * G.plane] - acc[q];
+}
+
+// Restriction (eq:ProjectAR, right): coarse right-hand side = sum over the
+// children (SW, SE, NW, NE; 1D: left, right) of their linear residuals.
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const double *__restrict__ A,
+                                                     const double *__restrict__ b,
+                                                     const double *__restrict__ x, LevelGeom Gc,
+                                                     double *__restrict__ bc)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)Gc.nx * Gc.ny) return;
+    const int I = (int)(t % Gc.nx), J = (int)(t / Gc.nx);
+    const int nch = (NC == 2) ? 2 : 4;
+    double acc[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < nch; ++ch) {
+        int i = 2 * I + (ch & 1);
+        int j = (NC == 2) ? 0 : 2 * J + (ch >> 1);
+        double r[NC];
+        lin_residual_cell<NC>(G, A, b, x, i, j, r);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[q] = acc[q] + r[q];
+    }
+    const int cc = (I + J) & 1;
+    double *bm = bc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) bm[q * Gc.plane] = acc[q];
+}
+
+// Galerkin coarse blocks (eq:ProjectAR, left) with the child-pair order of
+// the definition: children of I (SW, SE, NW, NE), then children of J.
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const double *__restrict__ Af,
+                                                     LevelGeom Gc, double *__restrict__ Ac)
+{
+    const int NF = (NC == 2) ? 2 : 4;
+    const int NE = (NF + 1) * NC * NC;
+    const int NN = NC * NC;
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)Gc.nx * Gc.ny) return;
+    const int I = (int)(t % Gc.nx), J = (int)(t / Gc.nx);
+    // child (ci, cj) block blk entry e -> pointer
+    auto ent = [&](int ci, int cj, int blk, int e) -> double {
+        int col = (ci + cj) & 1;
+        return Af[((long)col * NE + blk * NN + e) * Gf.plane + (long)cj * Gf.W + (ci >> 1)];
+    };
+    const int cc = (I + J) & 1;
+    double *out = Ac + (long)cc * NE * Gc.plane + (long)J * Gc.W + (I >> 1);
+    enum { BD = 0, BW = 1, BE = 2, BS = 3, BN = 4 };
+    if (NC == 2) {
+        const int L = 2 * I, R = 2 * I + 1;
+        for (int e = 0; e < NN; ++e) {
+            double d = 0.0;
+            d = d + ent(L, 0, BD, e);
+            d = d + ent(L, 0, BE, e);
+            d = d + ent(R, 0, BW, e);
+            d = d + ent(R, 0, BD, e);
+            out[(long)(BD * NN + e) * Gc.plane] = d;
+            double w = 0.0, ea = 0.0;
+            if (I > 0) w = w + ent(L, 0, BW, e);
+            if (I + 1 < Gc.nx) ea = ea + ent(R, 0, BE, e);
+            out[(long)(BW * NN + e) * Gc.plane] = w;
+            out[(long)(BE * NN + e) * Gc.plane] = ea;
+        }
+        return;
+    }
+    const int x0 = 2 * I, x1 = 2 * I + 1, y0 = 2 * J, y1 = 2 * J + 1;
+    for (int e = 0; e < NN; ++e) {
+        double d = 0.0;
+        d = d + ent(x0, y0, BD, e);   // SW -> SW
+        d = d + ent(x0, y0, BE, e);   // SW -> SE
+        d = d + ent(x0, y0, BN, e);   // SW -> NW
+        d = d + ent(x1, y0, BW, e);   // SE -> SW
+        d = d + ent(x1, y0, BD, e);   // SE -> SE
+        d = d + ent(x1, y0, BN, e);   // SE -> NE
+        d = d + ent(x0, y1, BS, e);   // NW -> SW
+        d = d + ent(x0, y1, BD, e);   // NW -> NW
+        d = d + ent(x0, y1, BE, e);   // NW -> NE
+        d = d + ent(x1, y1, BS, e);   // NE -> SE
+        d = d + ent(x1, y1, BW, e);   // NE -> NW
+        d = d + ent(x1, y1, BD, e);   // NE -> NE
+        out[(long)(BD * NN + e) * Gc.plane] = d;
+        double w = 0.0, ea = 0.0, s = 0.0, n = 0.0;
+        if (I > 0) { w = w + ent(x0, y0, BW, e); w = w + ent(x0, y1, BW, e); }
+        if (I + 1 < Gc.nx) { ea = ea + ent(x1, y0, BE, e); ea = ea + ent(x1, y1, BE, e); }
+        if (J > 0) { s = s + ent(x0, y0, BS, e); s = s + ent(x1, y0, BS, e); }
+        if (J + 1 < Gc.ny) { n = n + ent(x0, y1, BN, e); n = n + ent(x1, y1, BN, e); }
+        out[(long)(BW * NN + e) * Gc.plane] = w;
+        out[(long)(BE * NN + e) * Gc.plane] = ea;
+        out[(long)(BS * NN + e) * Gc.plane] = s;
+        out[(long)(BN * NN + e) * Gc.plane] = n;
+    }
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_fix_color(LevelGeom G, int op, double *__restrict__ x,
+                                                      int color, LevelGeom Gc,
+                                                      const double *__restrict__ xc)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= G.plane) return;
+    const int j = (int)(t / G.W), k = (int)(t % G.W);
+    const int i = 2 * k + ((j + color) & 1);
+    if (i >= G.nx) return;
+    double *xm = x + (long)color * NC * G.plane + t;
+    if (op == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xm[c * G.plane] = 0.0;
+        return;
+    }
+    int I = i >> 1, J = j >> 1;
+    int cc = (I + J) & 1;
+    const double *p = xc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double base = (op == 1) ? xm[c * G.plane] : 0.0;
+        xm[c * G.plane] = base + p[c * Gc.plane];
+    }
+}
+
+// Layout conversions.  `n` components of a [n][ny][nx] array <-> colour-split.
+__global__ void __launch_bounds__(kBlock) k_to_split(int n, LevelGeom G,
+                                                     const double *__restrict__ v,
+                                                     double *__restrict__ s)
+{
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long N = (long)G.nx * G.ny;
+    if (idx >= N) return;
+    int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
+    int color = (i + j) & 1;
+    double *o = s + (long)color * n * G.plane + (long)j * G.W + (i >> 1);
+    for (int c = 0; c < n; ++c) o[c * G.plane] = v[c * N + idx];
+}
+
+__global__ void __launch_bounds__(kBlock) k_from_split(int n, LevelGeom G,
+                                                       const double *__restrict__ s,
+                                                       double *__restrict__ v)
+{
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long N = (long)G.nx * G.ny;
+    if (idx >= N) return;
+    int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
+    int color = (i + j) & 1;
+    const double *o = s + (long)color * n * G.plane + (long)j * G.W + (i >> 1);
+    for (int c = 0; c < n; ++c) v[c * N + idx] = o[c * G.plane];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+#define NMG_LAUNCH(kern, grid, ...)                                                   \
+    do {                                                                              \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);        \
+        return hipGetLastError();                                                     \
+    } while (0)
+
+hipError_t launch_isolated(const Phys &P, const double *z, const double *U, unsigned char *iso,
+                           hipStream_t s)
+{
+    int g = nblocks((long)P.nx * P.ny);
+    if (P.dim == 1) NMG_LAUNCH(k_isolated<2>, g, P, z, U, iso);
+    NMG_LAUNCH(k_isolated<3>, g, P, z, U, iso);
+}
+
+hipError_t launch_assemble(const Phys &P, const LevelGeom &G, const double *z, const double *U,
+                           const unsigned char *iso, double *A, double *b, double *R_out,
+                           double *partial, hipStream_t s)
+{
+    int g = nblocks((long)P.nx * P.ny);
+    if (P.dim == 1) NMG_LAUNCH(k_assemble<2>, g, P, G, z, U, iso, A, b, R_out, partial);
+    NMG_LAUNCH(k_assemble<3>, g, P, G, z, U, iso, A, b, R_out, partial);
+}
+
+hipError_t launch_residual(const Phys &P, const double *z, const double *U, double *R_out,
+                           double *partial, hipStream_t s)
+{
+    int g = nblocks((long)P.nx * P.ny);
+    if (P.dim == 1) NMG_LAUNCH(k_residual<2>, g, P, z, U, R_out, partial);
+    NMG_LAUNCH(k_residual<3>, g, P, z, U, R_out, partial);
+}
+
+hipError_t launch_reduce(const double *partial, int n, double *out, hipStream_t s)
+{
+    NMG_LAUNCH(k_reduce, 1, partial, n, out);
+}
+
+hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipStream_t s)
+{
+    NMG_LAUNCH(k_count_u8, nblocks(n), v, n, partial);
+}
+
+hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, hipStream_t s)
+{
+    int g = nblocks((long)((P.nx + 1) / 2) * P.ny);
+    if (P.dim == 1) NMG_LAUNCH(k_blu_half<2>, g, P, z, U, color);
+    NMG_LAUNCH(k_blu_half<3>, g, P, z, U, color);
+}
+
+hipError_t launch_update(const Phys &P, const LevelGeom &G, const double *x, double *U,
+                         hipStream_t s)
+{
+    int g = nblocks((long)P.nx * P.ny);
+    if (P.dim == 1) NMG_LAUNCH(k_update<2>, g, P, G, x, U);
+    NMG_LAUNCH(k_update<3>, g, P, G, x, U);
+}
+
+hipError_t launch_threshold(const Phys &P, double *U, hipStream_t s)
+{
+    int g = nblocks((long)P.nx * P.ny);
+    if (P.dim == 1) NMG_LAUNCH(k_threshold<2>, g, P, U);
+    NMG_LAUNCH(k_threshold<3>, g, P, U);
+}
+
+template <int NC>
+static hipError_t sgs_dispatch(int mode, const LevelGeom &G, const double *A, const double *b,
+                               double *x, int color, const LevelGeom &Gc, const double *xc,
+                               hipStream_t s)
+{
+    int g = nblocks(G.plane);
+    switch (mode) {
+    case MODE_NORMAL: NMG_LAUNCH((k_sgs_half<NC, MODE_NORMAL>), g, G, A, b, x, color, Gc, xc);
+    case MODE_ZERO: NMG_LAUNCH((k_sgs_half<NC, MODE_ZERO>), g, G, A, b, x, color, Gc, xc);
+    case MODE_PROLONG: NMG_LAUNCH((k_sgs_half<NC, MODE_PROLONG>), g, G, A, b, x, color, Gc, xc);
+    default: NMG_LAUNCH((k_sgs_half<NC, MODE_PROLONG_ZERO>), g, G, A, b, x, color, Gc, xc);
+    }
+}
+
+hipError_t launch_sgs_half(int dim, int mode, const LevelGeom &G, const double *A, const double *b,
+                           double *x, int color, const LevelGeom &Gc, const double *xc,
+                           hipStream_t s)
+{
+    if (dim == 1) return sgs_dispatch<2>(mode, G, A, b, x, color, Gc, xc, s);
+    return sgs_dispatch<3>(mode, G, A, b, x, color, Gc, xc, s);
+}
+
+hipError_t launch_restrict(int dim, const LevelGeom &G, const double *A, const double *b,
+                           const double *x, const LevelGeom &Gc, double *bc, hipStream_t s)
+{
+    int g = nblocks((long)Gc.nx * Gc.ny);
+    if (dim == 1) NMG_LAUNCH(k_restrict<2>, g, G, A, b, x, Gc, bc);
+    NMG_LAUNCH(k_restrict<3>, g, G, A, b, x, Gc, bc);
+}
+
+hipError_t launch_galerkin(int dim, const LevelGeom &Gf, const double *Af, const LevelGeom &Gc,
+                           double *Ac, hipStream_t s)
+{
+    int g = nblocks((long)Gc.nx * Gc.ny);
+    if (dim == 1) NMG_LAUNCH(k_galerkin<2>, g, Gf, Af, Gc, Ac);
+    NMG_LAUNCH(k_galerkin<3>, g, Gf, Af, Gc, Ac);
+}
+
+hipError_t launch_fix_color(int dim, int op, const LevelGeom &G, double *x, int color,
+                            const LevelGeom &Gc, const double *xc, hipStream_t s)
+{
+    int g = nblocks(G.plane);
+    if (dim == 1) NMG_LAUNCH(k_fix_color<2>, g, G, op, x, color, Gc, xc);
+    NMG_LAUNCH(k_fix_color<3>, g, G, op, x, color, Gc, xc);
+}
+
+hipError_t launch_vec_to_split(int nc, const LevelGeom &G, const double *v, double *split,
+                               hipStream_t s)
+{
+    NMG_LAUNCH(k_to_split, nblocks((long)G.nx * G.ny), nc, G, v, split);
+}
+
+hipError_t launch_vec_from_split(int nc, const LevelGeom &G, const double *split, double *v,
+                                 hipStream_t s)
+{
+    NMG_LAUNCH(k_from_split, nblocks((long)G.nx * G.ny), nc, G, split, v);
+}
+
+hipError_t launch_mat_to_split(int ne, const LevelGeom &G, const double *A, double *split,
+                               hipStream_t s)
+{
+    NMG_LAUNCH(k_to_split, nblocks((long)G.nx * G.ny), ne, G, A, split);
+}
+
+hipError_t launch_mat_from_split(int ne, const LevelGeom &G, const double *split, double *A,
+                                 hipStream_t s)
+{
+    NMG_LAUNCH(k_from_split, nblocks((long)G.nx * G.ny), ne, G, split, A);
+}
+
+}  // namespace nmg

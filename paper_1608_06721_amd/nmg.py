@@ -1,0 +1,225 @@
+"""Thin Python binding of libnmg.so (include/nmg.h) over torch device tensors.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Tensors must be torch.float64, contiguous, on the GPU, in the
+layouts of include/nmg.h (cell vectors [nc][ny][nx], bed [ny][nx], blocks
+[nb][nc][nc][ny][nx]).  There is no CPU fallback: if the library cannot be
+loaded, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+from . import build as _build
+
+NMG_OK, NMG_NOT_CONVERGED = 0, 1
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
+          -4: "ENONFINITE", -5: "EDIVERGED"}
+
+
+class nmg_grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double)]
+
+
+class nmg_side(C.Structure):
+    _fields_ = [("kind", C.c_int), ("h", C.c_double), ("qn", C.c_double), ("ut", C.c_double)]
+
+
+class nmg_bc(C.Structure):
+    _fields_ = [("side", nmg_side * 4)]
+
+
+class nmg_params(C.Structure):
+    _fields_ = [("flux", C.c_int), ("g", C.c_double), ("alpha", C.c_double),
+                ("fd_eps", C.c_double), ("tau", C.c_double), ("h_eps", C.c_double),
+                ("eps_r", C.c_double), ("n_levels", C.c_int), ("nu1", C.c_int),
+                ("nu2", C.c_int), ("nu_coarse", C.c_int), ("n_mg", C.c_int),
+                ("blu_sweeps", C.c_int), ("max_newton", C.c_int), ("dry_pin", C.c_int),
+                ("pos_theta", C.c_double)]
+
+
+class nmg_stats(C.Structure):
+    _fields_ = [("newton_steps", C.c_int), ("status", C.c_int), ("n_pinned", C.c_int),
+                ("res_l1", C.c_double), ("res_hist", C.POINTER(C.c_double)),
+                ("hist_cap", C.c_int)]
+
+
+_lib = None
+EXPORTS = ["nmg_create", "nmg_destroy", "nmg_last_error", "nmg_residual",
+           "nmg_assemble_residual_jacobian", "nmg_mg_vcycle", "nmg_sgs", "nmg_blu_sweep",
+           "nmg_newton_mg_solve", "nmg_load_system", "nmg_get_system", "nmg_timing_enable",
+           "nmg_timing_read"]
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def lib():
+    """Load libnmg.so (building it first only if it does not exist)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        vp = C.c_void_p
+        L.nmg_create.argtypes = [C.POINTER(nmg_grid), C.POINTER(nmg_bc), C.POINTER(nmg_params),
+                                 vp, C.POINTER(vp)]
+        L.nmg_destroy.argtypes = [vp]
+        L.nmg_destroy.restype = None
+        L.nmg_last_error.argtypes = [vp]
+        L.nmg_last_error.restype = C.c_char_p
+        L.nmg_residual.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
+        L.nmg_assemble_residual_jacobian.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double)]
+        L.nmg_mg_vcycle.argtypes = [vp, vp, C.c_int]
+        L.nmg_sgs.argtypes = [vp, C.c_int, vp, C.c_int]
+        L.nmg_blu_sweep.argtypes = [vp, vp, vp]
+        L.nmg_newton_mg_solve.argtypes = [vp, vp, vp, C.c_double, C.POINTER(nmg_stats)]
+        L.nmg_load_system.argtypes = [vp, vp, vp]
+        L.nmg_get_system.argtypes = [vp, C.c_int, vp, vp]
+        L.nmg_timing_enable.argtypes = [vp, C.c_int, C.c_int]
+        L.nmg_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_longlong)]
+        _lib = L
+    return _lib
+
+
+def _ptr(t: Optional[torch.Tensor], what: str):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
+            or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous float64 CUDA tensor" % what)
+    return C.c_void_p(t.data_ptr())
+
+
+class NMGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+class Context:
+    """One grid / boundary condition / parameter set (nmg_create)."""
+
+    def __init__(self, dim, nx, ny, x0, x1, y0, y1, bc, params: dict, stream=None):
+        self.dim, self.nx, self.ny = int(dim), int(nx), int(ny)
+        self.nc = 2 if self.dim == 1 else 3
+        self.nb = 3 if self.dim == 1 else 5
+        self.n_levels = int(params["n_levels"])
+        g = nmg_grid(self.dim, self.nx, self.ny, x0, x1, y0, y1)
+        b = nmg_bc()
+        for k, s in enumerate(bc):
+            b.side[k] = nmg_side(int(s[0]), float(s[1]), float(s[2]), float(s[3]))
+        p = nmg_params(int(params["flux"]), params["g"], params["alpha"], params["fd_eps"],
+                       params["tau"], params["h_eps"], params["eps_r"], int(params["n_levels"]),
+                       int(params["nu1"]), int(params["nu2"]), int(params["nu_coarse"]),
+                       int(params["n_mg"]), int(params["blu_sweeps"]),
+                       int(params["max_newton"]), int(params["dry_pin"]),
+                       float(params["pos_theta"]))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        rc = lib().nmg_create(C.byref(g), C.byref(b), C.byref(p), C.c_void_p(stream.cuda_stream),
+                              C.byref(h))
+        if rc != 0:
+            raise NMGError(rc, "nmg_create failed")
+        self._h = h
+
+    @classmethod
+    def from_problem(cls, prob, stream=None, **overrides):
+        params = dict(prob.params)
+        params.update(overrides)
+        return cls(prob.dim, prob.nx, prob.ny, prob.x0, prob.x1, prob.y0, prob.y1, prob.bc,
+                   params, stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, ok=(0,)):
+        if rc not in ok:
+            msg = lib().nmg_last_error(self._h)
+            raise NMGError(rc, msg.decode() if msg else "")
+        return rc
+
+    def level_shape(self, level):
+        nx = self.nx >> level
+        ny = 1 if self.dim == 1 else self.ny >> level
+        return nx, ny
+
+    # --- entry points ------------------------------------------------------
+    def residual(self, z, U, R_out=None, want_norm=True):
+        res = C.c_double(0.0)
+        self._check(lib().nmg_residual(self._h, _ptr(z, "z"), _ptr(U, "U"), _ptr(R_out, "R_out"),
+                                       C.byref(res) if want_norm else None))
+        return res.value if want_norm else None
+
+    def assemble_residual_jacobian(self, z, U, R_out=None, want_norm=True):
+        res = C.c_double(0.0)
+        self._check(lib().nmg_assemble_residual_jacobian(
+            self._h, _ptr(z, "z"), _ptr(U, "U"), _ptr(R_out, "R_out"),
+            C.byref(res) if want_norm else None))
+        return res.value if want_norm else None
+
+    def mg_vcycle(self, dU, n_cycles=1):
+        self._check(lib().nmg_mg_vcycle(self._h, _ptr(dU, "dU"), int(n_cycles)))
+
+    def sgs(self, dU, iters, level=0):
+        self._check(lib().nmg_sgs(self._h, int(level), _ptr(dU, "dU"), int(iters)))
+
+    def blu_sweep(self, z, U):
+        self._check(lib().nmg_blu_sweep(self._h, _ptr(z, "z"), _ptr(U, "U")))
+
+    def newton_mg_solve(self, z, U, tol, hist_cap=10000):
+        hist = (C.c_double * hist_cap)()
+        st = nmg_stats(0, 0, 0, 0.0, C.cast(hist, C.POINTER(C.c_double)), hist_cap)
+        rc = lib().nmg_newton_mg_solve(self._h, _ptr(z, "z"), _ptr(U, "U"), float(tol),
+                                       C.byref(st))
+        self._check(rc, ok=(0, 1, -4, -5))
+        n = st.newton_steps
+        nh = min(n + 1 if rc in (0, -4, -5) else n, hist_cap)
+        return dict(status=STATUS.get(rc, rc), newton_steps=n, n_pinned=st.n_pinned,
+                    res_l1=st.res_l1, res_hist=[hist[k] for k in range(nh)])
+
+    def load_system(self, A0, b0):
+        self._check(lib().nmg_load_system(self._h, _ptr(A0, "A0"), _ptr(b0, "b0")))
+
+    def get_system(self, level=0, want_A=True, want_b=True):
+        nx, ny = self.level_shape(level)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        A = torch.empty((self.nb, self.nc, self.nc, ny, nx), dtype=torch.float64, device=dev) \
+            if want_A else None
+        b = torch.empty((self.nc, ny, nx), dtype=torch.float64, device=dev) if want_b else None
+        self._check(lib().nmg_get_system(self._h, int(level), _ptr(A, "A"), _ptr(b, "b")))
+        return A, b
+
+    def timing_enable(self, enable=True, cap=4096):
+        self._check(lib().nmg_timing_enable(self._h, int(bool(enable)), int(cap)))
+
+    def timing_read(self):
+        ms, n, cells = C.c_double(0), C.c_int(0), C.c_longlong(0)
+        self._check(lib().nmg_timing_read(self._h, C.byref(ms), C.byref(n), C.byref(cells)))
+        return dict(ms=ms.value, launches=n.value, cells=cells.value)
+
+
+def newton_mg_solve(prob, z, U, tol, stream=None, **overrides):
+    """Convenience: create a context for `prob` and solve in place from U."""
+    ctx = Context.from_problem(prob, stream, **overrides)
+    try:
+        return ctx.newton_mg_solve(z, U, tol)
+    finally:
+        ctx.close()
