@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the Newton multigrid steady shallow-water solver on one MI355X.
+
+One step = one steady solve of the 2D channel workload (1024 x 1024 cells,
+FP64): from the resting initial state resident in HBM to sum_i ||R_i||_1 <
+tol, i.e. every part of the hot path (BLU-SGS pre-smoothing, residual and
+FD-Jacobian assembly, Galerkin coarsening, red-black block-SGS V-cycles,
+relaxed update) as many Newton steps as the solve needs.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(the finest-level block SGS half sweep, timed with hipEvents on the
+library's stream) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "steady solves/s at 1024^2 to 1e-10 resid; SGS sweep HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes of one 2D FP64 block SGS cell update: the 45 block
+# entries (D and the four neighbour blocks), b_i, the new x_i, and the
+# neighbours' x (each read once per half sweep, 24 B per update amortized).
+SGS_BYTES_2D = 45 * 8 + 24 + 24 + 24
+
+
+def workload(args):
+    from paper_1608_06721_amd import workloads as W
+    n = args.size
+    levels = args.levels if args.levels is not None else int(math.log2(n)) - 2
+    prob = W.channel(n, n, n_levels=levels, max_newton=args.max_newton,
+                     bump_width=tuple(args.bump_width), mound_amp=args.mound_amp)
+    return prob
+
+
+def cpu_baseline(prob, n_steps, budget_s):
+    """The oracle (single thread) on a bounded sample of the same solve:
+    as many whole Newton steps as fit the budget (at least one), scaled to
+    solves/s with the solve's step count."""
+    import oracle
+    p = dict(prob.params)
+    t0 = time.time()
+    done = 0
+    U = prob.U0.copy()
+    while True:
+        U, _ = oracle.newton_solve(prob, U0=U, tol=0.0, params=dict(p, max_newton=1))
+        done += 1
+        if time.time() - t0 > budget_s * 0.5 or done >= max(1, n_steps):
+            break
+    dt = time.time() - t0
+    per_step = dt / done
+    return dict(value=1.0 / (per_step * max(1, n_steps)), unit="solves/s", cores=1,
+                kind="oracle",
+                sample="%d Newton step(s) of the same %dx%d solve in %.1f s on one host core, "
+                       "scaled by the solve's %d steps" % (done, prob.nx, prob.ny, dt, n_steps),
+                s_per_newton_step=per_step)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--levels", type=int, default=None)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--max-newton", type=int, default=500)
+    # Bed of the measured channel: 16 seeded Gaussians (amplitude U[0, 0.3],
+    # width U[0.2, 0.8]) and two mounds of amplitude 0.8 (one emerges as a
+    # dry island).  Narrower bumps or higher mounds do not converge with
+    # this method at 1024^2 (workload section).
+    ap.add_argument("--bump-width", type=float, nargs=2, default=[0.2, 0.8])
+    ap.add_argument("--mound-amp", type=float, default=0.8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--timing-cap", type=int, default=20000)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the method's single solve is not sharded "
+              "across GPUs in this build (see DESIGN.md); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1608_06721_amd import nmg
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    prob = workload(args)
+    print("[bench] workload %s levels=%d tol=%g" % (prob.name, prob.params["n_levels"], args.tol),
+          file=sys.stderr, flush=True)
+    ctx = nmg.Context.from_problem(prob)
+    z = torch.from_numpy(prob.z).cuda()
+    U0 = torch.from_numpy(prob.U0).cuda()
+    Us = [U0.clone() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        U = U0.clone()
+        st = ctx.newton_mg_solve(z, U, args.tol)
+        print("[bench] warmup %d: %s steps=%d res=%.3e" % (w, st["status"], st["newton_steps"],
+                                                          st["res_l1"]),
+              file=sys.stderr, flush=True)
+
+    ctx.timing_enable(True, args.timing_cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(args.steps):
+        stats.append(ctx.newton_mg_solve(z, Us[k], args.tol))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing_enable(False)
+    tm = ctx.timing_read()
+    for k, st in enumerate(stats):
+        print("[bench] solve %d: %s steps=%d res=%.3e" % (k, st["status"], st["newton_steps"],
+                                                         st["res_l1"]),
+              file=sys.stderr, flush=True)
+    converged = all(st["status"] == "OK" for st in stats)
+    n_newton = stats[-1]["newton_steps"]
+    ms_per_step = 1e3 * dt / args.steps
+
+    avg_ms = tm["ms"] / max(1, tm["launches"])
+    cells_per_launch = tm["cells"] / max(1, tm["launches"])
+    bytes_per_launch = cells_per_launch * SGS_BYTES_2D
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if tm["launches"] else None
+    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=None,
+                    kernel="k_sgs_half<3, MODE_NORMAL> (finest level)",
+                    avg_launch_us=avg_ms * 1e3, launches=tm["launches"],
+                    bytes_per_launch=bytes_per_launch)
+
+    out = {
+        "metric": METRIC,
+        "value": (args.steps / dt) if converged else None,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "channel_%dx%d" % (prob.nx, prob.ny),
+            "domain": [0.0, 10.0, 0.0, 2.0],
+            "bed": "16 seeded Gaussians (amp U[0,0.3], width U[%g,%g]) + 2 mounds of "
+                   "amplitude %g, width 0.25 (seed %d)" % (args.bump_width[0], args.bump_width[1],
+                                                         args.mound_amp, 160806721),
+            "flux": "LLF", "n_levels": prob.params["n_levels"],
+            "cycle": "V(%d,%d), nu_coarse=%d, n_mg=%d" % (prob.params["nu1"], prob.params["nu2"],
+                                                         prob.params["nu_coarse"],
+                                                         prob.params["n_mg"]),
+            "tol": args.tol, "newton_steps": n_newton, "converged": converged,
+            "final_res_l1": stats[-1]["res_l1"],
+            "ms_per_newton_step": ms_per_step / max(1, n_newton),
+        },
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob, n_newton, args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -168,8 +168,10 @@ int nmg_load_system(nmg_ctx *ctx, const double *A0, const double *b0);
 int nmg_get_system(nmg_ctx *ctx, int level, double *A, double *b);
 
 /* Measurement hooks.  With enable = 1 the library records a pair of
- * hipEvents on its stream around each finest-level block SGS half sweep,
- * for at most `cap` launches (older records are dropped when re-enabled);
+ * hipEvents on its stream around each full finest-level block SGS half
+ * sweep (one that reads every neighbour block), for at most `cap`
+ * (<= 2^20) launches; the events are created here, so recording adds no
+ * allocation to the solve, and enabling again drops earlier records.
  * enable = 0 stops recording.  nmg_timing_read synchronizes the stream and
  * returns, over the recorded launches, the summed kernel milliseconds, the
  * number of launches and the number of cell updates they performed. */

@@ -51,7 +51,7 @@ struct nmg_ctx {
     std::string err;
     // measurement hooks
     bool timing = false;
-    int tcap = 0;
+    int nrec = 0;                 // events of ev[] in use
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<long long> ev_cells;
 };
@@ -128,25 +128,18 @@ int halfsweep(nmg_ctx *c, int l, int color)
     default: mode = MODE_PROLONG_ZERO; break;
     }
     const Level &Lc = c->L[l + 1 <= c->NL ? l + 1 : l];
-    bool rec = c->timing && l == 0 && (int)c->ev.size() < c->tcap;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (rec) {
-        HIPCHK(c, hipEventCreate(&e0));
-        HIPCHK(c, hipEventCreate(&e1));
-        HIPCHK(c, hipEventRecord(e0, c->stream));
-    }
+    // Measurement hook: only full half sweeps (all neighbour blocks read)
+    // of the finest level are recorded.
+    const int k = c->nrec;
+    const bool rec = c->timing && l == 0 && mode == MODE_NORMAL && k < (int)c->ev.size();
+    if (rec) HIPCHK(c, hipEventRecord(c->ev[k].first, c->stream));
     HIPCHK(c, launch_sgs_half(c->dim, mode, Lv.G, Lv.A, Lv.b, Lv.x, color, Lc.G, Lc.x, c->stream));
     if (rec) {
-        HIPCHK(c, hipEventRecord(e1, c->stream));
-        c->ev.emplace_back(e0, e1);
-        int W = Lv.G.W;
+        HIPCHK(c, hipEventRecord(c->ev[k].second, c->stream));
         long n = 0;
-        for (int j = 0; j < Lv.G.ny; ++j) {
-            int first = (j + color) & 1;
-            n += (Lv.G.nx - first + 1) / 2;
-        }
-        (void)W;
-        c->ev_cells.push_back(n);
+        for (int j = 0; j < Lv.G.ny; ++j) n += (Lv.G.nx - ((j + color) & 1) + 1) / 2;
+        c->ev_cells[k] = n;
+        c->nrec = k + 1;
     }
     Lv.st[color] = ST_VALID;
     Lv.last = color;
@@ -490,14 +483,19 @@ int nmg_timing_enable(nmg_ctx *c, int enable, int cap)
 {
     if (!c) return NMG_EINVAL;
     if (enable) {
+        if (cap < 0 || cap > (1 << 20)) return fail(c, NMG_EINVAL, "timing cap out of range");
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        for (auto &e : c->ev) {
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
+        while ((int)c->ev.size() < cap) {
+            hipEvent_t a, b;
+            HIPCHK(c, hipEventCreate(&a));
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return fail(c, NMG_EHIP, "hipEventCreate failed");
+            }
+            c->ev.emplace_back(a, b);
         }
-        c->ev.clear();
-        c->ev_cells.clear();
-        c->tcap = cap > 0 ? cap : 0;
+        c->ev_cells.assign(c->ev.size(), 0);
+        c->nrec = 0;
     }
     c->timing = enable != 0;
     return NMG_OK;
@@ -509,14 +507,14 @@ int nmg_timing_read(nmg_ctx *c, double *ms_host, int *launches_host, long long *
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double tot = 0.0;
     long long cl = 0;
-    for (size_t k = 0; k < c->ev.size(); ++k) {
+    for (int k = 0; k < c->nrec; ++k) {
         float ms = 0.0f;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev[k].first, c->ev[k].second));
         tot += ms;
         cl += c->ev_cells[k];
     }
     if (ms_host) *ms_host = tot;
-    if (launches_host) *launches_host = (int)c->ev.size();
+    if (launches_host) *launches_host = c->nrec;
     if (cells_host) *cells_host = cl;
     return NMG_OK;
 }
