@@ -31,6 +31,23 @@ HBM_PEAK_GBS = 8000.0
 SGS_BYTES_2D = 45 * 8 + 24 + 24 + 24
 
 
+def measured_traffic():
+    """HBM bytes per finest-level SGS launch from the committed rocprofv3
+    counter runs, or None if the kernel source changed since they were taken."""
+    import hashlib
+    prof = os.path.join(HERE, "profiles", "sgs_halfsweep_channel1024_f64_pmc.md")
+    src = os.path.join(HERE, "paper_1608_06721_amd", "csrc", "nmg_kernels.hip")
+    try:
+        fields = dict(l.split(":", 1) for l in open(prof).read().splitlines()
+                      if l.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:")))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if fields["kernel_source_sha256_16"].strip() != digest:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def workload(args):
     from paper_1608_06721_amd import workloads as W
     n = args.size
@@ -81,6 +98,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--timing-cap", type=int, default=20000)
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="only run finest-level SGS iterations on the assembled system and a "
+                         "512 MiB device copy (for hardware-counter runs), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -101,6 +121,20 @@ def main():
     ctx = nmg.Context.from_problem(prob)
     z = torch.from_numpy(prob.z).cuda()
     U0 = torch.from_numpy(prob.U0).cuda()
+    if args.kernel_probe:
+        # Counter calibration: a plain copy of a known size, then 4 block SGS
+        # iterations (red, black, red per iteration after the first) on the
+        # system assembled at the initial state.
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        dst.copy_(src)
+        ctx.assemble_residual_jacobian(z, U0)
+        dU = torch.zeros_like(U0)
+        ctx.sgs(dU, 4)
+        torch.cuda.synchronize()
+        print("[bench] kernel probe done", file=sys.stderr, flush=True)
+        return
     Us = [U0.clone() for _ in range(args.steps)]
     torch.cuda.synchronize()
 
@@ -133,8 +167,11 @@ def main():
     cells_per_launch = tm["cells"] / max(1, tm["launches"])
     bytes_per_launch = cells_per_launch * SGS_BYTES_2D
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if tm["launches"] else None
+    traffic = measured_traffic()
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=None,
+                    frac=(achieved / HBM_PEAK_GBS) if achieved else None,
+                    traffic=(traffic / (avg_ms * 1e-3) / 1e9) if (traffic and achieved) else None,
+                    traffic_bytes_per_launch=traffic,
                     kernel="k_sgs_half<3, MODE_NORMAL> (finest level)",
                     avg_launch_us=avg_ms * 1e3, launches=tm["launches"],
                     bytes_per_launch=bytes_per_launch)

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -54,6 +55,13 @@ struct nmg_ctx {
     int nrec = 0;                 // events of ev[] in use
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<long long> ev_cells;
+    // coarse part of the V-cycle in one workgroup (levels lc..NL), recorded
+    // once from the same state machine that drives the per-level launches
+    int lc = -1;
+    bool recording = false;
+    std::vector<CoarseOp> rec;
+    CoarseOp *d_ops = nullptr;
+    LevelDev *d_lv = nullptr;
 };
 
 namespace {
@@ -128,6 +136,12 @@ int halfsweep(nmg_ctx *c, int l, int color)
     default: mode = MODE_PROLONG_ZERO; break;
     }
     const Level &Lc = c->L[l + 1 <= c->NL ? l + 1 : l];
+    if (c->recording) {
+        c->rec.push_back(CoarseOp{COP_SGS, l, color, mode});
+        Lv.st[color] = ST_VALID;
+        Lv.last = color;
+        return NMG_OK;
+    }
     // Measurement hook: only full half sweeps (all neighbour blocks read)
     // of the finest level are recorded.
     const int k = c->nrec;
@@ -168,7 +182,10 @@ int materialize(nmg_ctx *c, int l)
         else if (Lv.st[color] == ST_VALID_PP) op = 1;
         else if (Lv.st[color] == ST_ZERO_PP) op = 2;
         if (op < 0) continue;
-        HIPCHK(c, launch_fix_color(c->dim, op, Lv.G, Lv.x, color, Lc.G, Lc.x, c->stream));
+        if (c->recording)
+            c->rec.push_back(CoarseOp{COP_FIX, l, color, op});
+        else
+            HIPCHK(c, launch_fix_color(c->dim, op, Lv.G, Lv.x, color, Lc.G, Lc.x, c->stream));
         Lv.st[color] = ST_VALID;
         Lv.last = -1;
     }
@@ -186,6 +203,14 @@ int cycle(nmg_ctx *c, int l)
 {
     const nmg_params &p = c->prm;
     int rc;
+    if (l == c->lc && !c->recording) {
+        // the whole sub-cycle from level lc down runs in one workgroup; it
+        // leaves level lc's correction materialized
+        HIPCHK(c, launch_coarse_cycle(c->dim, c->d_ops, (int)c->rec.size(), c->d_lv, c->stream));
+        c->L[l].st[0] = c->L[l].st[1] = ST_VALID;
+        c->L[l].last = -1;
+        return NMG_OK;
+    }
     if ((rc = smooth(c, l, p.nu1))) return rc;
     if (l == c->NL) {
         if ((rc = smooth(c, l, p.nu_coarse))) return rc;
@@ -193,7 +218,10 @@ int cycle(nmg_ctx *c, int l)
         if ((rc = materialize(c, l))) return rc;
         Level &Lv = c->L[l];
         Level &Lc = c->L[l + 1];
-        HIPCHK(c, launch_restrict(c->dim, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b, c->stream));
+        if (c->recording)
+            c->rec.push_back(CoarseOp{COP_RESTRICT, l, 0, 0});
+        else
+            HIPCHK(c, launch_restrict(c->dim, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b, c->stream));
         set_zero(c, l + 1);
         if ((rc = cycle(c, l + 1))) return rc;
         if ((rc = materialize(c, l + 1))) return rc;
@@ -210,6 +238,44 @@ int build_coarse(nmg_ctx *c)
         HIPCHK(c, launch_galerkin(c->dim, c->L[l - 1].G, c->L[l - 1].A, c->L[l].G, c->L[l].A,
                                   c->stream));
     for (int l = 0; l <= c->NL; ++l) set_zero(c, l);
+    return NMG_OK;
+}
+
+// Record the operations of the sub-cycle from level lc (which always starts
+// from a zero correction) and upload them with the level table.
+int plan_coarse(nmg_ctx *c)
+{
+    long maxcells = 256;
+    if (const char *e = std::getenv("NMG_COARSE_CELLS")) maxcells = std::atol(e);
+    c->lc = -1;
+    for (int l = 1; l <= c->NL; ++l)
+        if (cells(c->L[l].G) <= maxcells) { c->lc = l; break; }
+    if (c->lc < 0) return NMG_OK;
+    Level saved[16];
+    for (int l = 0; l <= c->NL; ++l) saved[l] = c->L[l];
+    c->rec.clear();
+    c->recording = true;
+    set_zero(c, c->lc);
+    int rc = cycle(c, c->lc);
+    if (!rc) rc = materialize(c, c->lc);
+    c->recording = false;
+    for (int l = 0; l <= c->NL; ++l) c->L[l] = saved[l];
+    if (rc) return rc;
+    if ((int)c->rec.size() > kMaxCoarseOps) {   // too long for LDS: per-level launches
+        c->lc = -1;
+        c->rec.clear();
+        return NMG_OK;
+    }
+    LevelDev lv[kMaxLevels];
+    for (int l = 0; l < kMaxLevels; ++l) {
+        const Level &Lv = c->L[l <= c->NL ? l : c->NL];
+        lv[l] = LevelDev{Lv.G, Lv.A, Lv.b, Lv.x};
+    }
+    size_t ob = sizeof(CoarseOp) * c->rec.size();
+    if (hipMalloc(&c->d_ops, ob) != hipSuccess || hipMalloc(&c->d_lv, sizeof lv) != hipSuccess)
+        return fail(c, NMG_ENOMEM, "coarse-cycle tables");
+    HIPCHK(c, hipMemcpy(c->d_ops, c->rec.data(), ob, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_lv, lv, sizeof lv, hipMemcpyHostToDevice));
     return NMG_OK;
 }
 
@@ -304,7 +370,7 @@ int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     for (int l = 0; l <= c->NL; ++l) {
         int nx = grid->nx >> l, ny = grid->dim == 1 ? 1 : grid->ny >> l;
         c->L[l].G = make_geom(nx, ny);
-        total += (size_t)2 * (c->ne + 2 * c->nc) * c->L[l].G.plane;
+        total += (size_t)2 * c->ne * c->L[l].G.planeP + (size_t)2 * 2 * c->nc * c->L[l].G.plane;
     }
     double *pool = nullptr;
     if (hipMalloc(&pool, total * sizeof(double)) != hipSuccess) {
@@ -314,7 +380,7 @@ int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     size_t off = 0;
     for (int l = 0; l <= c->NL; ++l) {
         Level &Lv = c->L[l];
-        Lv.A = pool + off; off += (size_t)2 * c->ne * Lv.G.plane;
+        Lv.A = pool + off; off += (size_t)2 * c->ne * Lv.G.planeP;
         Lv.b = pool + off; off += (size_t)2 * c->nc * Lv.G.plane;
         Lv.x = pool + off; off += (size_t)2 * c->nc * Lv.G.plane;
     }
@@ -329,6 +395,11 @@ int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     if (!ok) {
         nmg_destroy(c);
         return NMG_ENOMEM;
+    }
+    rc = plan_coarse(c);
+    if (rc) {
+        nmg_destroy(c);
+        return rc;
     }
     *out = c;
     return NMG_OK;
@@ -348,6 +419,8 @@ void nmg_destroy(nmg_ctx *c)
     if (c->scal) (void)hipFree(c->scal);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
     if (c->Ulast) (void)hipFree(c->Ulast);
+    if (c->d_ops) (void)hipFree(c->d_ops);
+    if (c->d_lv) (void)hipFree(c->d_lv);
     delete c;
 }
 

@@ -24,12 +24,17 @@ struct Phys {
 };
 
 // Geometry of one multigrid level in the colour-split layout: every cell
-// (i, j) lives in colour (i + j) & 1 at slot (j, i >> 1) of a [ny][W]
-// plane, W = (nx + 1) / 2.  Vectors are [colour][NC][ny][W]; matrices are
-// [colour][NE][ny][W] with entry e = (block * NC + row) * NC + col.
+// (i, j) lives in colour (i + j) & 1 at slot t = j * W + (i >> 1) of a
+// [ny][W] plane, W = (nx + 1) / 2.  Vectors are [colour][NC][ny][W].
+// Matrices are tiled by 64 slots (one wavefront): [colour][tile][NE][64],
+// entry e = (block * NC + row) * NC + col, so the NE entries that one wave
+// reads in a half sweep form one contiguous NE * 512-byte run.
+constexpr int kTile = 64;
+
 struct LevelGeom {
     int nx, ny, W;
     long plane;             // ny * W
+    long planeP;            // plane rounded up to a multiple of kTile
 };
 
 inline LevelGeom make_geom(int nx, int ny)
@@ -39,7 +44,15 @@ inline LevelGeom make_geom(int nx, int ny)
     g.ny = ny;
     g.W = (nx + 1) / 2;
     g.plane = (long)ny * g.W;
+    g.planeP = (g.plane + kTile - 1) / kTile * kTile;
     return g;
+}
+
+// Offset of entry 0 of slot t's block row in a colour-split tiled matrix
+// with NE entries per row; entry e is at + e * kTile.
+__host__ __device__ inline long mat_off(const LevelGeom &G, int NE, int color, long t)
+{
+    return (long)color * NE * G.planeP + (t / kTile) * NE * kTile + (t % kTile);
 }
 
 // Read mode of the other colour in a block SGS half sweep.
@@ -51,6 +64,24 @@ enum SweepMode {
 };
 
 constexpr int kBlock = 256;
+constexpr int kCoarseBlock = 512;     // one workgroup runs the coarse part of a cycle
+constexpr int kMaxLevels = 16;
+constexpr int kMaxCoarseOps = 2048;  // LDS capacity of the coarse-cycle kernel's op list
+
+// Device-side description of one level (for the coarse-cycle kernel).
+struct LevelDev {
+    LevelGeom G;
+    double *A, *b, *x;
+};
+
+// One operation of the recorded coarse part of a V-cycle.
+enum CoarseOpKind { COP_SGS = 0, COP_RESTRICT = 1, COP_FIX = 2 };
+struct CoarseOp {
+    int kind;               // CoarseOpKind
+    int level;
+    int color;              // SGS / FIX: colour
+    int mode;               // SGS: SweepMode; FIX: 0 zero, 1 add parent, 2 set parent
+};
 
 inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
 
@@ -80,6 +111,10 @@ hipError_t launch_galerkin(int dim, const LevelGeom &Gf, const double *Af, const
 // coarse value, 2 = set to the parent's coarse value.
 hipError_t launch_fix_color(int dim, int op, const LevelGeom &G, double *x, int color,
                             const LevelGeom &Gc, const double *xc, hipStream_t s);
+
+// The recorded coarse part of a V-cycle, executed by one workgroup.
+hipError_t launch_coarse_cycle(int dim, const CoarseOp *ops, int nops, const LevelDev *lv,
+                               hipStream_t s);
 
 // Layout conversions between the public layouts and the colour-split one.
 hipError_t launch_vec_to_split(int nc, const LevelGeom &G, const double *v, double *split,

@@ -253,10 +253,15 @@ __device__ __forceinline__ double block_sum(double v)
 
 // Residual and forward-difference blocks of one cell.  D receives
 // sum_e |e| dT/dU_i, Off[f] receives |e| dT/dU_j for interior faces.
-template <int NC, bool WANT_OFF>
+// Off-diagonal blocks are handed to `off(f, r, k, value)` as soon as face f
+// is done (value 0 on boundary faces), so no per-face array is kept.
+struct NoOff {
+    __device__ void operator()(int, int, int, double) const {}
+};
+
+template <int NC, bool WANT_OFF, class OffSink>
 __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, const double *U, int i,
-                                              int j, double *Rc, double (*D)[NC],
-                                              double (*Off)[NC][NC])
+                                              int j, double *Rc, double (*D)[NC], const OffSink &off)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const long idx = (long)j * P.nx + i;
@@ -310,7 +315,7 @@ __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, co
                     Side othp = cell_side<NC>(P, qp, zj);
                     edge_term<NC>(P, f, own, othp, Tk);
 #pragma unroll
-                    for (int r = 0; r < NC; ++r) Off[f][r][k] = e * ((Tk[r] - T0[r]) / eps);
+                    for (int r = 0; r < NC; ++r) off(f, r, k, e * ((Tk[r] - T0[r]) / eps));
                 }
             }
         } else {
@@ -329,7 +334,7 @@ __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, co
 #pragma unroll
                 for (int r = 0; r < NC; ++r)
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) Off[f][r][c] = 0.0;
+                    for (int c = 0; c < NC; ++c) off(f, r, c, 0.0);
             }
         }
     }
@@ -378,6 +383,22 @@ __global__ void __launch_bounds__(kBlock) k_isolated(Phys P, const double *__res
     iso[idx] = res;
 }
 
+// Stores the off-diagonal blocks of one cell in the colour-split layout,
+// applying the pinning rules: an isolated cell gets a zero row, a dry cell
+// under the dry-cell pin zero momentum rows, and the column of an isolated
+// neighbour is zero.
+template <int NC>
+struct OffStore {
+    double *Ac;            // this cell's entry 0 in the colour-split matrix
+    bool me_iso, dryp;
+    bool nb_iso[4];
+    __device__ void operator()(int f, int r, int c, double v) const
+    {
+        if (me_iso || nb_iso[f] || (dryp && r > 0)) v = 0.0;
+        Ac[(((f + 1) * NC + r) * NC + c) * kTile] = v;
+    }
+};
+
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
                                                      const double *__restrict__ z,
@@ -395,8 +416,18 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
     double nrm = 0.0;
     if (idx < N) {
         int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
-        double Rc[NC], D[NC][NC], Off[4][NC][NC];
-        cell_jacobian<NC, true>(P, z, U, i, j, Rc, D, Off);
+        const int color = (i + j) & 1;
+        const long slot = (long)j * G.W + (i >> 1);
+        OffStore<NC> st;
+        st.Ac = A + mat_off(G, NE, color, slot);
+        st.me_iso = iso[idx] != 0;
+        st.dryp = !st.me_iso && P.dry_pin && U[idx] == 0.0;
+        for (int f = 0; f < 4; ++f) {
+            int ni, nj;
+            st.nb_iso[f] = f < NF && neighbour(P, i, j, f, ni, nj) && iso[(long)nj * P.nx + ni];
+        }
+        double Rc[NC], D[NC][NC];
+        cell_jacobian<NC, true>(P, z, U, i, j, Rc, D, st);
         if (R_out) {
 #pragma unroll
             for (int r = 0; r < NC; ++r) R_out[r * N + idx] = Rc[r];
@@ -404,53 +435,26 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
         nrm = l1norm<NC>(Rc);
 #pragma unroll
         for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
-        const bool me_iso = iso[idx] != 0;
-        if (me_iso) {
+        if (st.me_iso) {
 #pragma unroll
             for (int r = 0; r < NC; ++r)
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    D[r][c] = 0.0;
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) Off[f][r][c] = 0.0;
-                }
-        } else if (P.dry_pin && U[idx] == 0.0) {
+                for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
+        } else if (st.dryp) {
 #pragma unroll
             for (int r = 1; r < NC; ++r) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    D[r][c] = 0.0;
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) Off[f][r][c] = 0.0;
-                }
+                for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
                 D[r][r] = D[0][0];
                 Rc[r] = 0.0;
             }
         }
-        for (int f = 0; f < NF; ++f) {
-            int ni, nj;
-            if (neighbour(P, i, j, f, ni, nj) && iso[(long)nj * P.nx + ni]) {
-#pragma unroll
-                for (int r = 0; r < NC; ++r)
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) Off[f][r][c] = 0.0;
-            }
-        }
-        // colour-split store
-        const int color = (i + j) & 1;
-        const long slot = (long)j * G.W + (i >> 1);
-        double *Ac = A + (long)color * NE * G.plane + slot;
         double *bc = b + (long)color * NC * G.plane + slot;
 #pragma unroll
         for (int r = 0; r < NC; ++r) {
-            bc[r * G.plane] = me_iso ? 0.0 : -Rc[r];
+            bc[r * G.plane] = st.me_iso ? 0.0 : -Rc[r];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                Ac[(long)(r * NC + c) * G.plane] = D[r][c];
-#pragma unroll
-                for (int f = 0; f < NF; ++f)
-                    Ac[(long)(((f + 1) * NC + r) * NC + c) * G.plane] = Off[f][r][c];
-            }
+            for (int c = 0; c < NC; ++c) st.Ac[(r * NC + c) * kTile] = D[r][c];
         }
     }
     double s = block_sum(nrm);
@@ -535,7 +539,7 @@ __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__res
     const long N = (long)P.nx * P.ny;
     const long idx = (long)j * P.nx + i;
     double Rc[NC], D[NC][NC];
-    cell_jacobian<NC, false>(P, z, U, i, j, Rc, D, nullptr);
+    cell_jacobian<NC, false>(P, z, U, i, j, Rc, D, NoOff());
     double nrm = l1norm<NC>(Rc);
 #pragma unroll
     for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
@@ -645,57 +649,87 @@ __device__ __forceinline__ void read_other(const LevelGeom &G, const double *xo,
 
 // Block Gauss-Seidel half sweep of one colour: x_i = D_i^-1 (b_i - sum_j
 // A_ij x_j), the sum over existing neighbours in W, E, S, N order and then
-// components.  One thread per cell of the colour, coalesced along x.
+// components.  One thread per cell of the colour, coalesced along x.  All
+// loads of a cell (its block row, b_i and the neighbours' x) are issued
+// before any arithmetic, so each wave keeps ~50 independent loads in flight.
 template <int NC, int MODE>
-__global__ void __launch_bounds__(kBlock) k_sgs_half(LevelGeom G, const double *__restrict__ A,
-                                                     const double *__restrict__ b,
-                                                     double *__restrict__ x, int color,
-                                                     LevelGeom Gc, const double *__restrict__ xc)
+__device__ __forceinline__ void sgs_cell(const LevelGeom &G, const double *__restrict__ A,
+                                         const double *__restrict__ b, double *__restrict__ x,
+                                         int color, const LevelGeom &Gc,
+                                         const double *__restrict__ xc, long t)
 {
-    const int NF = (NC == 2) ? 2 : 4;
-    const int NE = (NF + 1) * NC * NC;
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= G.plane) return;
+    constexpr int NF = (NC == 2) ? 2 : 4;
+    constexpr int NN = NC * NC;
+    constexpr int NE = (NF + 1) * NN;
     const int j = (int)(t / G.W), k = (int)(t % G.W);
     const int i = 2 * k + ((j + color) & 1);
     if (i >= G.nx) return;
     const int oc = color ^ 1;
-    const double *Am = A + (long)color * NE * G.plane + t;
+    const double *Am = A + mat_off(G, NE, color, t);
     const double *bm = b + (long)color * NC * G.plane + t;
     const double *xo = x + (long)oc * NC * G.plane;
+
+    bool ok[NF];
+    int ni[NF], nj[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        ni[f] = i;
+        nj[f] = j;
+        if (f == FW) { ni[f] = i - 1; ok[f] = i > 0; }
+        else if (f == FE) { ni[f] = i + 1; ok[f] = i + 1 < G.nx; }
+        else if (f == FS) { nj[f] = j - 1; ok[f] = j > 0; }
+        else { nj[f] = j + 1; ok[f] = j + 1 < G.ny; }
+    }
+    double a[NE], bv[NC], v[NF][NC];
+#pragma unroll
+    for (int e = 0; e < NN; ++e) a[e] = Am[e * kTile];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) bv[r] = bm[r * G.plane];
+    if (MODE != MODE_ZERO) {
+#pragma unroll
+        for (int e = NN; e < NE; ++e) a[e] = Am[e * kTile];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (ok[f]) {
+                read_other<NC, MODE>(G, xo, ni[f], nj[f], Gc, xc, v[f]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) v[f][c] = 0.0;
+            }
+        }
+    }
     double acc[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) acc[r] = 0.0;
     if (MODE != MODE_ZERO) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            int ni = i, nj = j;
-            bool ok;
-            if (f == FW) { ni = i - 1; ok = i > 0; }
-            else if (f == FE) { ni = i + 1; ok = i + 1 < G.nx; }
-            else if (f == FS) { nj = j - 1; ok = j > 0; }
-            else { nj = j + 1; ok = j + 1 < G.ny; }
-            if (!ok) continue;
-            double v[NC];
-            read_other<NC, MODE>(G, xo, ni, nj, Gc, xc, v);
+            if (!ok[f]) continue;
 #pragma unroll
             for (int r = 0; r < NC; ++r)
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
-                    acc[r] = acc[r] + Am[(long)(((f + 1) * NC + r) * NC + c) * G.plane] * v[c];
+                    acc[r] = acc[r] + a[((f + 1) * NC + r) * NC + c] * v[f][c];
         }
     }
-    double rhs[NC], D[NC * NC], xi[NC];
+    double rhs[NC], xi[NC];
 #pragma unroll
-    for (int r = 0; r < NC; ++r) {
-        rhs[r] = bm[r * G.plane] - acc[r];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) D[r * NC + c] = Am[(long)(r * NC + c) * G.plane];
-    }
-    solve_block<NC>(D, rhs, xi);
+    for (int r = 0; r < NC; ++r) rhs[r] = bv[r] - acc[r];
+    solve_block<NC>(a, rhs, xi);
     double *xm = x + (long)color * NC * G.plane + t;
 #pragma unroll
     for (int r = 0; r < NC; ++r) xm[r * G.plane] = xi[r];
+}
+
+template <int NC, int MODE>
+__global__ void __launch_bounds__(kBlock) k_sgs_half(LevelGeom G, const double *__restrict__ A,
+                                                     const double *__restrict__ b,
+                                                     double *__restrict__ x, int color,
+                                                     LevelGeom Gc, const double *__restrict__ xc)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= G.plane) return;
+    sgs_cell<NC, MODE>(G, A, b, x, color, Gc, xc, t);
 }
 
 // Linear residual of fine cell (i, j): b - (D x_i + sum_nbr A x_nbr).
@@ -708,7 +742,7 @@ __device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const doub
     const int NE = (NF + 1) * NC * NC;
     const int color = (i + j) & 1;
     const long slot = (long)j * G.W + (i >> 1);
-    const double *Am = A + (long)color * NE * G.plane + slot;
+    const double *Am = A + mat_off(G, NE, color, slot);
     const double *bm = b + (long)color * NC * G.plane + slot;
     const double *xm = x + (long)color * NC * G.plane + slot;
     const double *xo = x + (long)(color ^ 1) * NC * G.plane;
@@ -719,7 +753,7 @@ __device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const doub
     for (int q = 0; q < NC; ++q) {
         acc[q] = 0.0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[q] = acc[q] + Am[(long)(q * NC + c) * G.plane] * xi[c];
+        for (int c = 0; c < NC; ++c) acc[q] = acc[q] + Am[(q * NC + c) * kTile] * xi[c];
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -738,7 +772,7 @@ __device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const doub
         for (int q = 0; q < NC; ++q)
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                acc[q] = acc[q] + Am[(long)(((f + 1) * NC + q) * NC + c) * G.plane] * v[c];
+                acc[q] = acc[q] + Am[(((f + 1) * NC + q) * NC + c) * kTile] * v[c];
     }
 #pragma unroll
     for (int q = 0; q < NC; ++q) r[q] = bm[q * G.plane] - acc[q];
@@ -747,13 +781,11 @@ __device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const doub
 // Restriction (eq:ProjectAR, right): coarse right-hand side = sum over the
 // children (SW, SE, NW, NE; 1D: left, right) of their linear residuals.
 template <int NC>
-__global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const double *__restrict__ A,
-                                                     const double *__restrict__ b,
-                                                     const double *__restrict__ x, LevelGeom Gc,
-                                                     double *__restrict__ bc)
+__device__ __forceinline__ void restrict_cell(const LevelGeom &G, const double *__restrict__ A,
+                                              const double *__restrict__ b,
+                                              const double *__restrict__ x, const LevelGeom &Gc,
+                                              double *__restrict__ bc, long t)
 {
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= (long)Gc.nx * Gc.ny) return;
     const int I = (int)(t % Gc.nx), J = (int)(t / Gc.nx);
     const int nch = (NC == 2) ? 2 : 4;
     double acc[NC];
@@ -774,6 +806,17 @@ __global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const double *
     for (int q = 0; q < NC; ++q) bm[q * Gc.plane] = acc[q];
 }
 
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const double *__restrict__ A,
+                                                     const double *__restrict__ b,
+                                                     const double *__restrict__ x, LevelGeom Gc,
+                                                     double *__restrict__ bc)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)Gc.nx * Gc.ny) return;
+    restrict_cell<NC>(G, A, b, x, Gc, bc, t);
+}
+
 // Galerkin coarse blocks (eq:ProjectAR, left) with the child-pair order of
 // the definition: children of I (SW, SE, NW, NE), then children of J.
 template <int NC>
@@ -789,10 +832,10 @@ __global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const double 
     // child (ci, cj) block blk entry e -> pointer
     auto ent = [&](int ci, int cj, int blk, int e) -> double {
         int col = (ci + cj) & 1;
-        return Af[((long)col * NE + blk * NN + e) * Gf.plane + (long)cj * Gf.W + (ci >> 1)];
+        return Af[mat_off(Gf, NE, col, (long)cj * Gf.W + (ci >> 1)) + (blk * NN + e) * kTile];
     };
     const int cc = (I + J) & 1;
-    double *out = Ac + (long)cc * NE * Gc.plane + (long)J * Gc.W + (I >> 1);
+    double *out = Ac + mat_off(Gc, NE, cc, (long)J * Gc.W + (I >> 1));
     enum { BD = 0, BW = 1, BE = 2, BS = 3, BN = 4 };
     if (NC == 2) {
         const int L = 2 * I, R = 2 * I + 1;
@@ -802,12 +845,12 @@ __global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const double 
             d = d + ent(L, 0, BE, e);
             d = d + ent(R, 0, BW, e);
             d = d + ent(R, 0, BD, e);
-            out[(long)(BD * NN + e) * Gc.plane] = d;
+            out[(BD * NN + e) * kTile] = d;
             double w = 0.0, ea = 0.0;
             if (I > 0) w = w + ent(L, 0, BW, e);
             if (I + 1 < Gc.nx) ea = ea + ent(R, 0, BE, e);
-            out[(long)(BW * NN + e) * Gc.plane] = w;
-            out[(long)(BE * NN + e) * Gc.plane] = ea;
+            out[(BW * NN + e) * kTile] = w;
+            out[(BE * NN + e) * kTile] = ea;
         }
         return;
     }
@@ -826,26 +869,24 @@ __global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const double 
         d = d + ent(x1, y1, BS, e);   // NE -> SE
         d = d + ent(x1, y1, BW, e);   // NE -> NW
         d = d + ent(x1, y1, BD, e);   // NE -> NE
-        out[(long)(BD * NN + e) * Gc.plane] = d;
+        out[(BD * NN + e) * kTile] = d;
         double w = 0.0, ea = 0.0, s = 0.0, n = 0.0;
         if (I > 0) { w = w + ent(x0, y0, BW, e); w = w + ent(x0, y1, BW, e); }
         if (I + 1 < Gc.nx) { ea = ea + ent(x1, y0, BE, e); ea = ea + ent(x1, y1, BE, e); }
         if (J > 0) { s = s + ent(x0, y0, BS, e); s = s + ent(x1, y0, BS, e); }
         if (J + 1 < Gc.ny) { n = n + ent(x0, y1, BN, e); n = n + ent(x1, y1, BN, e); }
-        out[(long)(BW * NN + e) * Gc.plane] = w;
-        out[(long)(BE * NN + e) * Gc.plane] = ea;
-        out[(long)(BS * NN + e) * Gc.plane] = s;
-        out[(long)(BN * NN + e) * Gc.plane] = n;
+        out[(BW * NN + e) * kTile] = w;
+        out[(BE * NN + e) * kTile] = ea;
+        out[(BS * NN + e) * kTile] = s;
+        out[(BN * NN + e) * kTile] = n;
     }
 }
 
 template <int NC>
-__global__ void __launch_bounds__(kBlock) k_fix_color(LevelGeom G, int op, double *__restrict__ x,
-                                                      int color, LevelGeom Gc,
-                                                      const double *__restrict__ xc)
+__device__ __forceinline__ void fix_cell(const LevelGeom &G, int op, double *__restrict__ x,
+                                         int color, const LevelGeom &Gc,
+                                         const double *__restrict__ xc, long t)
 {
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= G.plane) return;
     const int j = (int)(t / G.W), k = (int)(t % G.W);
     const int i = 2 * k + ((j + color) & 1);
     if (i >= G.nx) return;
@@ -862,6 +903,56 @@ __global__ void __launch_bounds__(kBlock) k_fix_color(LevelGeom G, int op, doubl
     for (int c = 0; c < NC; ++c) {
         double base = (op == 1) ? xm[c * G.plane] : 0.0;
         xm[c * G.plane] = base + p[c * Gc.plane];
+    }
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_fix_color(LevelGeom G, int op, double *__restrict__ x,
+                                                      int color, LevelGeom Gc,
+                                                      const double *__restrict__ xc)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= G.plane) return;
+    fix_cell<NC>(G, op, x, color, Gc, xc, t);
+}
+
+// The coarse levels of a V-cycle in one workgroup: the host records the
+// exact sequence of half sweeps, restrictions and colour fixes that the
+// level-by-level launches would perform, and this kernel executes it with a
+// workgroup barrier between operations (one CU; the coarse data stay in L2).
+template <int NC>
+__global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *__restrict__ ops,
+                                                               int nops,
+                                                               const LevelDev *__restrict__ lv_g)
+{
+    // The op list and the level table live in LDS for the whole kernel, so
+    // each operation costs one round trip for its data only.
+    __shared__ CoarseOp sops[kMaxCoarseOps];
+    __shared__ LevelDev lv[kMaxLevels];
+    for (int q = threadIdx.x; q < nops; q += kCoarseBlock) sops[q] = ops[q];
+    for (int q = threadIdx.x; q < kMaxLevels; q += kCoarseBlock) lv[q] = lv_g[q];
+    __syncthreads();
+    for (int q = 0; q < nops; ++q) {
+        const CoarseOp op = sops[q];
+        const LevelDev L = lv[op.level];
+        const LevelDev Lc = lv[op.level + 1 < kMaxLevels ? op.level + 1 : op.level];
+        if (op.kind == COP_SGS) {
+            for (long t = threadIdx.x; t < L.G.plane; t += kCoarseBlock) {
+                switch (op.mode) {
+                case MODE_NORMAL: sgs_cell<NC, MODE_NORMAL>(L.G, L.A, L.b, L.x, op.color, Lc.G, Lc.x, t); break;
+                case MODE_ZERO: sgs_cell<NC, MODE_ZERO>(L.G, L.A, L.b, L.x, op.color, Lc.G, Lc.x, t); break;
+                case MODE_PROLONG: sgs_cell<NC, MODE_PROLONG>(L.G, L.A, L.b, L.x, op.color, Lc.G, Lc.x, t); break;
+                default: sgs_cell<NC, MODE_PROLONG_ZERO>(L.G, L.A, L.b, L.x, op.color, Lc.G, Lc.x, t); break;
+                }
+            }
+        } else if (op.kind == COP_RESTRICT) {
+            for (long t = threadIdx.x; t < (long)Lc.G.nx * Lc.G.ny; t += kCoarseBlock)
+                restrict_cell<NC>(L.G, L.A, L.b, L.x, Lc.G, Lc.b, t);
+        } else {
+            for (long t = threadIdx.x; t < L.G.plane; t += kCoarseBlock)
+                fix_cell<NC>(L.G, op.mode, L.x, op.color, Lc.G, Lc.x, t);
+        }
+        __syncthreads();
     }
 }
 
@@ -890,6 +981,31 @@ __global__ void __launch_bounds__(kBlock) k_from_split(int n, LevelGeom G,
     int color = (i + j) & 1;
     const double *o = s + (long)color * n * G.plane + (long)j * G.W + (i >> 1);
     for (int c = 0; c < n; ++c) v[c * N + idx] = o[c * G.plane];
+}
+
+// Block matrices [NE][ny][nx] <-> colour-split tiled layout.
+__global__ void __launch_bounds__(kBlock) k_mat_to_tiled(int ne, LevelGeom G,
+                                                         const double *__restrict__ v,
+                                                         double *__restrict__ s)
+{
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long N = (long)G.nx * G.ny;
+    if (idx >= N) return;
+    int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
+    double *o = s + mat_off(G, ne, (i + j) & 1, (long)j * G.W + (i >> 1));
+    for (int e = 0; e < ne; ++e) o[e * kTile] = v[e * N + idx];
+}
+
+__global__ void __launch_bounds__(kBlock) k_mat_from_tiled(int ne, LevelGeom G,
+                                                           const double *__restrict__ s,
+                                                           double *__restrict__ v)
+{
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    const long N = (long)G.nx * G.ny;
+    if (idx >= N) return;
+    int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
+    const double *o = s + mat_off(G, ne, (i + j) & 1, (long)j * G.W + (i >> 1));
+    for (int e = 0; e < ne; ++e) v[e * N + idx] = o[e * kTile];
 }
 
 }  // namespace
@@ -1006,6 +1122,17 @@ hipError_t launch_fix_color(int dim, int op, const LevelGeom &G, double *x, int 
     NMG_LAUNCH(k_fix_color<3>, g, G, op, x, color, Gc, xc);
 }
 
+hipError_t launch_coarse_cycle(int dim, const CoarseOp *ops, int nops, const LevelDev *lv,
+                               hipStream_t s)
+{
+    if (dim == 1) {
+        hipLaunchKernelGGL(k_coarse_cycle<2>, dim3(1), dim3(kCoarseBlock), 0, s, ops, nops, lv);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_coarse_cycle<3>, dim3(1), dim3(kCoarseBlock), 0, s, ops, nops, lv);
+    return hipGetLastError();
+}
+
 hipError_t launch_vec_to_split(int nc, const LevelGeom &G, const double *v, double *split,
                                hipStream_t s)
 {
@@ -1021,13 +1148,13 @@ hipError_t launch_vec_from_split(int nc, const LevelGeom &G, const double *split
 hipError_t launch_mat_to_split(int ne, const LevelGeom &G, const double *A, double *split,
                                hipStream_t s)
 {
-    NMG_LAUNCH(k_to_split, nblocks((long)G.nx * G.ny), ne, G, A, split);
+    NMG_LAUNCH(k_mat_to_tiled, nblocks((long)G.nx * G.ny), ne, G, A, split);
 }
 
 hipError_t launch_mat_from_split(int ne, const LevelGeom &G, const double *split, double *A,
                                  hipStream_t s)
 {
-    NMG_LAUNCH(k_from_split, nblocks((long)G.nx * G.ny), ne, G, split, A);
+    NMG_LAUNCH(k_mat_from_tiled, nblocks((long)G.nx * G.ny), ne, G, split, A);
 }
 
 }  // namespace nmg

@@ -145,9 +145,13 @@ def test_sgs_bitwise(nmg, case, iters):
 @pytest.mark.parametrize("case", LIN)
 @pytest.mark.parametrize("nus", [(2, 2, 10), (1, 0, 3), (0, 1, 2), (0, 0, 1), (3, 1, 0)])
 @pytest.mark.parametrize("cycles", [1, 3])
-def test_vcycle_bitwise(nmg, case, nus, cycles):
+@pytest.mark.parametrize("coarse_cells", ["4096", "0"])
+def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, monkeypatch):
+    """coarse_cells: levels up to this many cells run in the single-workgroup
+    coarse-cycle kernel ("0": every level launched on its own)."""
     prob, A, b, x0 = random_case(*case)
-    say("vcycle", case, nus, cycles)
+    say("vcycle", case, nus, cycles, coarse_cells)
+    monkeypatch.setenv("NMG_COARSE_CELLS", coarse_cells)
     p = dict(prob.params, nu1=nus[0], nu2=nus[1], nu_coarse=nus[2])
     ctx = nmg.Context.from_problem(prob, **p)
     ctx.load_system(dev(A), dev(b))
