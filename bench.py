@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # entries (D and the four neighbour blocks), b_i, the new x_i, and the
 # neighbours' x (each read once per half sweep, 24 B per update amortized).
 SGS_BYTES_2D = 45 * 8 + 24 + 24 + 24
+SGS_BYTES_2D_FP32 = 45 * 4 + 12 + 12 + 12
 
 
 def measured_traffic():
@@ -78,6 +79,23 @@ def cpu_baseline(prob, n_steps, budget_s):
                 sample="%d Newton step(s) of the same %dx%d solve in %.1f s on one host core, "
                        "scaled by the solve's %d steps" % (done, prob.nx, prob.ny, dt, n_steps),
                 s_per_newton_step=per_step)
+
+
+def timed_solves(ctx, z, U0, steps, warmup, tol, cap):
+    """Warm-up solves, then `steps` timed solves from U0 (inputs resident in
+    HBM); returns (seconds, stats, timing of the finest full SGS sweeps)."""
+    import torch
+    for _ in range(warmup):
+        ctx.newton_mg_solve(z, U0.clone(), tol)
+    Us = [U0.clone() for _ in range(steps)]
+    ctx.timing_enable(True, cap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [ctx.newton_mg_solve(z, Us[k], tol) for k in range(steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.timing_enable(False)
+    return dt, stats, ctx.timing_read()
 
 
 def main():
@@ -205,6 +223,27 @@ def main():
         },
         "roofline": roofline,
     }
+    # The same solve with the FP32 inner V-cycle (hierarchy and smoother in
+    # FP32, residual, update and stop test in FP64).
+    ctx32 = nmg.Context.from_problem(prob, inner_fp32=1)
+    dt32, st32, tm32 = timed_solves(ctx32, z, U0, args.steps, args.warmup, args.tol,
+                                    args.timing_cap)
+    ok32 = all(st["status"] == "OK" for st in st32)
+    avg32 = tm32["ms"] / max(1, tm32["launches"])
+    bpl32 = tm32["cells"] / max(1, tm32["launches"]) * SGS_BYTES_2D_FP32
+    ach32 = bpl32 / (avg32 * 1e-3) / 1e9 if tm32["launches"] else None
+    out["fp32_inner"] = {
+        "value": (args.steps / dt32) if ok32 else None, "unit": "solves/s",
+        "ms_per_step": 1e3 * dt32 / args.steps, "converged": ok32,
+        "newton_steps": st32[-1]["newton_steps"], "final_res_l1": st32[-1]["res_l1"],
+        "roofline": {"bound": "hbm", "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (ach32 / HBM_PEAK_GBS) if ach32 else None,
+                     "avg_launch_us": avg32 * 1e3, "bytes_per_launch": bpl32},
+    }
+    print("[bench] fp32-inner: %s steps=%d %.3f s/solve" % (ok32, st32[-1]["newton_steps"],
+                                                           dt32 / args.steps),
+          file=sys.stderr, flush=True)
+    ctx32.close()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, n_newton, args.cpu_budget)

@@ -89,7 +89,11 @@ typedef struct {
  * iterations that stand for the coarsest-level solve.  dry_pin (0/1) holds
  * the momentum of exactly dry cells at zero in the step that wets them;
  * pos_theta (>= 0, < 1) limits the per-cell relaxation so that no step
- * removes more than that fraction of a cell's depth (0 = tau everywhere). */
+ * removes more than that fraction of a cell's depth (0 = tau everywhere).
+ * inner_fp32 (0/1) stores the multigrid hierarchy (blocks, right-hand
+ * sides, corrections) in FP32 and runs the V-cycle in FP32, while residuals,
+ * assembly arithmetic, the update, the threshold and the stop test stay FP64
+ * (Newton then acts as iterative refinement). */
 typedef struct {
     int flux;
     double g, alpha, fd_eps, tau, h_eps, eps_r;
@@ -97,6 +101,7 @@ typedef struct {
     int blu_sweeps, max_newton;
     int dry_pin;
     double pos_theta;
+    int inner_fp32;
 } nmg_params;
 
 /* Solve statistics (host memory).  res_hist (optional, host) receives the

@@ -145,33 +145,6 @@ void orc_ghost(const orc_side *bc, int f, double g, double h_eps,
     else           { out[1] = utg;       out[2] = sgn * ung; }
 }
 
-/* Solve D x = r for one nc x nc block by the adjugate (cofactors expanded
- * along row 0) times the reciprocal determinant.  A block whose reciprocal
- * determinant is not finite (singular, or isolated cell) yields x = 0. */
-void orc_solve_block(int nc, const double *D, const double *r, double *x)
-{
-    if (nc == 2) {
-        double det = D[0] * D[3] - D[1] * D[2];
-        double idet = 1.0 / det;
-        if (!isfinite(idet)) { x[0] = 0.0; x[1] = 0.0; return; }
-        x[0] = (D[3] * r[0] - D[1] * r[1]) * idet;
-        x[1] = (D[0] * r[1] - D[2] * r[0]) * idet;
-        return;
-    }
-    double d00 = D[0], d01 = D[1], d02 = D[2];
-    double d10 = D[3], d11 = D[4], d12 = D[5];
-    double d20 = D[6], d21 = D[7], d22 = D[8];
-    double C00 = d11 * d22 - d12 * d21, C01 = d12 * d20 - d10 * d22, C02 = d10 * d21 - d11 * d20;
-    double C10 = d02 * d21 - d01 * d22, C11 = d00 * d22 - d02 * d20, C12 = d01 * d20 - d00 * d21;
-    double C20 = d01 * d12 - d02 * d11, C21 = d02 * d10 - d00 * d12, C22 = d00 * d11 - d01 * d10;
-    double det = d00 * C00 + d01 * C01 + d02 * C02;
-    double idet = 1.0 / det;
-    if (!isfinite(idet)) { x[0] = 0.0; x[1] = 0.0; x[2] = 0.0; return; }
-    x[0] = (C00 * r[0] + C10 * r[1] + C20 * r[2]) * idet;
-    x[1] = (C01 * r[0] + C11 * r[1] + C21 * r[2]) * idet;
-    x[2] = (C02 * r[0] + C12 * r[1] + C22 * r[2]) * idet;
-}
-
 /* ------------------------------------------------------------------------ */
 /* Problem description shared by the discretization routines. */
 typedef struct {
@@ -478,82 +451,6 @@ static lvl mklvl(int dim, int nx, int ny)
 
 #define LA(L, b, r, c, idx) ((((size_t)(b) * (L)->nc + (r)) * (L)->nc + (c)) * (L)->N + (idx))
 
-/* acc[r] += sum over existing neighbours (W, E, S, N), then components, of
- * A_f[r][c] x_nbr[c]. */
-static void offdiag_acc(const lvl *L, const double *A, const double *x, int i, int j, double *acc)
-{
-    int ni, nj, idx = j * L->nx + i;
-    for (int f = 0; f < L->nf; ++f) {
-        if (!nbr(L->dim, L->nx, L->ny, i, j, f, &ni, &nj)) continue;
-        int nidx = nj * L->nx + ni;
-        for (int r = 0; r < L->nc; ++r)
-            for (int c = 0; c < L->nc; ++c)
-                acc[r] = acc[r] + A[LA(L, f + 1, r, c, idx)] * x[c * L->N + nidx];
-    }
-}
-
-/* Block Gauss-Seidel update of one cell: x_i = D_i^{-1} (b_i - sum_j A_ij x_j). */
-static void gs_cell(const lvl *L, const double *A, const double *b, double *x, int i, int j)
-{
-    int idx = j * L->nx + i;
-    double acc[3] = {0, 0, 0}, rhs[3], D[9], xi[3];
-    offdiag_acc(L, A, x, i, j, acc);
-    for (int r = 0; r < L->nc; ++r) {
-        rhs[r] = b[r * L->N + idx] - acc[r];
-        for (int c = 0; c < L->nc; ++c) D[r * L->nc + c] = A[LA(L, 0, r, c, idx)];
-    }
-    orc_solve_block(L->nc, D, rhs, xi);
-    for (int r = 0; r < L->nc; ++r) x[r * L->N + idx] = xi[r];
-}
-
-/* Red-black half sweep: every cell with (i + j) mod 2 == color. */
-void orc_sgs_half(int dim, int nx, int ny, const double *A, const double *b, double *x, int color)
-{
-    lvl L = mklvl(dim, nx, ny);
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i)
-            if (((i + j) & 1) == color) gs_cell(&L, A, b, x, i, j);
-}
-
-/* `iters` block symmetric Gauss-Seidel iterations (the smoother of Sec. 2.3).
- * One iteration is a forward sweep followed by a backward sweep: in
- * lexicographic order the cells in increasing then decreasing index; in
- * red-black order red then black, then black then red. */
-void orc_sgs(int dim, int nx, int ny, const double *A, const double *b, double *x,
-             int iters, int order)
-{
-    lvl L = mklvl(dim, nx, ny);
-    for (int it = 0; it < iters; ++it) {
-        if (order == ORC_LEX) {
-            for (int idx = 0; idx < L.N; ++idx) gs_cell(&L, A, b, x, idx % nx, idx / nx);
-            for (int idx = L.N - 1; idx >= 0; --idx) gs_cell(&L, A, b, x, idx % nx, idx / nx);
-        } else {
-            orc_sgs_half(dim, nx, ny, A, b, x, 0);
-            orc_sgs_half(dim, nx, ny, A, b, x, 1);
-            orc_sgs_half(dim, nx, ny, A, b, x, 1);
-            orc_sgs_half(dim, nx, ny, A, b, x, 0);
-        }
-    }
-}
-
-/* Linear residual r = b - A x, with A x accumulated as the diagonal block's
- * product first and then the neighbours in W, E, S, N order. */
-void orc_lin_residual(int dim, int nx, int ny, const double *A, const double *b,
-                      const double *x, double *r)
-{
-    lvl L = mklvl(dim, nx, ny);
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            int idx = j * nx + i;
-            double acc[3] = {0, 0, 0};
-            for (int q = 0; q < L.nc; ++q)
-                for (int c = 0; c < L.nc; ++c)
-                    acc[q] = acc[q] + A[LA(&L, 0, q, c, idx)] * x[c * L.N + idx];
-            offdiag_acc(&L, A, x, i, j, acc);
-            for (int q = 0; q < L.nc; ++q) r[q * L.N + idx] = b[q * L.N + idx] - acc[q];
-        }
-}
-
 /* Children of coarse cell (I, J) in the order SW, SE, NW, NE (1D: left,
  * right).  Returns the count. */
 static int children(const lvl *Lf, int I, int J, int ci[4], int cj[4])
@@ -569,144 +466,64 @@ static int children(const lvl *Lf, int I, int J, int ci[4], int cj[4])
     return 4;
 }
 
-/* Restriction (right half of eq:ProjectAR, with b = -R): the coarse
- * right-hand side is the sum over the children, in child order, of the
- * children's linear residuals b - A x. */
-void orc_restrict(int dim, int nx, int ny, const double *A, const double *b,
-                  const double *x, double *bc)
+/* The linear multigrid in FP64 (suffix _d) and, for the FP32 inner
+ * V-cycle, in FP32 (suffix _f). */
+#define REAL double
+#define MG(name) name##_d
+#include "nmg_oracle_mg.inc"
+#undef REAL
+#undef MG
+#define REAL float
+#define MG(name) name##_f
+#include "nmg_oracle_mg.inc"
+#undef REAL
+#undef MG
+
+void orc_solve_block(int nc, const double *D, const double *r, double *x)
 {
-    lvl L = mklvl(dim, nx, ny);
-    int ncx = nx / 2, ncy = dim == 1 ? 1 : ny / 2, Nc = ncx * ncy;
-    double *r = (double *)malloc(sizeof(double) * (size_t)L.nc * L.N);
-    orc_lin_residual(dim, nx, ny, A, b, x, r);
-    for (int J = 0; J < ncy; ++J)
-        for (int I = 0; I < ncx; ++I) {
-            int ci[4], cj[4], n = children(&L, I, J, ci, cj);
-            for (int q = 0; q < L.nc; ++q) {
-                double acc = 0.0;
-                for (int k = 0; k < n; ++k) acc = acc + r[q * L.N + cj[k] * nx + ci[k]];
-                bc[q * Nc + J * ncx + I] = acc;
-            }
-        }
-    free(r);
+    solve_block_d(nc, D, r, x);
 }
 
-/* Prolongation (eq:correction), piecewise constant: every child receives its
- * parent's correction. */
+void orc_sgs_half(int dim, int nx, int ny, const double *A, const double *b, double *x, int color)
+{
+    sgs_half_d(dim, nx, ny, A, b, x, color);
+}
+
+void orc_sgs(int dim, int nx, int ny, const double *A, const double *b, double *x, int iters,
+             int order)
+{
+    sgs_d(dim, nx, ny, A, b, x, iters, order);
+}
+
+void orc_lin_residual(int dim, int nx, int ny, const double *A, const double *b, const double *x,
+                      double *r)
+{
+    lin_residual_d(dim, nx, ny, A, b, x, r);
+}
+
+void orc_restrict(int dim, int nx, int ny, const double *A, const double *b, const double *x,
+                  double *bc)
+{
+    restrict__d(dim, nx, ny, A, b, x, bc);
+}
+
 void orc_prolong(int dim, int nx, int ny, const double *xc, double *x)
 {
-    lvl L = mklvl(dim, nx, ny);
-    int ncx = nx / 2, Nc = ncx * (dim == 1 ? 1 : ny / 2);
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            int P = (dim == 1 ? 0 : (j / 2) * ncx) + i / 2;
-            for (int q = 0; q < L.nc; ++q)
-                x[q * L.N + j * nx + i] = x[q * L.N + j * nx + i] + xc[q * Nc + P];
-        }
+    prolong_d(dim, nx, ny, xc, x);
 }
 
-/* Galerkin coarse blocks (left half of eq:ProjectAR): the coarse block
- * coupling coarse cells I and J is the sum, over children i of I (child
- * order) and then children j of J (child order), of the fine blocks A_ij. */
 void orc_galerkin(int dim, int nx, int ny, const double *Af, double *Ac)
 {
-    lvl Lf = mklvl(dim, nx, ny);
-    int ncx = nx / 2, ncy = dim == 1 ? 1 : ny / 2;
-    lvl Lc = mklvl(dim, ncx, ncy);
-    for (int J = 0; J < ncy; ++J)
-        for (int I = 0; I < ncx; ++I) {
-            int cidx = J * ncx + I;
-            for (int cb = 0; cb < Lc.nf + 1; ++cb) {     /* coarse block D, W, E, S, N */
-                int TI = I, TJ = J;                      /* target coarse cell */
-                int exists = 1;
-                if (cb > 0) exists = nbr(dim, ncx, ncy, I, J, cb - 1, &TI, &TJ);
-                double acc[3][3] = {{0}};
-                if (exists) {
-                    int ai[4], aj[4], bi[4], bj[4];
-                    int na = children(&Lf, I, J, ai, aj), nbc = children(&Lf, TI, TJ, bi, bj);
-                    for (int a = 0; a < na; ++a)
-                        for (int c2 = 0; c2 < nbc; ++c2) {
-                            int fb = -1;                 /* fine block linking a to c2 */
-                            if (ai[a] == bi[c2] && aj[a] == bj[c2]) fb = 0;
-                            for (int f = 0; f < Lf.nf && fb < 0; ++f) {
-                                int ni, nj;
-                                if (nbr(dim, nx, ny, ai[a], aj[a], f, &ni, &nj) && ni == bi[c2] &&
-                                    nj == bj[c2])
-                                    fb = f + 1;
-                            }
-                            if (fb < 0) continue;
-                            int fidx = aj[a] * nx + ai[a];
-                            for (int r = 0; r < Lf.nc; ++r)
-                                for (int c = 0; c < Lf.nc; ++c)
-                                    acc[r][c] = acc[r][c] + Af[LA(&Lf, fb, r, c, fidx)];
-                        }
-                }
-                for (int r = 0; r < Lc.nc; ++r)
-                    for (int c = 0; c < Lc.nc; ++c) Ac[LA(&Lc, cb, r, c, cidx)] = acc[r][c];
-            }
-        }
+    galerkin_d(dim, nx, ny, Af, Ac);
 }
 
-/* Algorithm 0 with gamma = 1 on level l of the hierarchy. */
-typedef struct {
-    int NL;
-    lvl L[16];
-    double *A[16], *b[16], *x[16];
-} hier;
-
-static void mg_cycle(hier *H, const orc_params *p, int l)
-{
-    lvl *L = &H->L[l];
-    orc_sgs(L->dim, L->nx, L->ny, H->A[l], H->b[l], H->x[l], p->nu1, p->order);
-    if (l == H->NL) {
-        /* coarsest level: the "solve" is nu_coarse further SGS iterations */
-        orc_sgs(L->dim, L->nx, L->ny, H->A[l], H->b[l], H->x[l], p->nu_coarse, p->order);
-    } else {
-        orc_restrict(L->dim, L->nx, L->ny, H->A[l], H->b[l], H->x[l], H->b[l + 1]);
-        memset(H->x[l + 1], 0, sizeof(double) * (size_t)H->L[l + 1].nc * H->L[l + 1].N);
-        mg_cycle(H, p, l + 1);
-        orc_prolong(L->dim, L->nx, L->ny, H->x[l + 1], H->x[l]);
-    }
-    orc_sgs(L->dim, L->nx, L->ny, H->A[l], H->b[l], H->x[l], p->nu2, p->order);
-}
-
-static int hier_build(hier *H, int dim, int nx, int ny, int NL, const double *A0)
-{
-    if (NL < 0 || NL > 15) return ORC_EINVAL;
-    int div = 1 << NL;
-    if (nx % div || (dim == 2 && ny % div)) return ORC_EINVAL;
-    memset(H, 0, sizeof *H);
-    H->NL = NL;
-    for (int l = 0; l <= NL; ++l) {
-        H->L[l] = mklvl(dim, nx >> l, dim == 1 ? 1 : ny >> l);
-        size_t N = (size_t)H->L[l].N, nc = (size_t)H->L[l].nc, nb = (size_t)H->L[l].nf + 1;
-        H->A[l] = (double *)malloc(sizeof(double) * nb * nc * nc * N);
-        H->b[l] = (double *)calloc(nc * N, sizeof(double));
-        H->x[l] = (double *)calloc(nc * N, sizeof(double));
-        if (!H->A[l] || !H->b[l] || !H->x[l]) return ORC_EINVAL;
-        if (l == 0) memcpy(H->A[0], A0, sizeof(double) * nb * nc * nc * N);
-        else orc_galerkin(dim, H->L[l - 1].nx, H->L[l - 1].ny, H->A[l - 1], H->A[l]);
-    }
-    return ORC_OK;
-}
-
-static void hier_free(hier *H)
-{
-    for (int l = 0; l <= H->NL; ++l) { free(H->A[l]); free(H->b[l]); free(H->x[l]); }
-}
-
+/* V-cycles in FP64, or in FP32 when p->inner_fp32 (A0, b0 and x rounded to
+ * float on entry, x returned in double). */
 int orc_vcycles(int dim, int nx, int ny, const orc_params *p, const double *A0,
                 const double *b0, double *x, int n_cycles)
 {
-    hier H;
-    if (hier_build(&H, dim, nx, ny, p->n_levels, A0)) { hier_free(&H); return ORC_EINVAL; }
-    size_t n = (size_t)H.L[0].nc * H.L[0].N;
-    memcpy(H.b[0], b0, sizeof(double) * n);
-    memcpy(H.x[0], x, sizeof(double) * n);
-    for (int c = 0; c < n_cycles; ++c) mg_cycle(&H, p, 0);
-    memcpy(x, H.x[0], sizeof(double) * n);
-    hier_free(&H);
-    return ORC_OK;
+    if (p->inner_fp32) return vcycles_f(dim, nx, ny, p, A0, b0, x, n_cycles);
+    return vcycles_d(dim, nx, ny, p, A0, b0, x, n_cycles);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -814,12 +631,7 @@ int orc_newton_solve(const orc_grid *gr, const orc_side bc[4], const orc_params 
         if (res < tol) { status = ORC_OK; break; }
         if (res > 1e8 * res0) { status = ORC_EDIVERGED; break; }
         double *x = (double *)calloc(nv, sizeof(double));
-        hier H;
-        if (hier_build(&H, dim, nx, ny, p->n_levels, A)) { hier_free(&H); free(x); status = ORC_EINVAL; break; }
-        memcpy(H.b[0], b, sizeof(double) * nv);
-        for (int m = 0; m < p->n_mg; ++m) mg_cycle(&H, p, 0);
-        memcpy(x, H.x[0], sizeof(double) * nv);
-        hier_free(&H);
+        if (orc_vcycles(dim, nx, ny, p, A, b, x, p->n_mg)) { free(x); status = ORC_EINVAL; break; }
         relaxed_update(&P, U, x);
         free(x);
         orc_threshold(gr, p, U);

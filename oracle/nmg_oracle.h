@@ -49,6 +49,7 @@ typedef struct {
     int blu_sweeps, max_newton, order;
     int dry_pin;                    /* hold the momentum of exactly dry cells at 0 */
     double pos_theta;               /* positivity limit of the per-cell relaxation (0 = off) */
+    int inner_fp32;                 /* V-cycles in FP32 (Newton residual and update in FP64) */
 } orc_params;
 
 typedef struct {
@@ -89,7 +90,8 @@ void orc_restrict(int dim, int nx, int ny, const double *A, const double *b,
                   const double *x, double *bc);
 void orc_prolong(int dim, int nx, int ny, const double *xc, double *x);
 /* n_cycles V-cycles on the hierarchy built by Galerkin from A0; x in/out.
- * If Ah != NULL it receives all levels' matrices (level after level). */
+ * With p->inner_fp32 the hierarchy and the cycles are FP32 (A0, b0, x
+ * rounded on entry, x widened on return). */
 int orc_vcycles(int dim, int nx, int ny, const orc_params *p, const double *A0,
                 const double *b0, double *x, int n_cycles);
 

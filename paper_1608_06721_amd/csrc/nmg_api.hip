@@ -29,7 +29,7 @@ enum ColorState {
 
 struct Level {
     LevelGeom G;
-    double *A = nullptr, *b = nullptr, *x = nullptr;
+    void *A = nullptr, *b = nullptr, *x = nullptr;   // double, or float (FP32 inner)
     int st[2] = {ST_ZERO, ST_ZERO};
     int last = -1;      // colour of the last half sweep if nothing changed since, else -1
 };
@@ -43,6 +43,7 @@ struct nmg_ctx {
     hipStream_t stream = nullptr;
     Phys P;
     int dim = 0, nc = 0, nb = 0, ne = 0, NL = 0;
+    bool f32 = false;                 // FP32 inner V-cycle
     Level L[16];
     unsigned char *iso = nullptr;
     double *partial = nullptr;    // per-block partial sums
@@ -102,6 +103,7 @@ int check_params(const nmg_grid *g, const nmg_bc *bc, const nmg_params *p, std::
         msg = "bad scalar parameter";
         return NMG_EINVAL;
     }
+    if (p->inner_fp32 != 0 && p->inner_fp32 != 1) { msg = "inner_fp32 must be 0 or 1"; return NMG_EINVAL; }
     if (p->nu1 < 0 || p->nu2 < 0 || p->nu_coarse < 0 || p->n_mg < 0 || p->blu_sweeps < 0 ||
         p->max_newton < 0) {
         msg = "negative iteration count";
@@ -147,7 +149,8 @@ int halfsweep(nmg_ctx *c, int l, int color)
     const int k = c->nrec;
     const bool rec = c->timing && l == 0 && mode == MODE_NORMAL && k < (int)c->ev.size();
     if (rec) HIPCHK(c, hipEventRecord(c->ev[k].first, c->stream));
-    HIPCHK(c, launch_sgs_half(c->dim, mode, Lv.G, Lv.A, Lv.b, Lv.x, color, Lc.G, Lc.x, c->stream));
+    HIPCHK(c, launch_sgs_half(c->dim, c->f32, mode, Lv.G, Lv.A, Lv.b, Lv.x, color, Lc.G, Lc.x,
+                              c->stream));
     if (rec) {
         HIPCHK(c, hipEventRecord(c->ev[k].second, c->stream));
         long n = 0;
@@ -185,7 +188,7 @@ int materialize(nmg_ctx *c, int l)
         if (c->recording)
             c->rec.push_back(CoarseOp{COP_FIX, l, color, op});
         else
-            HIPCHK(c, launch_fix_color(c->dim, op, Lv.G, Lv.x, color, Lc.G, Lc.x, c->stream));
+            HIPCHK(c, launch_fix_color(c->dim, c->f32, op, Lv.G, Lv.x, color, Lc.G, Lc.x, c->stream));
         Lv.st[color] = ST_VALID;
         Lv.last = -1;
     }
@@ -206,7 +209,8 @@ int cycle(nmg_ctx *c, int l)
     if (l == c->lc && !c->recording) {
         // the whole sub-cycle from level lc down runs in one workgroup; it
         // leaves level lc's correction materialized
-        HIPCHK(c, launch_coarse_cycle(c->dim, c->d_ops, (int)c->rec.size(), c->d_lv, c->stream));
+        HIPCHK(c, launch_coarse_cycle(c->dim, c->f32, c->d_ops, (int)c->rec.size(), c->d_lv,
+                                      c->stream));
         c->L[l].st[0] = c->L[l].st[1] = ST_VALID;
         c->L[l].last = -1;
         return NMG_OK;
@@ -221,7 +225,7 @@ int cycle(nmg_ctx *c, int l)
         if (c->recording)
             c->rec.push_back(CoarseOp{COP_RESTRICT, l, 0, 0});
         else
-            HIPCHK(c, launch_restrict(c->dim, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b, c->stream));
+            HIPCHK(c, launch_restrict(c->dim, c->f32, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b, c->stream));
         set_zero(c, l + 1);
         if ((rc = cycle(c, l + 1))) return rc;
         if ((rc = materialize(c, l + 1))) return rc;
@@ -235,8 +239,8 @@ int cycle(nmg_ctx *c, int l)
 int build_coarse(nmg_ctx *c)
 {
     for (int l = 1; l <= c->NL; ++l)
-        HIPCHK(c, launch_galerkin(c->dim, c->L[l - 1].G, c->L[l - 1].A, c->L[l].G, c->L[l].A,
-                                  c->stream));
+        HIPCHK(c, launch_galerkin(c->dim, c->f32, c->L[l - 1].G, c->L[l - 1].A, c->L[l].G,
+                                  c->L[l].A, c->stream));
     for (int l = 0; l <= c->NL; ++l) set_zero(c, l);
     return NMG_OK;
 }
@@ -292,7 +296,8 @@ int assemble(nmg_ctx *c, const double *z, const double *U, double *R_out, double
 {
     Level &L0 = c->L[0];
     HIPCHK(c, launch_isolated(c->P, z, U, c->iso, c->stream));
-    HIPCHK(c, launch_assemble(c->P, L0.G, z, U, c->iso, L0.A, L0.b, R_out, c->partial, c->stream));
+    HIPCHK(c, launch_assemble(c->P, L0.G, z, U, c->iso, L0.A, L0.b, c->f32, R_out, c->partial,
+                              c->stream));
     int rc = build_coarse(c);
     if (rc) return rc;
     if (res) return reduce_to_host(c, nblocks(cells(L0.G)), res);
@@ -366,27 +371,29 @@ int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
         P.bc[f].hast = !std::isnan(s.ut);
     }
 
-    size_t total = 0;
+    c->f32 = params->inner_fp32 != 0;
+    const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
+    size_t total = 0;   // elements
     for (int l = 0; l <= c->NL; ++l) {
         int nx = grid->nx >> l, ny = grid->dim == 1 ? 1 : grid->ny >> l;
         c->L[l].G = make_geom(nx, ny);
         total += (size_t)2 * c->ne * c->L[l].G.planeP + (size_t)2 * 2 * c->nc * c->L[l].G.plane;
     }
-    double *pool = nullptr;
-    if (hipMalloc(&pool, total * sizeof(double)) != hipSuccess) {
+    char *pool = nullptr;
+    if (hipMalloc(&pool, total * esz) != hipSuccess) {
         delete c;
         return NMG_ENOMEM;
     }
     size_t off = 0;
     for (int l = 0; l <= c->NL; ++l) {
         Level &Lv = c->L[l];
-        Lv.A = pool + off; off += (size_t)2 * c->ne * Lv.G.planeP;
-        Lv.b = pool + off; off += (size_t)2 * c->nc * Lv.G.plane;
-        Lv.x = pool + off; off += (size_t)2 * c->nc * Lv.G.plane;
+        Lv.A = pool + off * esz; off += (size_t)2 * c->ne * Lv.G.planeP;
+        Lv.b = pool + off * esz; off += (size_t)2 * c->nc * Lv.G.plane;
+        Lv.x = pool + off * esz; off += (size_t)2 * c->nc * Lv.G.plane;
     }
     long N = cells(c->L[0].G);
     int nparts = nblocks(N);
-    bool ok = hipMemsetAsync(pool, 0, total * sizeof(double), c->stream) == hipSuccess &&
+    bool ok = hipMemsetAsync(pool, 0, total * esz, c->stream) == hipSuccess &&
               hipMalloc(&c->iso, N) == hipSuccess &&
               hipMalloc(&c->partial, sizeof(double) * (nparts + 1)) == hipSuccess &&
               hipMalloc(&c->scal, sizeof(double) * 4) == hipSuccess &&
@@ -448,7 +455,7 @@ int nmg_mg_vcycle(nmg_ctx *c, double *dU, int n_cycles)
     if (!c) return NMG_EINVAL;
     if (!dU || n_cycles < 0) return fail(c, NMG_EINVAL, "null dU or negative cycle count");
     Level &L0 = c->L[0];
-    HIPCHK(c, launch_vec_to_split(c->nc, L0.G, dU, L0.x, c->stream));
+    HIPCHK(c, launch_vec_to_split(c->nc, c->f32, L0.G, dU, L0.x, c->stream));
     L0.st[0] = L0.st[1] = ST_VALID;
     L0.last = -1;
     for (int k = 0; k < n_cycles; ++k) {
@@ -457,7 +464,7 @@ int nmg_mg_vcycle(nmg_ctx *c, double *dU, int n_cycles)
     }
     int rc = materialize(c, 0);
     if (rc) return rc;
-    HIPCHK(c, launch_vec_from_split(c->nc, L0.G, L0.x, dU, c->stream));
+    HIPCHK(c, launch_vec_from_split(c->nc, c->f32, L0.G, L0.x, dU, c->stream));
     return NMG_OK;
 }
 
@@ -467,12 +474,12 @@ int nmg_sgs(nmg_ctx *c, int level, double *dU, int iters)
     if (!dU || iters < 0 || level < 0 || level > c->NL)
         return fail(c, NMG_EINVAL, "bad level, dU or iteration count");
     Level &Lv = c->L[level];
-    HIPCHK(c, launch_vec_to_split(c->nc, Lv.G, dU, Lv.x, c->stream));
+    HIPCHK(c, launch_vec_to_split(c->nc, c->f32, Lv.G, dU, Lv.x, c->stream));
     Lv.st[0] = Lv.st[1] = ST_VALID;
     Lv.last = -1;
     int rc = smooth(c, level, iters);
     if (rc) return rc;
-    HIPCHK(c, launch_vec_from_split(c->nc, Lv.G, Lv.x, dU, c->stream));
+    HIPCHK(c, launch_vec_from_split(c->nc, c->f32, Lv.G, Lv.x, dU, c->stream));
     return NMG_OK;
 }
 
@@ -490,8 +497,8 @@ int nmg_load_system(nmg_ctx *c, const double *A0, const double *b0)
     if (!c) return NMG_EINVAL;
     if (!A0 || !b0) return fail(c, NMG_EINVAL, "null A0 or b0");
     Level &L0 = c->L[0];
-    HIPCHK(c, launch_mat_to_split(c->ne, L0.G, A0, L0.A, c->stream));
-    HIPCHK(c, launch_vec_to_split(c->nc, L0.G, b0, L0.b, c->stream));
+    HIPCHK(c, launch_mat_to_split(c->ne, c->f32, L0.G, A0, L0.A, c->stream));
+    HIPCHK(c, launch_vec_to_split(c->nc, c->f32, L0.G, b0, L0.b, c->stream));
     return build_coarse(c);
 }
 
@@ -500,8 +507,8 @@ int nmg_get_system(nmg_ctx *c, int level, double *A, double *b)
     if (!c) return NMG_EINVAL;
     if (level < 0 || level > c->NL) return fail(c, NMG_EINVAL, "level out of range");
     Level &Lv = c->L[level];
-    if (A) HIPCHK(c, launch_mat_from_split(c->ne, Lv.G, Lv.A, A, c->stream));
-    if (b) HIPCHK(c, launch_vec_from_split(c->nc, Lv.G, Lv.b, b, c->stream));
+    if (A) HIPCHK(c, launch_mat_from_split(c->ne, c->f32, Lv.G, Lv.A, A, c->stream));
+    if (b) HIPCHK(c, launch_vec_from_split(c->nc, c->f32, Lv.G, Lv.b, b, c->stream));
     return NMG_OK;
 }
 
@@ -534,7 +541,7 @@ int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_
         for (int m = 0; m < p.n_mg; ++m)
             if ((rc = cycle(c, 0))) return rc;
         if ((rc = materialize(c, 0))) return rc;
-        HIPCHK(c, launch_update(c->P, L0.G, L0.x, U, c->stream));
+        HIPCHK(c, launch_update(c->P, L0.G, L0.x, c->f32, U, c->stream));
     }
     if (status == NMG_NOT_CONVERGED) {
         HIPCHK(c, launch_residual(c->P, z, U, nullptr, c->partial, c->stream));

@@ -68,10 +68,12 @@ constexpr int kCoarseBlock = 512;     // one workgroup runs the coarse part of a
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarseOps = 2048;  // LDS capacity of the coarse-cycle kernel's op list
 
-// Device-side description of one level (for the coarse-cycle kernel).
+// Device-side description of one level (for the coarse-cycle kernel); the
+// arrays hold the hierarchy's scalar type (double, or float for the FP32
+// inner V-cycle).
 struct LevelDev {
     LevelGeom G;
-    double *A, *b, *x;
+    void *A, *b, *x;
 };
 
 // One operation of the recorded coarse part of a V-cycle.
@@ -89,41 +91,43 @@ inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
 hipError_t launch_isolated(const Phys &P, const double *z, const double *U, unsigned char *iso,
                            hipStream_t s);
 hipError_t launch_assemble(const Phys &P, const LevelGeom &G, const double *z, const double *U,
-                           const unsigned char *iso, double *A, double *b, double *R_out,
+                           const unsigned char *iso, void *A, void *b, bool f32, double *R_out,
                            double *partial, hipStream_t s);
 hipError_t launch_residual(const Phys &P, const double *z, const double *U, double *R_out,
                            double *partial, hipStream_t s);
 hipError_t launch_reduce(const double *partial, int n, double *out, hipStream_t s);
 hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipStream_t s);
 hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, hipStream_t s);
-hipError_t launch_update(const Phys &P, const LevelGeom &G, const double *x, double *U,
+hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool f32, double *U,
                          hipStream_t s);
 hipError_t launch_threshold(const Phys &P, double *U, hipStream_t s);
 
-hipError_t launch_sgs_half(int dim, int mode, const LevelGeom &G, const double *A, const double *b,
-                           double *x, int color, const LevelGeom &Gc, const double *xc,
+// Linear multigrid launchers; f32 selects the float hierarchy.
+hipError_t launch_sgs_half(int dim, bool f32, int mode, const LevelGeom &G, const void *A,
+                           const void *b, void *x, int color, const LevelGeom &Gc, const void *xc,
                            hipStream_t s);
-hipError_t launch_restrict(int dim, const LevelGeom &G, const double *A, const double *b,
-                           const double *x, const LevelGeom &Gc, double *bc, hipStream_t s);
-hipError_t launch_galerkin(int dim, const LevelGeom &Gf, const double *Af, const LevelGeom &Gc,
-                           double *Ac, hipStream_t s);
+hipError_t launch_restrict(int dim, bool f32, const LevelGeom &G, const void *A, const void *b,
+                           const void *x, const LevelGeom &Gc, void *bc, hipStream_t s);
+hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *Af,
+                           const LevelGeom &Gc, void *Ac, hipStream_t s);
 // Materialize one colour of x: op 0 = set zero, 1 = add the parent's
 // coarse value, 2 = set to the parent's coarse value.
-hipError_t launch_fix_color(int dim, int op, const LevelGeom &G, double *x, int color,
-                            const LevelGeom &Gc, const double *xc, hipStream_t s);
+hipError_t launch_fix_color(int dim, bool f32, int op, const LevelGeom &G, void *x, int color,
+                            const LevelGeom &Gc, const void *xc, hipStream_t s);
 
 // The recorded coarse part of a V-cycle, executed by one workgroup.
-hipError_t launch_coarse_cycle(int dim, const CoarseOp *ops, int nops, const LevelDev *lv,
-                               hipStream_t s);
+hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
+                               const LevelDev *lv, hipStream_t s);
 
-// Layout conversions between the public layouts and the colour-split one.
-hipError_t launch_vec_to_split(int nc, const LevelGeom &G, const double *v, double *split,
+// Layout conversions between the public FP64 layouts and the colour-split
+// hierarchy storage.
+hipError_t launch_vec_to_split(int nc, bool f32, const LevelGeom &G, const double *v, void *split,
                                hipStream_t s);
-hipError_t launch_vec_from_split(int nc, const LevelGeom &G, const double *split, double *v,
-                                 hipStream_t s);
-hipError_t launch_mat_to_split(int ne, const LevelGeom &G, const double *A, double *split,
+hipError_t launch_vec_from_split(int nc, bool f32, const LevelGeom &G, const void *split,
+                                 double *v, hipStream_t s);
+hipError_t launch_mat_to_split(int ne, bool f32, const LevelGeom &G, const double *A, void *split,
                                hipStream_t s);
-hipError_t launch_mat_from_split(int ne, const LevelGeom &G, const double *split, double *A,
-                                 hipStream_t s);
+hipError_t launch_mat_from_split(int ne, bool f32, const LevelGeom &G, const void *split,
+                                 double *A, hipStream_t s);
 
 }  // namespace nmg

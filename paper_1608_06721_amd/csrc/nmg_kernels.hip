@@ -207,28 +207,29 @@ __device__ __forceinline__ void load_state(const Phys &P, const double *U, long 
     for (int k = 0; k < NC; ++k) q[k] = U[k * N + idx];
 }
 
-// Solve the NC x NC block system D x = r: adjugate (cofactors along row 0)
-// times the reciprocal determinant; x = 0 when that reciprocal is not finite.
-template <int NC>
-__device__ __forceinline__ void solve_block(const double *D, const double *r, double *x)
+// Solve the NC x NC block system D x = r in precision T: adjugate (cofactors
+// along row 0) times the reciprocal determinant; x = 0 when that reciprocal
+// is not finite.
+template <class T, int NC>
+__device__ __forceinline__ void solve_block(const T *D, const T *r, T *x)
 {
     if (NC == 2) {
-        double det = D[0] * D[3] - D[1] * D[2];
-        double idet = 1.0 / det;
-        if (!finite(idet)) { x[0] = 0.0; x[1] = 0.0; return; }
+        T det = D[0] * D[3] - D[1] * D[2];
+        T idet = T(1) / det;
+        if (!__builtin_isfinite(idet)) { x[0] = T(0); x[1] = T(0); return; }
         x[0] = (D[3] * r[0] - D[1] * r[1]) * idet;
         x[1] = (D[0] * r[1] - D[2] * r[0]) * idet;
         return;
     }
-    double d00 = D[0], d01 = D[1], d02 = D[2];
-    double d10 = D[3], d11 = D[4], d12 = D[5];
-    double d20 = D[6], d21 = D[7], d22 = D[8];
-    double C00 = d11 * d22 - d12 * d21, C01 = d12 * d20 - d10 * d22, C02 = d10 * d21 - d11 * d20;
-    double C10 = d02 * d21 - d01 * d22, C11 = d00 * d22 - d02 * d20, C12 = d01 * d20 - d00 * d21;
-    double C20 = d01 * d12 - d02 * d11, C21 = d02 * d10 - d00 * d12, C22 = d00 * d11 - d01 * d10;
-    double det = d00 * C00 + d01 * C01 + d02 * C02;
-    double idet = 1.0 / det;
-    if (!finite(idet)) { x[0] = 0.0; x[1] = 0.0; x[2] = 0.0; return; }
+    T d00 = D[0], d01 = D[1], d02 = D[2];
+    T d10 = D[3], d11 = D[4], d12 = D[5];
+    T d20 = D[6], d21 = D[7], d22 = D[8];
+    T C00 = d11 * d22 - d12 * d21, C01 = d12 * d20 - d10 * d22, C02 = d10 * d21 - d11 * d20;
+    T C10 = d02 * d21 - d01 * d22, C11 = d00 * d22 - d02 * d20, C12 = d01 * d20 - d00 * d21;
+    T C20 = d01 * d12 - d02 * d11, C21 = d02 * d10 - d00 * d12, C22 = d00 * d11 - d01 * d10;
+    T det = d00 * C00 + d01 * C01 + d02 * C02;
+    T idet = T(1) / det;
+    if (!__builtin_isfinite(idet)) { x[0] = T(0); x[1] = T(0); x[2] = T(0); return; }
     x[0] = (C00 * r[0] + C10 * r[1] + C20 * r[2]) * idet;
     x[1] = (C01 * r[0] + C11 * r[1] + C21 * r[2]) * idet;
     x[2] = (C02 * r[0] + C12 * r[1] + C22 * r[2]) * idet;
@@ -387,25 +388,27 @@ __global__ void __launch_bounds__(kBlock) k_isolated(Phys P, const double *__res
 // applying the pinning rules: an isolated cell gets a zero row, a dry cell
 // under the dry-cell pin zero momentum rows, and the column of an isolated
 // neighbour is zero.
-template <int NC>
+template <int NC, class T>
 struct OffStore {
-    double *Ac;            // this cell's entry 0 in the colour-split matrix
+    T *Ac;                 // this cell's entry 0 in the colour-split matrix
     bool me_iso, dryp;
     bool nb_iso[4];
     __device__ void operator()(int f, int r, int c, double v) const
     {
         if (me_iso || nb_iso[f] || (dryp && r > 0)) v = 0.0;
-        Ac[(((f + 1) * NC + r) * NC + c) * kTile] = v;
+        Ac[(((f + 1) * NC + r) * NC + c) * kTile] = T(v);
     }
 };
 
-template <int NC>
+// The blocks and b are computed in FP64 and stored in the hierarchy's
+// precision T (rounded to nearest when T is float).
+template <int NC, class T>
 __global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
                                                      const double *__restrict__ z,
                                                      const double *__restrict__ U,
                                                      const unsigned char *__restrict__ iso,
-                                                     double *__restrict__ A,
-                                                     double *__restrict__ b,
+                                                     T *__restrict__ A,
+                                                     T *__restrict__ b,
                                                      double *__restrict__ R_out,
                                                      double *__restrict__ partial)
 {
@@ -418,7 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
         int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
         const int color = (i + j) & 1;
         const long slot = (long)j * G.W + (i >> 1);
-        OffStore<NC> st;
+        OffStore<NC, T> st;
         st.Ac = A + mat_off(G, NE, color, slot);
         st.me_iso = iso[idx] != 0;
         st.dryp = !st.me_iso && P.dry_pin && U[idx] == 0.0;
@@ -449,12 +452,12 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
                 Rc[r] = 0.0;
             }
         }
-        double *bc = b + (long)color * NC * G.plane + slot;
+        T *bc = b + (long)color * NC * G.plane + slot;
 #pragma unroll
         for (int r = 0; r < NC; ++r) {
-            bc[r * G.plane] = st.me_iso ? 0.0 : -Rc[r];
+            bc[r * G.plane] = T(st.me_iso ? 0.0 : -Rc[r]);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) st.Ac[(r * NC + c) * kTile] = D[r][c];
+            for (int c = 0; c < NC; ++c) st.Ac[(r * NC + c) * kTile] = T(D[r][c]);
         }
     }
     double s = block_sum(nrm);
@@ -557,7 +560,7 @@ __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__res
     for (int r = 0; r < NC; ++r)
 #pragma unroll
         for (int c = 0; c < NC; ++c) M[r * NC + c] = D[r][c];
-    solve_block<NC>(M, Rc, d);
+    solve_block<double, NC>(M, Rc, d);
     double q[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) q[c] = U[c * N + idx] - d[c];
@@ -570,9 +573,9 @@ __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__res
 }
 
 // Relaxed update U += tau_i dU (positivity-limited tau_i) and dry threshold.
-template <int NC>
+template <int NC, class T>
 __global__ void __launch_bounds__(kBlock) k_update(Phys P, LevelGeom G,
-                                                   const double *__restrict__ x,
+                                                   const T *__restrict__ x,
                                                    double *__restrict__ U)
 {
     long idx = (long)blockIdx.x * kBlock + threadIdx.x;
@@ -580,11 +583,11 @@ __global__ void __launch_bounds__(kBlock) k_update(Phys P, LevelGeom G,
     if (idx >= N) return;
     int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
     const int color = (i + j) & 1;
-    const double *xs = x + (long)color * NC * G.plane + (long)j * G.W + (i >> 1);
+    const T *xs = x + (long)color * NC * G.plane + (long)j * G.W + (i >> 1);
     double dq[NC], q[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        dq[c] = xs[c * G.plane];
+        dq[c] = double(xs[c * G.plane]);
         q[c] = U[c * N + idx];
     }
     const double th = P.pos_theta, tau = P.tau;
@@ -617,23 +620,23 @@ __global__ void __launch_bounds__(kBlock) k_threshold(Phys P, double *__restrict
 // Linear multigrid kernels on the colour-split layout.
 
 // Value of the other-colour neighbour at fine cell (ni, nj) under `mode`.
-template <int NC, int MODE>
-__device__ __forceinline__ void read_other(const LevelGeom &G, const double *xo, int ni, int nj,
-                                           const LevelGeom &Gc, const double *xc, double *v)
+template <class T, int NC, int MODE>
+__device__ __forceinline__ void read_other(const LevelGeom &G, const T *xo, int ni, int nj,
+                                           const LevelGeom &Gc, const T *xc, T *v)
 {
     if (MODE == MODE_ZERO) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) v[c] = 0.0;
+        for (int c = 0; c < NC; ++c) v[c] = T(0);
         return;
     }
-    double base[NC];
+    T base[NC];
     if (MODE == MODE_NORMAL || MODE == MODE_PROLONG) {
-        const double *p = xo + (long)nj * G.W + (ni >> 1);
+        const T *p = xo + (long)nj * G.W + (ni >> 1);
 #pragma unroll
         for (int c = 0; c < NC; ++c) base[c] = p[c * G.plane];
     } else {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) base[c] = 0.0;
+        for (int c = 0; c < NC; ++c) base[c] = T(0);
     }
     if (MODE == MODE_NORMAL) {
 #pragma unroll
@@ -642,7 +645,7 @@ __device__ __forceinline__ void read_other(const LevelGeom &G, const double *xo,
     }
     int I = ni >> 1, J = nj >> 1;
     int cc = (I + J) & 1;
-    const double *p = xc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
+    const T *p = xc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) v[c] = base[c] + p[c * Gc.plane];
 }
@@ -652,11 +655,11 @@ __device__ __forceinline__ void read_other(const LevelGeom &G, const double *xo,
 // components.  One thread per cell of the colour, coalesced along x.  All
 // loads of a cell (its block row, b_i and the neighbours' x) are issued
 // before any arithmetic, so each wave keeps ~50 independent loads in flight.
-template <int NC, int MODE>
-__device__ __forceinline__ void sgs_cell(const LevelGeom &G, const double *__restrict__ A,
-                                         const double *__restrict__ b, double *__restrict__ x,
+template <class T, int NC, int MODE>
+__device__ __forceinline__ void sgs_cell(const LevelGeom &G, const T *__restrict__ A,
+                                         const T *__restrict__ b, T *__restrict__ x,
                                          int color, const LevelGeom &Gc,
-                                         const double *__restrict__ xc, long t)
+                                         const T *__restrict__ xc, long t)
 {
     constexpr int NF = (NC == 2) ? 2 : 4;
     constexpr int NN = NC * NC;
@@ -665,9 +668,9 @@ __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const double *__res
     const int i = 2 * k + ((j + color) & 1);
     if (i >= G.nx) return;
     const int oc = color ^ 1;
-    const double *Am = A + mat_off(G, NE, color, t);
-    const double *bm = b + (long)color * NC * G.plane + t;
-    const double *xo = x + (long)oc * NC * G.plane;
+    const T *Am = A + mat_off(G, NE, color, t);
+    const T *bm = b + (long)color * NC * G.plane + t;
+    const T *xo = x + (long)oc * NC * G.plane;
 
     bool ok[NF];
     int ni[NF], nj[NF];
@@ -680,7 +683,7 @@ __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const double *__res
         else if (f == FS) { nj[f] = j - 1; ok[f] = j > 0; }
         else { nj[f] = j + 1; ok[f] = j + 1 < G.ny; }
     }
-    double a[NE], bv[NC], v[NF][NC];
+    T a[NE], bv[NC], v[NF][NC];
 #pragma unroll
     for (int e = 0; e < NN; ++e) a[e] = Am[e * kTile];
 #pragma unroll
@@ -691,16 +694,16 @@ __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const double *__res
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             if (ok[f]) {
-                read_other<NC, MODE>(G, xo, ni[f], nj[f], Gc, xc, v[f]);
+                read_other<T, NC, MODE>(G, xo, ni[f], nj[f], Gc, xc, v[f]);
             } else {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) v[f][c] = 0.0;
+                for (int c = 0; c < NC; ++c) v[f][c] = T(0);
             }
         }
     }
-    double acc[NC];
+    T acc[NC];
 #pragma unroll
-    for (int r = 0; r < NC; ++r) acc[r] = 0.0;
+    for (int r = 0; r < NC; ++r) acc[r] = T(0);
     if (MODE != MODE_ZERO) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -712,46 +715,46 @@ __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const double *__res
                     acc[r] = acc[r] + a[((f + 1) * NC + r) * NC + c] * v[f][c];
         }
     }
-    double rhs[NC], xi[NC];
+    T rhs[NC], xi[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) rhs[r] = bv[r] - acc[r];
-    solve_block<NC>(a, rhs, xi);
-    double *xm = x + (long)color * NC * G.plane + t;
+    solve_block<T, NC>(a, rhs, xi);
+    T *xm = x + (long)color * NC * G.plane + t;
 #pragma unroll
     for (int r = 0; r < NC; ++r) xm[r * G.plane] = xi[r];
 }
 
-template <int NC, int MODE>
-__global__ void __launch_bounds__(kBlock) k_sgs_half(LevelGeom G, const double *__restrict__ A,
-                                                     const double *__restrict__ b,
-                                                     double *__restrict__ x, int color,
-                                                     LevelGeom Gc, const double *__restrict__ xc)
+template <class T, int NC, int MODE>
+__global__ void __launch_bounds__(kBlock) k_sgs_half(LevelGeom G, const T *__restrict__ A,
+                                                     const T *__restrict__ b,
+                                                     T *__restrict__ x, int color,
+                                                     LevelGeom Gc, const T *__restrict__ xc)
 {
     long t = (long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= G.plane) return;
-    sgs_cell<NC, MODE>(G, A, b, x, color, Gc, xc, t);
+    sgs_cell<T, NC, MODE>(G, A, b, x, color, Gc, xc, t);
 }
 
 // Linear residual of fine cell (i, j): b - (D x_i + sum_nbr A x_nbr).
-template <int NC>
-__device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const double *A,
-                                                  const double *b, const double *x, int i, int j,
-                                                  double *r)
+template <class T, int NC>
+__device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const T *A,
+                                                  const T *b, const T *x, int i, int j,
+                                                  T *r)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const int NE = (NF + 1) * NC * NC;
     const int color = (i + j) & 1;
     const long slot = (long)j * G.W + (i >> 1);
-    const double *Am = A + mat_off(G, NE, color, slot);
-    const double *bm = b + (long)color * NC * G.plane + slot;
-    const double *xm = x + (long)color * NC * G.plane + slot;
-    const double *xo = x + (long)(color ^ 1) * NC * G.plane;
-    double xi[NC], acc[NC];
+    const T *Am = A + mat_off(G, NE, color, slot);
+    const T *bm = b + (long)color * NC * G.plane + slot;
+    const T *xm = x + (long)color * NC * G.plane + slot;
+    const T *xo = x + (long)(color ^ 1) * NC * G.plane;
+    T xi[NC], acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) xi[c] = xm[c * G.plane];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-        acc[q] = 0.0;
+        acc[q] = T(0);
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[q] = acc[q] + Am[(q * NC + c) * kTile] * xi[c];
     }
@@ -764,8 +767,8 @@ __device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const doub
         else if (f == FS) { nj = j - 1; ok = j > 0; }
         else { nj = j + 1; ok = j + 1 < G.ny; }
         if (!ok) continue;
-        const double *p = xo + (long)nj * G.W + (ni >> 1);
-        double v[NC];
+        const T *p = xo + (long)nj * G.W + (ni >> 1);
+        T v[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c] = p[c * G.plane];
 #pragma unroll
@@ -780,48 +783,48 @@ __device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const doub
 
 // Restriction (eq:ProjectAR, right): coarse right-hand side = sum over the
 // children (SW, SE, NW, NE; 1D: left, right) of their linear residuals.
-template <int NC>
-__device__ __forceinline__ void restrict_cell(const LevelGeom &G, const double *__restrict__ A,
-                                              const double *__restrict__ b,
-                                              const double *__restrict__ x, const LevelGeom &Gc,
-                                              double *__restrict__ bc, long t)
+template <class T, int NC>
+__device__ __forceinline__ void restrict_cell(const LevelGeom &G, const T *__restrict__ A,
+                                              const T *__restrict__ b,
+                                              const T *__restrict__ x, const LevelGeom &Gc,
+                                              T *__restrict__ bc, long t)
 {
     const int I = (int)(t % Gc.nx), J = (int)(t / Gc.nx);
     const int nch = (NC == 2) ? 2 : 4;
-    double acc[NC];
+    T acc[NC];
 #pragma unroll
-    for (int q = 0; q < NC; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NC; ++q) acc[q] = T(0);
 #pragma unroll
     for (int ch = 0; ch < nch; ++ch) {
         int i = 2 * I + (ch & 1);
         int j = (NC == 2) ? 0 : 2 * J + (ch >> 1);
-        double r[NC];
-        lin_residual_cell<NC>(G, A, b, x, i, j, r);
+        T r[NC];
+        lin_residual_cell<T, NC>(G, A, b, x, i, j, r);
 #pragma unroll
         for (int q = 0; q < NC; ++q) acc[q] = acc[q] + r[q];
     }
     const int cc = (I + J) & 1;
-    double *bm = bc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
+    T *bm = bc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
 #pragma unroll
     for (int q = 0; q < NC; ++q) bm[q * Gc.plane] = acc[q];
 }
 
-template <int NC>
-__global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const double *__restrict__ A,
-                                                     const double *__restrict__ b,
-                                                     const double *__restrict__ x, LevelGeom Gc,
-                                                     double *__restrict__ bc)
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const T *__restrict__ A,
+                                                     const T *__restrict__ b,
+                                                     const T *__restrict__ x, LevelGeom Gc,
+                                                     T *__restrict__ bc)
 {
     long t = (long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (long)Gc.nx * Gc.ny) return;
-    restrict_cell<NC>(G, A, b, x, Gc, bc, t);
+    restrict_cell<T, NC>(G, A, b, x, Gc, bc, t);
 }
 
 // Galerkin coarse blocks (eq:ProjectAR, left) with the child-pair order of
 // the definition: children of I (SW, SE, NW, NE), then children of J.
-template <int NC>
-__global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const double *__restrict__ Af,
-                                                     LevelGeom Gc, double *__restrict__ Ac)
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const T *__restrict__ Af,
+                                                     LevelGeom Gc, T *__restrict__ Ac)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const int NE = (NF + 1) * NC * NC;
@@ -830,23 +833,23 @@ __global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const double 
     if (t >= (long)Gc.nx * Gc.ny) return;
     const int I = (int)(t % Gc.nx), J = (int)(t / Gc.nx);
     // child (ci, cj) block blk entry e -> pointer
-    auto ent = [&](int ci, int cj, int blk, int e) -> double {
+    auto ent = [&](int ci, int cj, int blk, int e) -> T {
         int col = (ci + cj) & 1;
         return Af[mat_off(Gf, NE, col, (long)cj * Gf.W + (ci >> 1)) + (blk * NN + e) * kTile];
     };
     const int cc = (I + J) & 1;
-    double *out = Ac + mat_off(Gc, NE, cc, (long)J * Gc.W + (I >> 1));
+    T *out = Ac + mat_off(Gc, NE, cc, (long)J * Gc.W + (I >> 1));
     enum { BD = 0, BW = 1, BE = 2, BS = 3, BN = 4 };
     if (NC == 2) {
         const int L = 2 * I, R = 2 * I + 1;
         for (int e = 0; e < NN; ++e) {
-            double d = 0.0;
+            T d = T(0);
             d = d + ent(L, 0, BD, e);
             d = d + ent(L, 0, BE, e);
             d = d + ent(R, 0, BW, e);
             d = d + ent(R, 0, BD, e);
             out[(BD * NN + e) * kTile] = d;
-            double w = 0.0, ea = 0.0;
+            T w = T(0), ea = T(0);
             if (I > 0) w = w + ent(L, 0, BW, e);
             if (I + 1 < Gc.nx) ea = ea + ent(R, 0, BE, e);
             out[(BW * NN + e) * kTile] = w;
@@ -856,7 +859,7 @@ __global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const double 
     }
     const int x0 = 2 * I, x1 = 2 * I + 1, y0 = 2 * J, y1 = 2 * J + 1;
     for (int e = 0; e < NN; ++e) {
-        double d = 0.0;
+        T d = T(0);
         d = d + ent(x0, y0, BD, e);   // SW -> SW
         d = d + ent(x0, y0, BE, e);   // SW -> SE
         d = d + ent(x0, y0, BN, e);   // SW -> NW
@@ -870,7 +873,7 @@ __global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const double 
         d = d + ent(x1, y1, BW, e);   // NE -> NW
         d = d + ent(x1, y1, BD, e);   // NE -> NE
         out[(BD * NN + e) * kTile] = d;
-        double w = 0.0, ea = 0.0, s = 0.0, n = 0.0;
+        T w = T(0), ea = T(0), s = T(0), n = T(0);
         if (I > 0) { w = w + ent(x0, y0, BW, e); w = w + ent(x0, y1, BW, e); }
         if (I + 1 < Gc.nx) { ea = ea + ent(x1, y0, BE, e); ea = ea + ent(x1, y1, BE, e); }
         if (J > 0) { s = s + ent(x0, y0, BS, e); s = s + ent(x1, y0, BS, e); }
@@ -882,45 +885,45 @@ __global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const double 
     }
 }
 
-template <int NC>
-__device__ __forceinline__ void fix_cell(const LevelGeom &G, int op, double *__restrict__ x,
+template <class T, int NC>
+__device__ __forceinline__ void fix_cell(const LevelGeom &G, int op, T *__restrict__ x,
                                          int color, const LevelGeom &Gc,
-                                         const double *__restrict__ xc, long t)
+                                         const T *__restrict__ xc, long t)
 {
     const int j = (int)(t / G.W), k = (int)(t % G.W);
     const int i = 2 * k + ((j + color) & 1);
     if (i >= G.nx) return;
-    double *xm = x + (long)color * NC * G.plane + t;
+    T *xm = x + (long)color * NC * G.plane + t;
     if (op == 0) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) xm[c * G.plane] = 0.0;
+        for (int c = 0; c < NC; ++c) xm[c * G.plane] = T(0);
         return;
     }
     int I = i >> 1, J = j >> 1;
     int cc = (I + J) & 1;
-    const double *p = xc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
+    const T *p = xc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        double base = (op == 1) ? xm[c * G.plane] : 0.0;
+        T base = (op == 1) ? xm[c * G.plane] : T(0);
         xm[c * G.plane] = base + p[c * Gc.plane];
     }
 }
 
-template <int NC>
-__global__ void __launch_bounds__(kBlock) k_fix_color(LevelGeom G, int op, double *__restrict__ x,
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) k_fix_color(LevelGeom G, int op, T *__restrict__ x,
                                                       int color, LevelGeom Gc,
-                                                      const double *__restrict__ xc)
+                                                      const T *__restrict__ xc)
 {
     long t = (long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= G.plane) return;
-    fix_cell<NC>(G, op, x, color, Gc, xc, t);
+    fix_cell<T, NC>(G, op, x, color, Gc, xc, t);
 }
 
 // The coarse levels of a V-cycle in one workgroup: the host records the
 // exact sequence of half sweeps, restrictions and colour fixes that the
 // level-by-level launches would perform, and this kernel executes it with a
 // workgroup barrier between operations (one CU; the coarse data stay in L2).
-template <int NC>
+template <class T, int NC>
 __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *__restrict__ ops,
                                                                int nops,
                                                                const LevelDev *__restrict__ lv_g)
@@ -934,44 +937,50 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
     __syncthreads();
     for (int q = 0; q < nops; ++q) {
         const CoarseOp op = sops[q];
-        const LevelDev L = lv[op.level];
-        const LevelDev Lc = lv[op.level + 1 < kMaxLevels ? op.level + 1 : op.level];
+        const LevelDev &Ld = lv[op.level];
+        const LevelDev &Lcd = lv[op.level + 1 < kMaxLevels ? op.level + 1 : op.level];
+        const LevelGeom G = Ld.G, Gc = Lcd.G;
+        T *A = (T *)Ld.A, *b = (T *)Ld.b, *x = (T *)Ld.x;
+        T *bcz = (T *)Lcd.b, *xc = (T *)Lcd.x;
         if (op.kind == COP_SGS) {
-            for (long t = threadIdx.x; t < L.G.plane; t += kCoarseBlock) {
+            for (long t = threadIdx.x; t < G.plane; t += kCoarseBlock) {
                 switch (op.mode) {
-                case MODE_NORMAL: sgs_cell<NC, MODE_NORMAL>(L.G, L.A, L.b, L.x, op.color, Lc.G, Lc.x, t); break;
-                case MODE_ZERO: sgs_cell<NC, MODE_ZERO>(L.G, L.A, L.b, L.x, op.color, Lc.G, Lc.x, t); break;
-                case MODE_PROLONG: sgs_cell<NC, MODE_PROLONG>(L.G, L.A, L.b, L.x, op.color, Lc.G, Lc.x, t); break;
-                default: sgs_cell<NC, MODE_PROLONG_ZERO>(L.G, L.A, L.b, L.x, op.color, Lc.G, Lc.x, t); break;
+                case MODE_NORMAL: sgs_cell<T, NC, MODE_NORMAL>(G, A, b, x, op.color, Gc, xc, t); break;
+                case MODE_ZERO: sgs_cell<T, NC, MODE_ZERO>(G, A, b, x, op.color, Gc, xc, t); break;
+                case MODE_PROLONG: sgs_cell<T, NC, MODE_PROLONG>(G, A, b, x, op.color, Gc, xc, t); break;
+                default: sgs_cell<T, NC, MODE_PROLONG_ZERO>(G, A, b, x, op.color, Gc, xc, t); break;
                 }
             }
         } else if (op.kind == COP_RESTRICT) {
-            for (long t = threadIdx.x; t < (long)Lc.G.nx * Lc.G.ny; t += kCoarseBlock)
-                restrict_cell<NC>(L.G, L.A, L.b, L.x, Lc.G, Lc.b, t);
+            for (long t = threadIdx.x; t < (long)Gc.nx * Gc.ny; t += kCoarseBlock)
+                restrict_cell<T, NC>(G, A, b, x, Gc, bcz, t);
         } else {
-            for (long t = threadIdx.x; t < L.G.plane; t += kCoarseBlock)
-                fix_cell<NC>(L.G, op.mode, L.x, op.color, Lc.G, Lc.x, t);
+            for (long t = threadIdx.x; t < G.plane; t += kCoarseBlock)
+                fix_cell<T, NC>(G, op.mode, x, op.color, Gc, xc, t);
         }
         __syncthreads();
     }
 }
 
-// Layout conversions.  `n` components of a [n][ny][nx] array <-> colour-split.
+// Layout conversions between the public FP64 layouts and the hierarchy's
+// colour-split storage of precision T.
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_to_split(int n, LevelGeom G,
                                                      const double *__restrict__ v,
-                                                     double *__restrict__ s)
+                                                     T *__restrict__ s)
 {
     long idx = (long)blockIdx.x * kBlock + threadIdx.x;
     const long N = (long)G.nx * G.ny;
     if (idx >= N) return;
     int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
     int color = (i + j) & 1;
-    double *o = s + (long)color * n * G.plane + (long)j * G.W + (i >> 1);
-    for (int c = 0; c < n; ++c) o[c * G.plane] = v[c * N + idx];
+    T *o = s + (long)color * n * G.plane + (long)j * G.W + (i >> 1);
+    for (int c = 0; c < n; ++c) o[c * G.plane] = T(v[c * N + idx]);
 }
 
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_from_split(int n, LevelGeom G,
-                                                       const double *__restrict__ s,
+                                                       const T *__restrict__ s,
                                                        double *__restrict__ v)
 {
     long idx = (long)blockIdx.x * kBlock + threadIdx.x;
@@ -979,33 +988,35 @@ __global__ void __launch_bounds__(kBlock) k_from_split(int n, LevelGeom G,
     if (idx >= N) return;
     int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
     int color = (i + j) & 1;
-    const double *o = s + (long)color * n * G.plane + (long)j * G.W + (i >> 1);
-    for (int c = 0; c < n; ++c) v[c * N + idx] = o[c * G.plane];
+    const T *o = s + (long)color * n * G.plane + (long)j * G.W + (i >> 1);
+    for (int c = 0; c < n; ++c) v[c * N + idx] = double(o[c * G.plane]);
 }
 
-// Block matrices [NE][ny][nx] <-> colour-split tiled layout.
+// Block matrices [NE][ny][nx] (FP64) <-> colour-split tiled layout (T).
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_mat_to_tiled(int ne, LevelGeom G,
                                                          const double *__restrict__ v,
-                                                         double *__restrict__ s)
+                                                         T *__restrict__ s)
 {
     long idx = (long)blockIdx.x * kBlock + threadIdx.x;
     const long N = (long)G.nx * G.ny;
     if (idx >= N) return;
     int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
-    double *o = s + mat_off(G, ne, (i + j) & 1, (long)j * G.W + (i >> 1));
-    for (int e = 0; e < ne; ++e) o[e * kTile] = v[e * N + idx];
+    T *o = s + mat_off(G, ne, (i + j) & 1, (long)j * G.W + (i >> 1));
+    for (int e = 0; e < ne; ++e) o[e * kTile] = T(v[e * N + idx]);
 }
 
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_mat_from_tiled(int ne, LevelGeom G,
-                                                           const double *__restrict__ s,
+                                                           const T *__restrict__ s,
                                                            double *__restrict__ v)
 {
     long idx = (long)blockIdx.x * kBlock + threadIdx.x;
     const long N = (long)G.nx * G.ny;
     if (idx >= N) return;
     int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
-    const double *o = s + mat_off(G, ne, (i + j) & 1, (long)j * G.W + (i >> 1));
-    for (int e = 0; e < ne; ++e) v[e * N + idx] = o[e * kTile];
+    const T *o = s + mat_off(G, ne, (i + j) & 1, (long)j * G.W + (i >> 1));
+    for (int e = 0; e < ne; ++e) v[e * N + idx] = double(o[e * kTile]);
 }
 
 }  // namespace
@@ -1028,12 +1039,18 @@ hipError_t launch_isolated(const Phys &P, const double *z, const double *U, unsi
 }
 
 hipError_t launch_assemble(const Phys &P, const LevelGeom &G, const double *z, const double *U,
-                           const unsigned char *iso, double *A, double *b, double *R_out,
+                           const unsigned char *iso, void *A, void *b, bool f32, double *R_out,
                            double *partial, hipStream_t s)
 {
     int g = nblocks((long)P.nx * P.ny);
-    if (P.dim == 1) NMG_LAUNCH(k_assemble<2>, g, P, G, z, U, iso, A, b, R_out, partial);
-    NMG_LAUNCH(k_assemble<3>, g, P, G, z, U, iso, A, b, R_out, partial);
+    if (f32) {
+        if (P.dim == 1)
+            NMG_LAUNCH((k_assemble<2, float>), g, P, G, z, U, iso, (float *)A, (float *)b, R_out, partial);
+        NMG_LAUNCH((k_assemble<3, float>), g, P, G, z, U, iso, (float *)A, (float *)b, R_out, partial);
+    }
+    if (P.dim == 1)
+        NMG_LAUNCH((k_assemble<2, double>), g, P, G, z, U, iso, (double *)A, (double *)b, R_out, partial);
+    NMG_LAUNCH((k_assemble<3, double>), g, P, G, z, U, iso, (double *)A, (double *)b, R_out, partial);
 }
 
 hipError_t launch_residual(const Phys &P, const double *z, const double *U, double *R_out,
@@ -1061,12 +1078,16 @@ hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color,
     NMG_LAUNCH(k_blu_half<3>, g, P, z, U, color);
 }
 
-hipError_t launch_update(const Phys &P, const LevelGeom &G, const double *x, double *U,
+hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool f32, double *U,
                          hipStream_t s)
 {
     int g = nblocks((long)P.nx * P.ny);
-    if (P.dim == 1) NMG_LAUNCH(k_update<2>, g, P, G, x, U);
-    NMG_LAUNCH(k_update<3>, g, P, G, x, U);
+    if (f32) {
+        if (P.dim == 1) NMG_LAUNCH((k_update<2, float>), g, P, G, (const float *)x, U);
+        NMG_LAUNCH((k_update<3, float>), g, P, G, (const float *)x, U);
+    }
+    if (P.dim == 1) NMG_LAUNCH((k_update<2, double>), g, P, G, (const double *)x, U);
+    NMG_LAUNCH((k_update<3, double>), g, P, G, (const double *)x, U);
 }
 
 hipError_t launch_threshold(const Phys &P, double *U, hipStream_t s)
@@ -1076,85 +1097,121 @@ hipError_t launch_threshold(const Phys &P, double *U, hipStream_t s)
     NMG_LAUNCH(k_threshold<3>, g, P, U);
 }
 
-template <int NC>
-static hipError_t sgs_dispatch(int mode, const LevelGeom &G, const double *A, const double *b,
-                               double *x, int color, const LevelGeom &Gc, const double *xc,
-                               hipStream_t s)
+template <class T, int NC>
+static hipError_t sgs_dispatch(int mode, const LevelGeom &G, const T *A, const T *b, T *x,
+                               int color, const LevelGeom &Gc, const T *xc, hipStream_t s)
 {
     int g = nblocks(G.plane);
     switch (mode) {
-    case MODE_NORMAL: NMG_LAUNCH((k_sgs_half<NC, MODE_NORMAL>), g, G, A, b, x, color, Gc, xc);
-    case MODE_ZERO: NMG_LAUNCH((k_sgs_half<NC, MODE_ZERO>), g, G, A, b, x, color, Gc, xc);
-    case MODE_PROLONG: NMG_LAUNCH((k_sgs_half<NC, MODE_PROLONG>), g, G, A, b, x, color, Gc, xc);
-    default: NMG_LAUNCH((k_sgs_half<NC, MODE_PROLONG_ZERO>), g, G, A, b, x, color, Gc, xc);
+    case MODE_NORMAL: NMG_LAUNCH((k_sgs_half<T, NC, MODE_NORMAL>), g, G, A, b, x, color, Gc, xc);
+    case MODE_ZERO: NMG_LAUNCH((k_sgs_half<T, NC, MODE_ZERO>), g, G, A, b, x, color, Gc, xc);
+    case MODE_PROLONG: NMG_LAUNCH((k_sgs_half<T, NC, MODE_PROLONG>), g, G, A, b, x, color, Gc, xc);
+    default: NMG_LAUNCH((k_sgs_half<T, NC, MODE_PROLONG_ZERO>), g, G, A, b, x, color, Gc, xc);
     }
 }
 
-hipError_t launch_sgs_half(int dim, int mode, const LevelGeom &G, const double *A, const double *b,
-                           double *x, int color, const LevelGeom &Gc, const double *xc,
+hipError_t launch_sgs_half(int dim, bool f32, int mode, const LevelGeom &G, const void *A,
+                           const void *b, void *x, int color, const LevelGeom &Gc, const void *xc,
                            hipStream_t s)
 {
-    if (dim == 1) return sgs_dispatch<2>(mode, G, A, b, x, color, Gc, xc, s);
-    return sgs_dispatch<3>(mode, G, A, b, x, color, Gc, xc, s);
+    if (f32) {
+        if (dim == 1)
+            return sgs_dispatch<float, 2>(mode, G, (const float *)A, (const float *)b, (float *)x,
+                                          color, Gc, (const float *)xc, s);
+        return sgs_dispatch<float, 3>(mode, G, (const float *)A, (const float *)b, (float *)x,
+                                      color, Gc, (const float *)xc, s);
+    }
+    if (dim == 1)
+        return sgs_dispatch<double, 2>(mode, G, (const double *)A, (const double *)b, (double *)x,
+                                       color, Gc, (const double *)xc, s);
+    return sgs_dispatch<double, 3>(mode, G, (const double *)A, (const double *)b, (double *)x,
+                                   color, Gc, (const double *)xc, s);
 }
 
-hipError_t launch_restrict(int dim, const LevelGeom &G, const double *A, const double *b,
-                           const double *x, const LevelGeom &Gc, double *bc, hipStream_t s)
+hipError_t launch_restrict(int dim, bool f32, const LevelGeom &G, const void *A, const void *b,
+                           const void *x, const LevelGeom &Gc, void *bc, hipStream_t s)
 {
     int g = nblocks((long)Gc.nx * Gc.ny);
-    if (dim == 1) NMG_LAUNCH(k_restrict<2>, g, G, A, b, x, Gc, bc);
-    NMG_LAUNCH(k_restrict<3>, g, G, A, b, x, Gc, bc);
+    if (f32) {
+        if (dim == 1) NMG_LAUNCH((k_restrict<float, 2>), g, G, (const float *)A, (const float *)b, (const float *)x, Gc, (float *)bc);
+        NMG_LAUNCH((k_restrict<float, 3>), g, G, (const float *)A, (const float *)b, (const float *)x, Gc, (float *)bc);
+    }
+    if (dim == 1) NMG_LAUNCH((k_restrict<double, 2>), g, G, (const double *)A, (const double *)b, (const double *)x, Gc, (double *)bc);
+    NMG_LAUNCH((k_restrict<double, 3>), g, G, (const double *)A, (const double *)b, (const double *)x, Gc, (double *)bc);
 }
 
-hipError_t launch_galerkin(int dim, const LevelGeom &Gf, const double *Af, const LevelGeom &Gc,
-                           double *Ac, hipStream_t s)
+hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *Af,
+                           const LevelGeom &Gc, void *Ac, hipStream_t s)
 {
     int g = nblocks((long)Gc.nx * Gc.ny);
-    if (dim == 1) NMG_LAUNCH(k_galerkin<2>, g, Gf, Af, Gc, Ac);
-    NMG_LAUNCH(k_galerkin<3>, g, Gf, Af, Gc, Ac);
+    if (f32) {
+        if (dim == 1) NMG_LAUNCH((k_galerkin<float, 2>), g, Gf, (const float *)Af, Gc, (float *)Ac);
+        NMG_LAUNCH((k_galerkin<float, 3>), g, Gf, (const float *)Af, Gc, (float *)Ac);
+    }
+    if (dim == 1) NMG_LAUNCH((k_galerkin<double, 2>), g, Gf, (const double *)Af, Gc, (double *)Ac);
+    NMG_LAUNCH((k_galerkin<double, 3>), g, Gf, (const double *)Af, Gc, (double *)Ac);
 }
 
-hipError_t launch_fix_color(int dim, int op, const LevelGeom &G, double *x, int color,
-                            const LevelGeom &Gc, const double *xc, hipStream_t s)
+hipError_t launch_fix_color(int dim, bool f32, int op, const LevelGeom &G, void *x, int color,
+                            const LevelGeom &Gc, const void *xc, hipStream_t s)
 {
     int g = nblocks(G.plane);
-    if (dim == 1) NMG_LAUNCH(k_fix_color<2>, g, G, op, x, color, Gc, xc);
-    NMG_LAUNCH(k_fix_color<3>, g, G, op, x, color, Gc, xc);
-}
-
-hipError_t launch_coarse_cycle(int dim, const CoarseOp *ops, int nops, const LevelDev *lv,
-                               hipStream_t s)
-{
-    if (dim == 1) {
-        hipLaunchKernelGGL(k_coarse_cycle<2>, dim3(1), dim3(kCoarseBlock), 0, s, ops, nops, lv);
-        return hipGetLastError();
+    if (f32) {
+        if (dim == 1) NMG_LAUNCH((k_fix_color<float, 2>), g, G, op, (float *)x, color, Gc, (const float *)xc);
+        NMG_LAUNCH((k_fix_color<float, 3>), g, G, op, (float *)x, color, Gc, (const float *)xc);
     }
-    hipLaunchKernelGGL(k_coarse_cycle<3>, dim3(1), dim3(kCoarseBlock), 0, s, ops, nops, lv);
-    return hipGetLastError();
+    if (dim == 1) NMG_LAUNCH((k_fix_color<double, 2>), g, G, op, (double *)x, color, Gc, (const double *)xc);
+    NMG_LAUNCH((k_fix_color<double, 3>), g, G, op, (double *)x, color, Gc, (const double *)xc);
 }
 
-hipError_t launch_vec_to_split(int nc, const LevelGeom &G, const double *v, double *split,
+hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
+                               const LevelDev *lv, hipStream_t s)
+{
+#define NMG_COARSE(T, NC)                                                                     \
+    do {                                                                                      \
+        hipLaunchKernelGGL((k_coarse_cycle<T, NC>), dim3(1), dim3(kCoarseBlock), 0, s, ops,   \
+                           nops, lv);                                                         \
+        return hipGetLastError();                                                             \
+    } while (0)
+    if (f32) {
+        if (dim == 1) NMG_COARSE(float, 2);
+        NMG_COARSE(float, 3);
+    }
+    if (dim == 1) NMG_COARSE(double, 2);
+    NMG_COARSE(double, 3);
+#undef NMG_COARSE
+}
+
+hipError_t launch_vec_to_split(int nc, bool f32, const LevelGeom &G, const double *v, void *split,
                                hipStream_t s)
 {
-    NMG_LAUNCH(k_to_split, nblocks((long)G.nx * G.ny), nc, G, v, split);
+    int g = nblocks((long)G.nx * G.ny);
+    if (f32) NMG_LAUNCH(k_to_split<float>, g, nc, G, v, (float *)split);
+    NMG_LAUNCH(k_to_split<double>, g, nc, G, v, (double *)split);
 }
 
-hipError_t launch_vec_from_split(int nc, const LevelGeom &G, const double *split, double *v,
-                                 hipStream_t s)
+hipError_t launch_vec_from_split(int nc, bool f32, const LevelGeom &G, const void *split,
+                                 double *v, hipStream_t s)
 {
-    NMG_LAUNCH(k_from_split, nblocks((long)G.nx * G.ny), nc, G, split, v);
+    int g = nblocks((long)G.nx * G.ny);
+    if (f32) NMG_LAUNCH(k_from_split<float>, g, nc, G, (const float *)split, v);
+    NMG_LAUNCH(k_from_split<double>, g, nc, G, (const double *)split, v);
 }
 
-hipError_t launch_mat_to_split(int ne, const LevelGeom &G, const double *A, double *split,
+hipError_t launch_mat_to_split(int ne, bool f32, const LevelGeom &G, const double *A, void *split,
                                hipStream_t s)
 {
-    NMG_LAUNCH(k_mat_to_tiled, nblocks((long)G.nx * G.ny), ne, G, A, split);
+    int g = nblocks((long)G.nx * G.ny);
+    if (f32) NMG_LAUNCH(k_mat_to_tiled<float>, g, ne, G, A, (float *)split);
+    NMG_LAUNCH(k_mat_to_tiled<double>, g, ne, G, A, (double *)split);
 }
 
-hipError_t launch_mat_from_split(int ne, const LevelGeom &G, const double *split, double *A,
-                                 hipStream_t s)
+hipError_t launch_mat_from_split(int ne, bool f32, const LevelGeom &G, const void *split,
+                                 double *A, hipStream_t s)
 {
-    NMG_LAUNCH(k_mat_from_tiled, nblocks((long)G.nx * G.ny), ne, G, split, A);
+    int g = nblocks((long)G.nx * G.ny);
+    if (f32) NMG_LAUNCH(k_mat_from_tiled<float>, g, ne, G, (const float *)split, A);
+    NMG_LAUNCH(k_mat_from_tiled<double>, g, ne, G, (const double *)split, A);
 }
 
 }  // namespace nmg

@@ -36,7 +36,7 @@ def default_params(dim: int, **kw) -> dict:
     p = dict(flux=HLL if dim == 1 else LLF, g=9.81, alpha=3.0, fd_eps=1e-8, tau=1.0,
              h_eps=1e-6, eps_r=0.03, n_levels=3, nu1=2, nu2=2, nu_coarse=10,
              n_mg=2 if dim == 1 else 3, blu_sweeps=1, max_newton=500, order=REDBLACK,
-             dry_pin=1, pos_theta=0.9)
+             dry_pin=1, pos_theta=0.9 if dim == 2 else 0.0, inner_fp32=0)
     for k, v in kw.items():
         if k not in p:
             raise KeyError(k)

@@ -264,3 +264,54 @@ def test_full_size_assembly_and_cycle(nmg):
     ctx.mg_vcycle(x, 1)
     xo = oracle.vcycles(Ao, bo, np.zeros_like(bo), prob.params, 1)
     same(host(x), xo, "dU after one V-cycle 1024^2")
+
+
+# --- FP32 inner V-cycle (hierarchy and smoother in FP32, Newton in FP64) ---
+
+@pytest.mark.parametrize("case", LIN)
+@pytest.mark.parametrize("nus", [(2, 2, 10), (1, 0, 3)])
+@pytest.mark.parametrize("coarse_cells", ["256", "0"])
+def test_vcycle_fp32_bitwise(nmg, case, nus, coarse_cells, monkeypatch):
+    prob, A, b, x0 = random_case(*case)
+    say("vcycle fp32", case, nus, coarse_cells)
+    monkeypatch.setenv("NMG_COARSE_CELLS", coarse_cells)
+    p = dict(prob.params, nu1=nus[0], nu2=nus[1], nu_coarse=nus[2], inner_fp32=1)
+    ctx = nmg.Context.from_problem(prob, **p)
+    ctx.load_system(dev(A), dev(b))
+    Ag, bg = ctx.get_system(0)
+    same(host(Ag), A.astype(np.float32).astype(np.float64), "A rounded to FP32")
+    x = dev(x0)
+    ctx.mg_vcycle(x, 2)
+    same(host(x), oracle.vcycles(A, b, x0, p, 2), "x after FP32 V-cycles")
+
+
+@pytest.mark.parametrize("k", [0, 2, 3, 4])
+def test_newton_solve_fp32_inner_bitwise(nmg, k):
+    mk, tol, over = SOLVES[k]
+    prob = mk().with_params(inner_fp32=1, **over)
+    say("newton fp32-inner", prob.name, tol, over)
+    ctx = nmg.Context.from_problem(prob)
+    z, U = dev(prob.z), dev(prob.U0)
+    st = ctx.newton_mg_solve(z, U, tol)
+    Uo, sto = oracle.newton_solve(prob, tol=tol)
+    say("  gpu", st["status"], st["newton_steps"], st["res_l1"], "oracle", sto["status"],
+        sto["newton_steps"], sto["res_l1"])
+    assert st["status"] == sto["status"] and st["newton_steps"] == sto["newton_steps"]
+    same(host(U), Uo, "U after the FP32-inner solve")
+
+
+def test_full_size_fp32_cycle(nmg):
+    """1024 x 1024 channel, FP32 inner: assembly rounding and one V-cycle."""
+    prob = W.channel(1024, 1024, n_levels=8, inner_fp32=1)
+    say("full size 1024^2 fp32 V-cycle")
+    ctx = nmg.Context.from_problem(prob)
+    z, U = dev(prob.z), dev(prob.U0)
+    ctx.assemble_residual_jacobian(z, U)
+    Ao, bo, _ = oracle.assemble(prob, prob.U0)
+    A, b = ctx.get_system(0)
+    same(host(A), Ao.astype(np.float32).astype(np.float64), "A 1024^2 in FP32")
+    same(host(b), bo.astype(np.float32).astype(np.float64), "b 1024^2 in FP32")
+    del A
+    x = torch.zeros_like(U)
+    ctx.mg_vcycle(x, 1)
+    same(host(x), oracle.vcycles(Ao, bo, np.zeros_like(bo), prob.params, 1), "dU FP32 1024^2")

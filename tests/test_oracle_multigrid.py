@@ -117,3 +117,27 @@ def test_vcycles_converge(order, dim, nx, ny, nl):
         errs.append(np.abs(vec(x) - xs).max())
     assert errs[-1] < 1e-10 * np.abs(xs).max()
     assert all(e2 < 0.2 * e1 or e2 < 1e-12 for e1, e2 in zip(errs, errs[1:]))
+
+
+def test_fp32_vcycles_track_fp64():
+    """The FP32 V-cycle solves the same system to single precision."""
+    dim, nx, ny = 2, 32, 16
+    A, b = W.random_system(dim, nx, ny, seed=21)
+    M = dense(A)
+    xs = np.linalg.solve(M, vec(b))
+    p32 = W.default_params(dim, n_levels=3, inner_fp32=1)
+    x = np.zeros_like(b)
+    for _ in range(8):
+        x = oracle.vcycles(A, b, x, p32, 1)
+    err = np.abs(vec(x) - xs).max() / np.abs(xs).max()
+    assert 1e-9 < err < 1e-5      # float-level accuracy, not double
+
+
+def test_fp32_inner_newton_reaches_fp64_tolerance():
+    """Newton with an FP32 inner solve is iterative refinement: the FP64
+    residual still reaches 1e-10 and the state matches the FP64 solve."""
+    prob = W.bump_1d(200)
+    U64, st64 = oracle.newton_solve(prob, tol=1e-10)
+    U32, st32 = oracle.newton_solve(prob.with_params(inner_fp32=1), tol=1e-10)
+    assert st32["status"] == "OK" and st32["res_l1"] < 1e-10
+    assert np.abs(U32 - U64).max() < 1e-9
