@@ -52,7 +52,7 @@ enum {
     NMG_EDIVERGED = -5       /* sum ||R_i||_1 grew beyond 1e8 x its first value */
 };
 
-enum { NMG_FLUX_HLL = 0, NMG_FLUX_LLF = 1 };
+enum { NMG_FLUX_HLL = 0, NMG_FLUX_LLF = 1, NMG_FLUX_HLLC = 2 /* 2D only */ };
 enum { NMG_BC_REFLECT = 0, NMG_BC_SLIP = 1, NMG_BC_OPEN = 2 };
 
 /* Uniform Cartesian grid (paper Sec. 2, partition of the domain).  dim is 1
@@ -93,7 +93,9 @@ typedef struct {
  * inner_fp32 (0/1) stores the multigrid hierarchy (blocks, right-hand
  * sides, corrections) in FP32 and runs the V-cycle in FP32, while residuals,
  * assembly arithmetic, the update, the threshold and the stop test stay FP64
- * (Newton then acts as iterative refinement). */
+ * (Newton then acts as iterative refinement).  gamma is the cycle index of
+ * Algorithm 0 (1 = V-cycle, 2 = W-cycle); the finest level always makes a
+ * single coarse-grid call. */
 typedef struct {
     int flux;
     double g, alpha, fd_eps, tau, h_eps, eps_r;
@@ -102,6 +104,7 @@ typedef struct {
     int dry_pin;
     double pos_theta;
     int inner_fp32;
+    int gamma;
 } nmg_params;
 
 /* Solve statistics (host memory).  res_hist (optional, host) receives the
@@ -140,9 +143,9 @@ int nmg_residual(nmg_ctx *ctx, const double *z, const double *U, double *R_out,
 int nmg_assemble_residual_jacobian(nmg_ctx *ctx, const double *z, const double *U,
                                    double *R_out, double *res_l1_host);
 
-/* n_cycles multigrid V-cycles (Algorithm 0, gamma = 1, red-black block SGS
- * smoother) on the system last assembled or loaded, starting from and
- * returning dU (device, cell-vector layout, in/out). */
+/* n_cycles multigrid cycles (Algorithm 0 with the context's gamma,
+ * red-black block SGS smoother) on the system last assembled or loaded,
+ * starting from and returning dU (device, cell-vector layout, in/out). */
 int nmg_mg_vcycle(nmg_ctx *ctx, double *dU, int n_cycles);
 
 /* `iters` red-black block SGS iterations (red, black, black, red half

@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("eps_r", C.c_double), ("n_levels", C.c_int), ("nu1", C.c_int),
                 ("nu2", C.c_int), ("nu_coarse", C.c_int), ("n_mg", C.c_int),
                 ("blu_sweeps", C.c_int), ("max_newton", C.c_int), ("order", C.c_int),
-                ("dry_pin", C.c_int), ("pos_theta", C.c_double), ("inner_fp32", C.c_int)]
+                ("dry_pin", C.c_int), ("pos_theta", C.c_double), ("inner_fp32", C.c_int),
+                ("gamma", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -77,7 +78,7 @@ def params_struct(p: dict) -> Params:
                   p["eps_r"], int(p["n_levels"]), int(p["nu1"]), int(p["nu2"]),
                   int(p["nu_coarse"]), int(p["n_mg"]), int(p["blu_sweeps"]),
                   int(p["max_newton"]), int(p["order"]), int(p["dry_pin"]),
-                  float(p["pos_theta"]), int(p.get("inner_fp32", 0)))
+                  float(p["pos_theta"]), int(p.get("inner_fp32", 0)), int(p.get("gamma", 1)))
 
 
 def _f64(a):

@@ -68,7 +68,8 @@ void orc_num_flux(int flux, int nc, int axis, double g, double eps_r,
             out[k] = 0.5 * ((FL[k] + FR[k]) - s * (UR[k] - UL[k]));
         return;
     }
-    /* eq:HLLflux with the two-rarefaction star estimates u_*, h_*. */
+    /* eq:HLLflux with the two-rarefaction star estimates u_*, h_*; HLLC
+     * adds the contact wave s_M for the tangential momentum below. */
     double us = ((unL + unR) * 0.5 + cL) - cR;
     double a = (cL + cR) + (unL - unR) * 0.5;
     double hs = (a * a) / (4.0 * g);
@@ -82,6 +83,18 @@ void orc_num_flux(int flux, int nc, int axis, double g, double eps_r,
     } else {
         for (int k = 0; k < nc; ++k)
             out[k] = ((sR * FL[k] - sL * FR[k]) + (sL * sR) * (UR[k] - UL[k])) / (sR - sL);
+        if (flux == ORC_HLLC && nc == 3) {
+            /* HLLC (Remark on numerical fluxes): the tangential momentum flux
+             * is the upwind tangential velocity, chosen by the sign of the
+             * contact speed s_M, times the HLL mass flux.  s_M's 0/0 (both
+             * sides dry) is taken as 0. */
+            double num = (sL * hR) * (unR - sR) - (sR * hL) * (unL - sL);
+            double den = hR * (unR - sR) - hL * (unL - sL);
+            double sM = (den != 0.0) ? num / den : 0.0;
+            double utL = (axis == 0) ? vL : uL, utR = (axis == 0) ? vR : uR;
+            double ut = (sM >= 0.0) ? utL : utR;
+            out[2 - axis] = ut * out[0];
+        }
     }
 }
 

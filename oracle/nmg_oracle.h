@@ -23,7 +23,7 @@ extern "C" {
 #endif
 
 enum { ORC_REFLECT = 0, ORC_SLIP = 1, ORC_OPEN = 2 };
-enum { ORC_HLL = 0, ORC_LLF = 1 };
+enum { ORC_HLL = 0, ORC_LLF = 1, ORC_HLLC = 2 };
 enum { ORC_REDBLACK = 0, ORC_LEX = 1 };
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_EINVAL = -1, ORC_ENONFINITE = -4,
        ORC_EDIVERGED = -5 };
@@ -50,6 +50,7 @@ typedef struct {
     int dry_pin;                    /* hold the momentum of exactly dry cells at 0 */
     double pos_theta;               /* positivity limit of the per-cell relaxation (0 = off) */
     int inner_fp32;                 /* V-cycles in FP32 (Newton residual and update in FP64) */
+    int gamma;                      /* cycle index: 1 = V-cycle, 2 = W-cycle */
 } orc_params;
 
 typedef struct {

@@ -61,6 +61,8 @@ struct nmg_ctx {
     int lc = -1;
     bool recording = false;
     std::vector<CoarseOp> rec;
+    int prog_off[2] = {0, 0}, prog_len[2] = {0, 0};   // [0]: zero start, [1]: valid start
+    int l_lds = -1;                   // levels l_lds..NL run from LDS in the coarse kernel
     CoarseOp *d_ops = nullptr;
     LevelDev *d_lv = nullptr;
 };
@@ -97,13 +99,18 @@ int check_params(const nmg_grid *g, const nmg_bc *bc, const nmg_params *p, std::
         msg = "nx (and ny) must be divisible by 2^n_levels";
         return NMG_EINVAL;
     }
-    if (p->flux != NMG_FLUX_HLL && p->flux != NMG_FLUX_LLF) { msg = "unknown flux"; return NMG_EINVAL; }
+    if (p->flux != NMG_FLUX_HLL && p->flux != NMG_FLUX_LLF && p->flux != NMG_FLUX_HLLC) {
+        msg = "unknown flux";
+        return NMG_EINVAL;
+    }
     if (!(p->g > 0) || !(p->fd_eps > 0) || !(p->alpha >= 0) || !(p->h_eps >= 0) || !(p->tau > 0) ||
         !(p->eps_r >= 0) || !(p->pos_theta >= 0 && p->pos_theta < 1)) {
         msg = "bad scalar parameter";
         return NMG_EINVAL;
     }
     if (p->inner_fp32 != 0 && p->inner_fp32 != 1) { msg = "inner_fp32 must be 0 or 1"; return NMG_EINVAL; }
+    if (p->gamma < 1 || p->gamma > 3) { msg = "gamma must be 1, 2 or 3"; return NMG_EINVAL; }
+    if (p->flux == NMG_FLUX_HLLC && g->dim != 2) { msg = "HLLC is a 2D flux"; return NMG_EINVAL; }
     if (p->nu1 < 0 || p->nu2 < 0 || p->nu_coarse < 0 || p->n_mg < 0 || p->blu_sweeps < 0 ||
         p->max_newton < 0) {
         msg = "negative iteration count";
@@ -207,13 +214,21 @@ int cycle(nmg_ctx *c, int l)
     const nmg_params &p = c->prm;
     int rc;
     if (l == c->lc && !c->recording) {
-        // the whole sub-cycle from level lc down runs in one workgroup; it
-        // leaves level lc's correction materialized
-        HIPCHK(c, launch_coarse_cycle(c->dim, c->f32, c->d_ops, (int)c->rec.size(), c->d_lv,
-                                      c->stream));
-        c->L[l].st[0] = c->L[l].st[1] = ST_VALID;
-        c->L[l].last = -1;
-        return NMG_OK;
+        // The whole sub-cycle from level lc down runs in one workgroup and
+        // leaves level lc's correction materialized.  Program 0 starts from a
+        // zero correction, program 1 from stored values (the later calls of a
+        // W-cycle).
+        int st0 = c->L[l].st[0], st1 = c->L[l].st[1];
+        int prog = (st0 == ST_ZERO && st1 == ST_ZERO) ? 0
+                   : (st0 == ST_VALID && st1 == ST_VALID) ? 1 : -1;
+        if (prog >= 0 && c->prog_len[prog] > 0) {
+            HIPCHK(c, launch_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[prog],
+                                          c->prog_len[prog], c->d_lv, c->l_lds, c->NL,
+                                          c->stream));
+            c->L[l].st[0] = c->L[l].st[1] = ST_VALID;
+            c->L[l].last = -1;
+            return NMG_OK;
+        }
     }
     if ((rc = smooth(c, l, p.nu1))) return rc;
     if (l == c->NL) {
@@ -227,7 +242,11 @@ int cycle(nmg_ctx *c, int l)
         else
             HIPCHK(c, launch_restrict(c->dim, c->f32, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b, c->stream));
         set_zero(c, l + 1);
-        if ((rc = cycle(c, l + 1))) return rc;
+        // gamma coarse cycles (gamma = 1: V, 2: W), one when leaving the
+        // finest level (Algorithm 0)
+        const int calls = (l == 0) ? 1 : p.gamma;
+        for (int g = 0; g < calls; ++g)
+            if ((rc = cycle(c, l + 1))) return rc;
         if ((rc = materialize(c, l + 1))) return rc;
         for (int color = 0; color < 2; ++color)
             Lv.st[color] = (Lv.st[color] == ST_ZERO) ? ST_ZERO_PP : ST_VALID_PP;
@@ -249,7 +268,7 @@ int build_coarse(nmg_ctx *c)
 // from a zero correction) and upload them with the level table.
 int plan_coarse(nmg_ctx *c)
 {
-    long maxcells = 256;
+    long maxcells = 1024;
     if (const char *e = std::getenv("NMG_COARSE_CELLS")) maxcells = std::atol(e);
     c->lc = -1;
     for (int l = 1; l <= c->NL; ++l)
@@ -258,17 +277,34 @@ int plan_coarse(nmg_ctx *c)
     Level saved[16];
     for (int l = 0; l <= c->NL; ++l) saved[l] = c->L[l];
     c->rec.clear();
-    c->recording = true;
-    set_zero(c, c->lc);
-    int rc = cycle(c, c->lc);
-    if (!rc) rc = materialize(c, c->lc);
-    c->recording = false;
+    int rc = NMG_OK;
+    for (int prog = 0; prog < 2 && !rc; ++prog) {
+        c->prog_off[prog] = (int)c->rec.size();
+        c->recording = true;
+        set_zero(c, c->lc);
+        if (prog == 1) c->L[c->lc].st[0] = c->L[c->lc].st[1] = ST_VALID;
+        rc = cycle(c, c->lc);
+        if (!rc) rc = materialize(c, c->lc);
+        c->recording = false;
+        c->prog_len[prog] = (int)c->rec.size() - c->prog_off[prog];
+    }
     for (int l = 0; l <= c->NL; ++l) c->L[l] = saved[l];
     if (rc) return rc;
-    if ((int)c->rec.size() > kMaxCoarseOps) {   // too long for LDS: per-level launches
-        c->lc = -1;
+    if (c->prog_len[0] > kMaxCoarseOps || c->prog_len[1] > kMaxCoarseOps) {
+        c->lc = -1;                              // too long for LDS: per-level launches
         c->rec.clear();
         return NMG_OK;
+    }
+    // the coarsest levels whose data fit the kernel's LDS run from LDS
+    {
+        const long esz = c->f32 ? 4 : 8;
+        long tot = 0;
+        c->l_lds = -1;
+        for (int l = c->NL; l >= c->lc; --l) {
+            tot += level_bytes(c->L[l].G, c->ne, c->nc, esz);
+            if (tot > kCoarseLdsBytes) break;
+            c->l_lds = l;
+        }
     }
     LevelDev lv[kMaxLevels];
     for (int l = 0; l < kMaxLevels; ++l) {

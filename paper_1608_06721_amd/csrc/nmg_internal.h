@@ -66,7 +66,11 @@ enum SweepMode {
 constexpr int kBlock = 256;
 constexpr int kCoarseBlock = 512;     // one workgroup runs the coarse part of a cycle
 constexpr int kMaxLevels = 16;
-constexpr int kMaxCoarseOps = 2048;  // LDS capacity of the coarse-cycle kernel's op list
+constexpr int kMaxCoarseOps = 1024;  // LDS capacity of the coarse-cycle kernel's op list
+// LDS bytes of the coarse-cycle kernel for level data: the coarsest levels
+// whose blocks and vectors fit are copied in and run from LDS (gfx950 allows
+// 160 KB per workgroup; the op list and level table take the rest).
+constexpr long kCoarseLdsBytes = 140 * 1024;
 
 // Device-side description of one level (for the coarse-cycle kernel); the
 // arrays hold the hierarchy's scalar type (double, or float for the FP32
@@ -115,9 +119,17 @@ hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *A
 hipError_t launch_fix_color(int dim, bool f32, int op, const LevelGeom &G, void *x, int color,
                             const LevelGeom &Gc, const void *xc, hipStream_t s);
 
-// The recorded coarse part of a V-cycle, executed by one workgroup.
+// The recorded coarse part of a V-cycle, executed by one workgroup; levels
+// l_lds..nl are staged in LDS (l_lds < 0: none).
 hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
-                               const LevelDev *lv, hipStream_t s);
+                               const LevelDev *lv, int l_lds, int nl, hipStream_t s);
+
+// Bytes of one level's blocks, right-hand side and correction (both colours)
+// for the scalar size esz.
+inline long level_bytes(const LevelGeom &G, int ne, int nc, long esz)
+{
+    return (2 * ne * G.planeP + 2 * 2 * nc * G.plane) * esz;
+}
 
 // Layout conversions between the public FP64 layouts and the colour-split
 // hierarchy storage.

@@ -56,7 +56,7 @@ __device__ __forceinline__ void phys_flux(int axis, double g, double h, double u
 
 // Face flux in the +axis orientation between reconstructed left and right
 // states (Remark on numerical fluxes: HLL with two-rarefaction star
-// estimates, or LLF with the eps_r-enlarged wave speed).
+// estimates, HLLC, or LLF with the eps_r-enlarged wave speed).
 template <int NC>
 __device__ __forceinline__ void num_flux(const Phys &P, int axis, double hL, double uL, double vL,
                                          double hR, double uR, double vR, double *out)
@@ -92,6 +92,17 @@ __device__ __forceinline__ void num_flux(const Phys &P, int axis, double hL, dou
 #pragma unroll
         for (int k = 0; k < NC; ++k)
             out[k] = ((sR * FL[k] - sL * FR[k]) + (sL * sR) * (UR[k] - UL[k])) / (sR - sL);
+        if (NC == 3 && P.flux == 2) {
+            // HLLC: tangential momentum = upwind tangential velocity (by the
+            // sign of the contact speed s_M) times the HLL mass flux; s_M's
+            // 0/0 (both sides dry) counts as 0.
+            double num = (sL * hR) * (unR - sR) - (sR * hL) * (unL - sL);
+            double den = hR * (unR - sR) - hL * (unL - sL);
+            double sM = (den != 0.0) ? num / den : 0.0;
+            double utL = (axis == 0) ? vL : uL, utR = (axis == 0) ? vR : uR;
+            double ut = (sM >= 0.0) ? utL : utR;
+            out[2 - axis] = ut * out[0];
+        }
     }
 }
 
@@ -922,19 +933,37 @@ __global__ void __launch_bounds__(kBlock) k_fix_color(LevelGeom G, int op, T *__
 // The coarse levels of a V-cycle in one workgroup: the host records the
 // exact sequence of half sweeps, restrictions and colour fixes that the
 // level-by-level launches would perform, and this kernel executes it with a
-// workgroup barrier between operations (one CU; the coarse data stay in L2).
+// workgroup barrier between operations.  Levels l_lds..nl are first copied
+// into LDS and their results copied back at the end, so the many operations
+// on the smallest levels run at LDS latency (the arithmetic is unchanged).
 template <class T, int NC>
 __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *__restrict__ ops,
                                                                int nops,
-                                                               const LevelDev *__restrict__ lv_g)
+                                                               const LevelDev *__restrict__ lv_g,
+                                                               int l_lds, int nl)
 {
-    // The op list and the level table live in LDS for the whole kernel, so
-    // each operation costs one round trip for its data only.
+    constexpr int NF = (NC == 2) ? 2 : 4;
+    constexpr int NE = (NF + 1) * NC * NC;
     __shared__ CoarseOp sops[kMaxCoarseOps];
     __shared__ LevelDev lv[kMaxLevels];
+    __shared__ __attribute__((aligned(16))) char lds[kCoarseLdsBytes];
     for (int q = threadIdx.x; q < nops; q += kCoarseBlock) sops[q] = ops[q];
     for (int q = threadIdx.x; q < kMaxLevels; q += kCoarseBlock) lv[q] = lv_g[q];
     __syncthreads();
+    if (l_lds >= 0) {
+        long off = 0;
+        for (int l = l_lds; l <= nl; ++l) {
+            const LevelGeom G = lv_g[l].G;
+            const long na = 2L * NE * G.planeP, nv = 2L * NC * G.plane;
+            T *A = (T *)(lds + off), *b = A + na, *x = b + nv;
+            const T *gA = (const T *)lv_g[l].A, *gb = (const T *)lv_g[l].b, *gx = (const T *)lv_g[l].x;
+            for (long k = threadIdx.x; k < na; k += kCoarseBlock) A[k] = gA[k];
+            for (long k = threadIdx.x; k < nv; k += kCoarseBlock) { b[k] = gb[k]; x[k] = gx[k]; }
+            if (threadIdx.x == 0) { lv[l].A = A; lv[l].b = b; lv[l].x = x; }
+            off += (na + 2 * nv) * (long)sizeof(T);
+        }
+        __syncthreads();
+    }
     for (int q = 0; q < nops; ++q) {
         const CoarseOp op = sops[q];
         const LevelDev &Ld = lv[op.level];
@@ -959,6 +988,14 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
                 fix_cell<T, NC>(G, op.mode, x, op.color, Gc, xc, t);
         }
         __syncthreads();
+    }
+    if (l_lds >= 0) {
+        for (int l = l_lds; l <= nl; ++l) {
+            const long nv = 2L * NC * lv_g[l].G.plane;
+            const T *b = (const T *)lv[l].b, *x = (const T *)lv[l].x;
+            T *gb = (T *)lv_g[l].b, *gx = (T *)lv_g[l].x;
+            for (long k = threadIdx.x; k < nv; k += kCoarseBlock) { gb[k] = b[k]; gx[k] = x[k]; }
+        }
     }
 }
 
@@ -1165,12 +1202,12 @@ hipError_t launch_fix_color(int dim, bool f32, int op, const LevelGeom &G, void 
 }
 
 hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
-                               const LevelDev *lv, hipStream_t s)
+                               const LevelDev *lv, int l_lds, int nl, hipStream_t s)
 {
 #define NMG_COARSE(T, NC)                                                                     \
     do {                                                                                      \
         hipLaunchKernelGGL((k_coarse_cycle<T, NC>), dim3(1), dim3(kCoarseBlock), 0, s, ops,   \
-                           nops, lv);                                                         \
+                           nops, lv, l_lds, nl);                                              \
         return hipGetLastError();                                                             \
     } while (0)
     if (f32) {

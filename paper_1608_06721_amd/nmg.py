@@ -40,7 +40,7 @@ class nmg_params(C.Structure):
                 ("eps_r", C.c_double), ("n_levels", C.c_int), ("nu1", C.c_int),
                 ("nu2", C.c_int), ("nu_coarse", C.c_int), ("n_mg", C.c_int),
                 ("blu_sweeps", C.c_int), ("max_newton", C.c_int), ("dry_pin", C.c_int),
-                ("pos_theta", C.c_double), ("inner_fp32", C.c_int)]
+                ("pos_theta", C.c_double), ("inner_fp32", C.c_int), ("gamma", C.c_int)]
 
 
 class nmg_stats(C.Structure):
@@ -121,7 +121,8 @@ class Context:
                        int(params["nu1"]), int(params["nu2"]), int(params["nu_coarse"]),
                        int(params["n_mg"]), int(params["blu_sweeps"]),
                        int(params["max_newton"]), int(params["dry_pin"]),
-                       float(params["pos_theta"]), int(params.get("inner_fp32", 0)))
+                       float(params["pos_theta"]), int(params.get("inner_fp32", 0)),
+                       int(params.get("gamma", 1)))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

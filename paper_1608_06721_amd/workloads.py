@@ -18,7 +18,7 @@ from typing import List, Tuple
 import numpy as np
 
 REFLECT, SLIP, OPEN = 0, 1, 2
-HLL, LLF = 0, 1
+HLL, LLF, HLLC = 0, 1, 2
 REDBLACK, LEX = 0, 1
 NAN = float("nan")
 
@@ -36,7 +36,7 @@ def default_params(dim: int, **kw) -> dict:
     p = dict(flux=HLL if dim == 1 else LLF, g=9.81, alpha=3.0, fd_eps=1e-8, tau=1.0,
              h_eps=1e-6, eps_r=0.03, n_levels=3, nu1=2, nu2=2, nu_coarse=10,
              n_mg=2 if dim == 1 else 3, blu_sweeps=1, max_newton=500, order=REDBLACK,
-             dry_pin=1, pos_theta=0.9 if dim == 2 else 0.0, inner_fp32=0)
+             dry_pin=1, pos_theta=0.9 if dim == 2 else 0.0, inner_fp32=0, gamma=1)
     for k, v in kw.items():
         if k not in p:
             raise KeyError(k)
@@ -255,4 +255,22 @@ def dry_hill(nx: int = 128, ny: int = 64, **kw) -> Problem:
     U0[0] = np.maximum(0.2 - z, 0.0)
     bc = [open_q(0.1, 0.0), open_h(0.2), wall(), wall()]
     return Problem("dry_hill_%dx%d" % (nx, ny), 2, nx, ny, 0.0, 25.0, -5.0, 5.0, bc,
+                   default_params(2, **kw), z, U0)
+
+
+def transcritical_bump_2d(nx: int = 160, ny: int = 64, **kw) -> Problem:
+    """2D flow over a bump (Example 3.6 set-up): [0, 25] x [-5, 5],
+    z = 0.2 - 0.05 ((x-10)^2 + y^2) inside radius 2, discharge 1.53 at x = 0,
+    depth 0.52 at x = 25, reflective walls at y = +-5, HLLC; start from rest
+    at the outflow level, h = max(0.52 - z, 0)."""
+    x = cell_centres(0.0, 25.0, nx)
+    y = cell_centres(-5.0, 5.0, ny)
+    X, Y = np.meshgrid(x, y)
+    r2 = (X - 10.0) ** 2 + Y ** 2
+    z = np.where(r2 < 4.0, 0.2 - 0.05 * r2, 0.0)
+    U0 = np.zeros((3, ny, nx))
+    U0[0] = np.maximum(0.52 - z, 0.0)
+    bc = [open_q(1.53, 0.0), open_h(0.52), wall(), wall()]
+    kw.setdefault("flux", HLLC)
+    return Problem("bump2d_%dx%d" % (nx, ny), 2, nx, ny, 0.0, 25.0, -5.0, 5.0, bc,
                    default_params(2, **kw), z, U0)

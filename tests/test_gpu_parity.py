@@ -78,6 +78,8 @@ def problems():
     out.append(W.lake_island(64, n_levels=4))
     out.append(W.channel(64, 64, n_levels=4))
     out.append(W.dry_hill(64, 32, n_levels=3))
+    out.append(tiny(2, 24, 16, 5, CHAN, W.HLLC, n_levels=3))
+    out.append(W.transcritical_bump_2d(80, 32, n_levels=3))
     return out
 
 
@@ -146,13 +148,15 @@ def test_sgs_bitwise(nmg, case, iters):
 @pytest.mark.parametrize("nus", [(2, 2, 10), (1, 0, 3), (0, 1, 2), (0, 0, 1), (3, 1, 0)])
 @pytest.mark.parametrize("cycles", [1, 3])
 @pytest.mark.parametrize("coarse_cells", ["4096", "0"])
-def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, monkeypatch):
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, gamma, monkeypatch):
     """coarse_cells: levels up to this many cells run in the single-workgroup
-    coarse-cycle kernel ("0": every level launched on its own)."""
+    coarse-cycle kernel ("0": every level launched on its own); gamma = 2 is
+    the W-cycle."""
     prob, A, b, x0 = random_case(*case)
-    say("vcycle", case, nus, cycles, coarse_cells)
+    say("vcycle", case, nus, cycles, coarse_cells, gamma)
     monkeypatch.setenv("NMG_COARSE_CELLS", coarse_cells)
-    p = dict(prob.params, nu1=nus[0], nu2=nus[1], nu_coarse=nus[2])
+    p = dict(prob.params, nu1=nus[0], nu2=nus[1], nu_coarse=nus[2], gamma=gamma)
     ctx = nmg.Context.from_problem(prob, **p)
     ctx.load_system(dev(A), dev(b))
     x = dev(x0)
@@ -176,6 +180,8 @@ SOLVES = [
     (lambda: W.lake_island(64, n_levels=4), 0.0, dict(max_newton=5)),
     (lambda: W.channel(64, 64, n_levels=4), 0.0, dict(max_newton=12)),
     (lambda: W.dry_hill(128, 64, n_levels=5), 1e-10, {}),
+    (lambda: W.dry_hill(128, 64, n_levels=5, gamma=2), 1e-10, {}),
+    (lambda: W.transcritical_bump_2d(80, 32, n_levels=3), 0.0, dict(max_newton=6)),
 ]
 
 

@@ -36,7 +36,7 @@ def test_physical_flux_is_the_swe_flux(axis):
                                rtol=1e-15)
 
 
-@pytest.mark.parametrize("flux", [W.HLL, W.LLF])
+@pytest.mark.parametrize("flux", [W.HLL, W.LLF, W.HLLC])
 @pytest.mark.parametrize("axis", [0, 1])
 def test_consistency(flux, axis):
     """F_hat(U, U) = F(U) (the consistency required of eq:totalFlux)."""
@@ -48,7 +48,7 @@ def test_consistency(flux, axis):
         np.testing.assert_allclose(got, ref, rtol=4e-15, atol=4e-15 * (1 + np.abs(ref).max()))
 
 
-@pytest.mark.parametrize("flux", [W.HLL, W.LLF])
+@pytest.mark.parametrize("flux", [W.HLL, W.LLF, W.HLLC])
 def test_rotation_invariance(flux):
     """The y-flux of (h, u, v) is the x-flux of (h, v, u) with the momentum
     components swapped (rotational invariance of the SWE)."""
@@ -60,7 +60,7 @@ def test_rotation_invariance(flux):
         np.testing.assert_allclose(fy, fx[[0, 2, 1]], rtol=1e-13, atol=1e-13)
 
 
-@pytest.mark.parametrize("flux", [W.HLL, W.LLF])
+@pytest.mark.parametrize("flux", [W.HLL, W.LLF, W.HLLC])
 def test_mirror_symmetry(flux):
     """Reflecting x -> -x maps the face problem (L, R) to (mirror R,
     mirror L); the mass and tangential fluxes change sign, the normal
@@ -174,3 +174,18 @@ def test_ghost_supercritical():
     side = (W.OPEN, 0.3, 1.5, 0.0)       # everything prescribed: supercritical inflow
     hg, ug, vg = oracle.ghost(side, 0, G, 1e-6, h, u, 0.0)
     assert (hg, ug, vg) == (0.3, 1.5 / 0.3, 0.0)
+
+
+def test_hllc_tangential_upwinding():
+    """HLLC keeps HLL's mass and normal momentum fluxes and carries the
+    tangential velocity of the side the contact wave comes from."""
+    r = rng(7)
+    for _ in range(100):
+        hL, hR = r.uniform(0.3, 2, 2)
+        uL, uR = r.uniform(-0.5, 0.5, 2)        # subcritical: sL < 0 < sR
+        vL, vR = r.uniform(-1, 1, 2)
+        hll = oracle.num_flux(W.HLL, 3, 0, G, EPS_R, hL, uL, vL, hR, uR, vR)
+        hllc = oracle.num_flux(W.HLLC, 3, 0, G, EPS_R, hL, uL, vL, hR, uR, vR)
+        assert hllc[0] == hll[0] and hllc[1] == hll[1]
+        ut = vL if hllc[0] >= 0 else vR       # contact moves with the mass flux
+        assert hllc[2] == pytest.approx(ut * hllc[0], rel=1e-14, abs=1e-300)

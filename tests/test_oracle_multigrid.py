@@ -141,3 +141,30 @@ def test_fp32_inner_newton_reaches_fp64_tolerance():
     U32, st32 = oracle.newton_solve(prob.with_params(inner_fp32=1), tol=1e-10)
     assert st32["status"] == "OK" and st32["res_l1"] < 1e-10
     assert np.abs(U32 - U64).max() < 1e-9
+
+
+@pytest.mark.parametrize("dim,nx,ny,nl", [(1, 64, 1, 4), (2, 32, 32, 3)])
+def test_w_cycle_converges_at_least_as_fast(dim, nx, ny, nl):
+    """gamma = 2 (W-cycle, one coarse call from the finest level) converges
+    and contracts at least as well as the V-cycle per cycle."""
+    A, b = W.random_system(dim, nx, ny, seed=13, diag_boost=1.0)
+    xs = np.linalg.solve(dense(A), vec(b))
+    errs = {}
+    for gamma in (1, 2):
+        p = W.default_params(dim, n_levels=nl, gamma=gamma, nu_coarse=2)
+        x = np.zeros_like(b)
+        for _ in range(5):
+            x = oracle.vcycles(A, b, x, p, 1)
+        errs[gamma] = np.abs(vec(x) - xs).max()
+    assert errs[2] <= errs[1] * 1.0001
+    assert errs[2] < 1e-6 * np.abs(xs).max()
+
+
+def test_w_cycle_equals_v_cycle_with_one_coarse_level():
+    """With a single coarse level the finest level's single call makes the
+    W-cycle identical to the V-cycle."""
+    A, b = W.random_system(2, 16, 16, seed=14)
+    x0 = np.zeros_like(b)
+    pv = W.default_params(2, n_levels=1, gamma=1)
+    pw = W.default_params(2, n_levels=1, gamma=2)
+    np.testing.assert_array_equal(oracle.vcycles(A, b, x0, pv, 2), oracle.vcycles(A, b, x0, pw, 2))
