@@ -266,6 +266,43 @@ int build_coarse(nmg_ctx *c)
 
 // Record the operations of the sub-cycle from level lc (which always starts
 // from a zero correction) and upload them with the level table.
+// Replace each maximal sequence of alternating half sweeps on the coarsest
+// level (normal, or zero start first) by one COP_RUN, when that level is in
+// LDS and has a thread per cell in the coarse-cycle kernel.
+void merge_runs(nmg_ctx *c)
+{
+    const int nl = c->NL;
+    if (c->l_lds < 0 || 2 * c->L[nl].G.plane > kCoarseBlock) return;
+    std::vector<CoarseOp> out;
+    int off[2], len[2];
+    for (int prog = 0; prog < 2; ++prog) {
+        off[prog] = (int)out.size();
+        const CoarseOp *r = c->rec.data() + c->prog_off[prog];
+        const int n = c->prog_len[prog];
+        for (int q = 0; q < n;) {
+            CoarseOp o = r[q];
+            if (o.kind == COP_SGS && o.level == nl && (o.mode == MODE_NORMAL || o.mode == MODE_ZERO)) {
+                int e = q + 1;
+                while (e < n && r[e].kind == COP_SGS && r[e].level == nl && r[e].mode == MODE_NORMAL &&
+                       r[e].color == (r[e - 1].color ^ 1))
+                    ++e;
+                o.kind = COP_RUN;
+                o.count = e - q;
+                q = e;
+            } else {
+                ++q;
+            }
+            out.push_back(o);
+        }
+        len[prog] = (int)out.size() - off[prog];
+    }
+    c->rec.swap(out);
+    for (int prog = 0; prog < 2; ++prog) {
+        c->prog_off[prog] = off[prog];
+        c->prog_len[prog] = len[prog];
+    }
+}
+
 int plan_coarse(nmg_ctx *c)
 {
     long maxcells = 1024;
@@ -291,7 +328,7 @@ int plan_coarse(nmg_ctx *c)
     for (int l = 0; l <= c->NL; ++l) c->L[l] = saved[l];
     if (rc) return rc;
     if (c->prog_len[0] > kMaxCoarseOps || c->prog_len[1] > kMaxCoarseOps) {
-        c->lc = -1;                              // too long for LDS: per-level launches
+        c->lc = -1;                              // too long: per-level launches
         c->rec.clear();
         return NMG_OK;
     }
@@ -301,15 +338,21 @@ int plan_coarse(nmg_ctx *c)
         long tot = 0;
         c->l_lds = -1;
         for (int l = c->NL; l >= c->lc; --l) {
-            tot += level_bytes(c->L[l].G, c->ne, c->nc, esz);
+            tot += lds_level_bytes(c->L[l].G, c->ne, c->nc, esz);
             if (tot > kCoarseLdsBytes) break;
             c->l_lds = l;
         }
     }
+    merge_runs(c);
     LevelDev lv[kMaxLevels];
+    long off = 0;
     for (int l = 0; l < kMaxLevels; ++l) {
         const Level &Lv = c->L[l <= c->NL ? l : c->NL];
-        lv[l] = LevelDev{Lv.G, Lv.A, Lv.b, Lv.x};
+        lv[l] = LevelDev{Lv.G, Lv.A, Lv.b, Lv.x, -1};
+        if (c->l_lds >= 0 && l >= c->l_lds && l <= c->NL) {
+            lv[l].lds_off = off;
+            off += lds_level_bytes(Lv.G, c->ne, c->nc, c->f32 ? 4 : 8);
+        }
     }
     size_t ob = sizeof(CoarseOp) * c->rec.size();
     if (hipMalloc(&c->d_ops, ob) != hipSuccess || hipMalloc(&c->d_lv, sizeof lv) != hipSuccess)

@@ -66,27 +66,34 @@ enum SweepMode {
 constexpr int kBlock = 256;
 constexpr int kCoarseBlock = 512;     // one workgroup runs the coarse part of a cycle
 constexpr int kMaxLevels = 16;
-constexpr int kMaxCoarseOps = 1024;  // LDS capacity of the coarse-cycle kernel's op list
+constexpr int kMaxCoarseOps = 1 << 16;  // longest recorded coarse program
 // LDS bytes of the coarse-cycle kernel for level data: the coarsest levels
-// whose blocks and vectors fit are copied in and run from LDS (gfx950 allows
-// 160 KB per workgroup; the op list and level table take the rest).
-constexpr long kCoarseLdsBytes = 140 * 1024;
+// whose blocks, block inverses and vectors fit are copied in and run from
+// LDS (gfx950 allows 160 KB per workgroup).
+constexpr long kCoarseLdsBytes = 160 * 1024;
 
 // Device-side description of one level (for the coarse-cycle kernel); the
 // arrays hold the hierarchy's scalar type (double, or float for the FP32
-// inner V-cycle).
+// inner V-cycle).  lds_off >= 0: byte offset of the level's copy in the
+// kernel's LDS (blocks, then block inverses, then b, then x); -1: the level
+// is used in place in global memory.
 struct LevelDev {
     LevelGeom G;
     void *A, *b, *x;
+    long lds_off;
 };
 
-// One operation of the recorded coarse part of a V-cycle.
-enum CoarseOpKind { COP_SGS = 0, COP_RESTRICT = 1, COP_FIX = 2 };
+// One operation of the recorded coarse part of a cycle.  COP_RUN is count
+// consecutive half sweeps of alternating colour on an LDS-resident level
+// with a thread per cell, the first of them in `mode` (normal or zero start)
+// and the rest normal.
+enum CoarseOpKind { COP_SGS = 0, COP_RESTRICT = 1, COP_FIX = 2, COP_RUN = 3 };
 struct CoarseOp {
     int kind;               // CoarseOpKind
     int level;
-    int color;              // SGS / FIX: colour
-    int mode;               // SGS: SweepMode; FIX: 0 zero, 1 add parent, 2 set parent
+    int color;              // SGS / FIX: colour; RUN: colour of the first half sweep
+    int mode;               // SGS / RUN: SweepMode; FIX: 0 zero, 1 add parent, 2 set parent
+    int count;              // RUN: number of half sweeps
 };
 
 inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
@@ -129,6 +136,17 @@ hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
 inline long level_bytes(const LevelGeom &G, int ne, int nc, long esz)
 {
     return (2 * ne * G.planeP + 2 * 2 * nc * G.plane) * esz;
+}
+
+// Entries of a block's precomputed inverse data: the NC x NC cofactors and
+// the reciprocal determinant.
+__host__ __device__ constexpr int inv_entries(int nc) { return nc * nc + 1; }
+
+// Bytes of one level's LDS copy in the coarse-cycle kernel: level_bytes plus
+// the block inverses of both colours, tiled like the blocks.
+__host__ __device__ inline long lds_level_bytes(const LevelGeom &G, int ne, int nc, long esz)
+{
+    return (2 * ne * G.planeP + 2 * inv_entries(nc) * G.planeP + 2 * 2 * nc * G.plane) * esz;
 }
 
 // Layout conversions between the public FP64 layouts and the colour-split

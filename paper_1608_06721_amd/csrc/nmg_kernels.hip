@@ -246,6 +246,53 @@ __device__ __forceinline__ void solve_block(const T *D, const T *r, T *x)
     x[2] = (C02 * r[0] + C12 * r[1] + C22 * r[2]) * idet;
 }
 
+// Precomputed form of solve_block for blocks that many sweeps reuse: the
+// cofactors in the order the solution products read them and the reciprocal
+// determinant (NaN marks a block whose reciprocal is not finite).  Applying
+// it with solve_inv performs solve_block's final products and sums in the
+// same order, so the result is bit-for-bit the same.
+template <class T, int NC>
+__device__ __forceinline__ void block_inverse(const T *D, T *inv)
+{
+    const T nan = T(__builtin_nan(""));
+    if (NC == 2) {
+        T det = D[0] * D[3] - D[1] * D[2];
+        T idet = T(1) / det;
+        inv[0] = D[3]; inv[1] = D[1]; inv[2] = D[0]; inv[3] = D[2];
+        inv[4] = __builtin_isfinite(idet) ? idet : nan;
+        return;
+    }
+    T d00 = D[0], d01 = D[1], d02 = D[2];
+    T d10 = D[3], d11 = D[4], d12 = D[5];
+    T d20 = D[6], d21 = D[7], d22 = D[8];
+    T C00 = d11 * d22 - d12 * d21, C01 = d12 * d20 - d10 * d22, C02 = d10 * d21 - d11 * d20;
+    T C10 = d02 * d21 - d01 * d22, C11 = d00 * d22 - d02 * d20, C12 = d01 * d20 - d00 * d21;
+    T C20 = d01 * d12 - d02 * d11, C21 = d02 * d10 - d00 * d12, C22 = d00 * d11 - d01 * d10;
+    T det = d00 * C00 + d01 * C01 + d02 * C02;
+    T idet = T(1) / det;
+    inv[0] = C00; inv[1] = C10; inv[2] = C20;
+    inv[3] = C01; inv[4] = C11; inv[5] = C21;
+    inv[6] = C02; inv[7] = C12; inv[8] = C22;
+    inv[9] = __builtin_isfinite(idet) ? idet : nan;
+}
+
+template <class T, int NC>
+__device__ __forceinline__ void solve_inv(const T *inv, const T *r, T *x)
+{
+    const T idet = inv[NC * NC];
+    const bool sing = idet != idet;
+    if (NC == 2) {
+        x[0] = (inv[0] * r[0] - inv[1] * r[1]) * idet;
+        x[1] = (inv[2] * r[1] - inv[3] * r[0]) * idet;
+    } else {
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            x[k] = (inv[3 * k] * r[0] + inv[3 * k + 1] * r[1] + inv[3 * k + 2] * r[2]) * idet;
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) x[k] = sing ? T(0) : x[k];
+}
+
 // Deterministic block reduction of one double per thread; thread 0 of the
 // block receives the sum.  Fixed pairing order, so the result depends only
 // on the block size, never on timing.
@@ -661,13 +708,48 @@ __device__ __forceinline__ void read_other(const LevelGeom &G, const T *xo, int 
     for (int c = 0; c < NC; ++c) v[c] = base[c] + p[c * Gc.plane];
 }
 
+// The arithmetic of one block Gauss-Seidel cell update: acc = sum over the
+// existing neighbours (W, E, S, N order) and components of A_f x_f, then
+// x_i = D_i^-1 (b_i - acc) by solve_block (a holds D) or solve_inv (inv).
+// ZERO: every neighbour value is zero, so acc = 0.
+template <class T, int NC, bool ZERO, bool INV>
+__device__ __forceinline__ void gs_update(const T *a, const T *inv, const T *bv,
+                                          const T (*v)[NC], const bool *ok, T *xi)
+{
+    constexpr int NF = (NC == 2) ? 2 : 4;
+    T acc[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) acc[r] = T(0);
+    if (!ZERO) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (!ok[f]) continue;
+#pragma unroll
+            for (int r = 0; r < NC; ++r)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[r] = acc[r] + a[((f + 1) * NC + r) * NC + c] * v[f][c];
+        }
+    }
+    T rhs[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) rhs[r] = bv[r] - acc[r];
+    if (INV)
+        solve_inv<T, NC>(inv, rhs, xi);
+    else
+        solve_block<T, NC>(a, rhs, xi);
+}
+
 // Block Gauss-Seidel half sweep of one colour: x_i = D_i^-1 (b_i - sum_j
 // A_ij x_j), the sum over existing neighbours in W, E, S, N order and then
 // components.  One thread per cell of the colour, coalesced along x.  All
 // loads of a cell (its block row, b_i and the neighbours' x) are issued
 // before any arithmetic, so each wave keeps ~50 independent loads in flight.
-template <class T, int NC, int MODE>
+// INV: the diagonal block is applied through its precomputed inverse data
+// Ai (tiled like A, inv_entries(NC) entries per slot) instead of solve_block.
+template <class T, int NC, int MODE, bool INV = false>
 __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const T *__restrict__ A,
+                                         const T *__restrict__ Ai,
                                          const T *__restrict__ b, T *__restrict__ x,
                                          int color, const LevelGeom &Gc,
                                          const T *__restrict__ xc, long t)
@@ -675,6 +757,7 @@ __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const T *__restrict
     constexpr int NF = (NC == 2) ? 2 : 4;
     constexpr int NN = NC * NC;
     constexpr int NE = (NF + 1) * NN;
+    constexpr int NI = inv_entries(NC);
     const int j = (int)(t / G.W), k = (int)(t % G.W);
     const int i = 2 * k + ((j + color) & 1);
     if (i >= G.nx) return;
@@ -694,9 +777,15 @@ __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const T *__restrict
         else if (f == FS) { nj[f] = j - 1; ok[f] = j > 0; }
         else { nj[f] = j + 1; ok[f] = j + 1 < G.ny; }
     }
-    T a[NE], bv[NC], v[NF][NC];
+    T a[NE], bv[NC], v[NF][NC], inv[NI];
+    if (INV) {
+        const T *Im = Ai + mat_off(G, NI, color, t);
 #pragma unroll
-    for (int e = 0; e < NN; ++e) a[e] = Am[e * kTile];
+        for (int e = 0; e < NI; ++e) inv[e] = Im[e * kTile];
+    } else {
+#pragma unroll
+        for (int e = 0; e < NN; ++e) a[e] = Am[e * kTile];
+    }
 #pragma unroll
     for (int r = 0; r < NC; ++r) bv[r] = bm[r * G.plane];
     if (MODE != MODE_ZERO) {
@@ -712,24 +801,8 @@ __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const T *__restrict
             }
         }
     }
-    T acc[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) acc[r] = T(0);
-    if (MODE != MODE_ZERO) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            if (!ok[f]) continue;
-#pragma unroll
-            for (int r = 0; r < NC; ++r)
-#pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    acc[r] = acc[r] + a[((f + 1) * NC + r) * NC + c] * v[f][c];
-        }
-    }
-    T rhs[NC], xi[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) rhs[r] = bv[r] - acc[r];
-    solve_block<T, NC>(a, rhs, xi);
+    T xi[NC];
+    gs_update<T, NC, MODE == MODE_ZERO, INV>(a, inv, bv, v, ok, xi);
     T *xm = x + (long)color * NC * G.plane + t;
 #pragma unroll
     for (int r = 0; r < NC; ++r) xm[r * G.plane] = xi[r];
@@ -743,7 +816,7 @@ __global__ void __launch_bounds__(kBlock) k_sgs_half(LevelGeom G, const T *__res
 {
     long t = (long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= G.plane) return;
-    sgs_cell<T, NC, MODE>(G, A, b, x, color, Gc, xc, t);
+    sgs_cell<T, NC, MODE>(G, A, nullptr, b, x, color, Gc, xc, t);
 }
 
 // Linear residual of fine cell (i, j): b - (D x_i + sum_nbr A x_nbr).
@@ -930,71 +1003,199 @@ __global__ void __launch_bounds__(kBlock) k_fix_color(LevelGeom G, int op, T *__
     fix_cell<T, NC>(G, op, x, color, Gc, xc, t);
 }
 
-// The coarse levels of a V-cycle in one workgroup: the host records the
-// exact sequence of half sweeps, restrictions and colour fixes that the
+// A pointer known to address global memory: the round trip through the
+// global address space lets the compiler use global (not generic) loads and
+// stores for everything derived from it.
+template <class T>
+__device__ __forceinline__ T *in_global(T *p)
+{
+    return (T *)(__attribute__((address_space(1))) T *)p;
+}
+
+// One recorded operation on level G (blocks A, inverse data Ai when INV,
+// vectors b, x) with the next coarser level's b and x (bc, xc).
+template <class T, int NC, bool INV>
+__device__ __forceinline__ void coarse_op(const CoarseOp &op, const LevelGeom &G,
+                                          const LevelGeom &Gc, const T *A, const T *Ai, const T *b,
+                                          T *x, T *bc, const T *xc)
+{
+    if (op.kind == COP_SGS) {
+        for (long t = threadIdx.x; t < G.plane; t += kCoarseBlock) {
+            switch (op.mode) {
+            case MODE_NORMAL:
+                sgs_cell<T, NC, MODE_NORMAL, INV>(G, A, Ai, b, x, op.color, Gc, xc, t);
+                break;
+            case MODE_ZERO:
+                sgs_cell<T, NC, MODE_ZERO, INV>(G, A, Ai, b, x, op.color, Gc, xc, t);
+                break;
+            case MODE_PROLONG:
+                sgs_cell<T, NC, MODE_PROLONG, INV>(G, A, Ai, b, x, op.color, Gc, xc, t);
+                break;
+            default:
+                sgs_cell<T, NC, MODE_PROLONG_ZERO, INV>(G, A, Ai, b, x, op.color, Gc, xc, t);
+                break;
+            }
+        }
+    } else if (op.kind == COP_RESTRICT) {
+        for (long t = threadIdx.x; t < (long)Gc.nx * Gc.ny; t += kCoarseBlock)
+            restrict_cell<T, NC>(G, A, b, x, Gc, bc, t);
+    } else {
+        for (long t = threadIdx.x; t < G.plane; t += kCoarseBlock)
+            fix_cell<T, NC>(G, op.mode, x, op.color, Gc, xc, t);
+    }
+}
+
+// A run of op.count alternating half sweeps on an LDS-resident level whose
+// cells all have a thread (2 * plane <= kCoarseBlock): colour op.color ^ (s & 1)
+// at step s, the first in op.mode (normal or zero start), the rest normal.
+// Each thread keeps its cell's off-diagonal blocks, block inverse and
+// right-hand side in registers for the whole run, so a half sweep is the
+// neighbour reads, the update and one write of x, all in LDS.
+template <class T, int NC>
+__device__ __forceinline__ void coarse_run(const CoarseOp &op, const LevelGeom &G, const T *A,
+                                           const T *Ai, const T *b, T *x)
+{
+    constexpr int NF = (NC == 2) ? 2 : 4;
+    constexpr int NN = NC * NC;
+    constexpr int NE = (NF + 1) * NN;
+    constexpr int NI = inv_entries(NC);
+    const int plane = (int)G.plane;
+    const int tau = (int)threadIdx.x;
+    const int color = tau < plane ? 0 : 1;
+    const int t = tau - color * plane;
+    const int j = t / G.W, k = t - (t / G.W) * G.W;
+    const int i = 2 * k + ((j + color) & 1);
+    const bool mine = tau < 2 * plane && i < G.nx;
+    bool ok[NF];
+    int nb[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        int ni = i, nj = j;
+        if (f == FW) { ni = i - 1; ok[f] = i > 0; }
+        else if (f == FE) { ni = i + 1; ok[f] = i + 1 < G.nx; }
+        else if (f == FS) { nj = j - 1; ok[f] = j > 0; }
+        else { nj = j + 1; ok[f] = j + 1 < G.ny; }
+        nb[f] = nj * G.W + (ni >> 1);
+    }
+    T a[NE], inv[NI], bv[NC];
+    if (mine) {
+        const T *Am = A + mat_off(G, NE, color, t);
+        const T *Im = Ai + mat_off(G, NI, color, t);
+#pragma unroll
+        for (int e = NN; e < NE; ++e) a[e] = Am[e * kTile];
+#pragma unroll
+        for (int e = 0; e < NI; ++e) inv[e] = Im[e * kTile];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) bv[r] = b[(color * NC + r) * plane + t];
+    }
+    const T *xo = x + (color ^ 1) * NC * plane;
+    T *xm = x + color * NC * plane + t;
+    for (int s = 0; s < op.count; ++s) {
+        if (mine && color == (op.color ^ (s & 1))) {
+            T v[NF][NC], xi[NC];
+            if (s == 0 && op.mode == MODE_ZERO) {
+                gs_update<T, NC, true, true>(a, inv, bv, v, ok, xi);
+            } else {
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) v[f][c] = ok[f] ? xo[c * plane + nb[f]] : T(0);
+                gs_update<T, NC, false, true>(a, inv, bv, v, ok, xi);
+            }
+#pragma unroll
+            for (int r = 0; r < NC; ++r) xm[r * plane] = xi[r];
+        }
+        if (s + 1 < op.count) __syncthreads();
+    }
+}
+
+// Pointers into a level's LDS copy (layout of LevelDev::lds_off).
+template <class T, int NC>
+struct LdsLevel {
+    T *A, *Ai, *b, *x;
+    __device__ __forceinline__ LdsLevel(char *lds, const LevelDev &L)
+    {
+        constexpr int NE = ((NC == 2) ? 3 : 5) * NC * NC;
+        A = (T *)(lds + L.lds_off);
+        Ai = A + 2L * NE * L.G.planeP;
+        b = Ai + 2L * inv_entries(NC) * L.G.planeP;
+        x = b + 2L * NC * L.G.plane;
+    }
+};
+
+// The coarse levels of a cycle in one workgroup: the host records the exact
+// sequence of half sweeps, restrictions and colour fixes that the
 // level-by-level launches would perform, and this kernel executes it with a
-// workgroup barrier between operations.  Levels l_lds..nl are first copied
-// into LDS and their results copied back at the end, so the many operations
-// on the smallest levels run at LDS latency (the arithmetic is unchanged).
+// workgroup barrier between operations.  The coarsest levels (those with
+// lds_off >= 0) are first copied into LDS together with their blocks'
+// inverse data, so their many half sweeps run at LDS latency without a
+// division; their vectors are copied back at the end.  Every pointer is
+// formed in the branch that uses it, from the LDS array or from the level
+// table, so each access compiles to an LDS or a global load, never a generic
+// one.  The operation list and level table are read with uniform loads.
 template <class T, int NC>
 __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *__restrict__ ops,
                                                                int nops,
-                                                               const LevelDev *__restrict__ lv_g,
+                                                               const LevelDev *__restrict__ lv,
                                                                int l_lds, int nl)
 {
     constexpr int NF = (NC == 2) ? 2 : 4;
-    constexpr int NE = (NF + 1) * NC * NC;
-    __shared__ CoarseOp sops[kMaxCoarseOps];
-    __shared__ LevelDev lv[kMaxLevels];
+    constexpr int NN = NC * NC;
+    constexpr int NE = (NF + 1) * NN;
+    constexpr int NI = inv_entries(NC);
     __shared__ __attribute__((aligned(16))) char lds[kCoarseLdsBytes];
-    for (int q = threadIdx.x; q < nops; q += kCoarseBlock) sops[q] = ops[q];
-    for (int q = threadIdx.x; q < kMaxLevels; q += kCoarseBlock) lv[q] = lv_g[q];
-    __syncthreads();
     if (l_lds >= 0) {
-        long off = 0;
         for (int l = l_lds; l <= nl; ++l) {
-            const LevelGeom G = lv_g[l].G;
-            const long na = 2L * NE * G.planeP, nv = 2L * NC * G.plane;
-            T *A = (T *)(lds + off), *b = A + na, *x = b + nv;
-            const T *gA = (const T *)lv_g[l].A, *gb = (const T *)lv_g[l].b, *gx = (const T *)lv_g[l].x;
-            for (long k = threadIdx.x; k < na; k += kCoarseBlock) A[k] = gA[k];
-            for (long k = threadIdx.x; k < nv; k += kCoarseBlock) { b[k] = gb[k]; x[k] = gx[k]; }
-            if (threadIdx.x == 0) { lv[l].A = A; lv[l].b = b; lv[l].x = x; }
-            off += (na + 2 * nv) * (long)sizeof(T);
+            const LevelDev &L = lv[l];
+            const LdsLevel<T, NC> S(lds, L);
+            const long na = 2L * NE * L.G.planeP, nv = 2L * NC * L.G.plane;
+            const T *gA = in_global((const T *)L.A), *gb = in_global((const T *)L.b);
+            const T *gx = in_global((const T *)L.x);
+            for (long k = threadIdx.x; k < na; k += kCoarseBlock) S.A[k] = gA[k];
+            for (long k = threadIdx.x; k < nv; k += kCoarseBlock) { S.b[k] = gb[k]; S.x[k] = gx[k]; }
+            for (long k = threadIdx.x; k < 2L * L.G.planeP; k += kCoarseBlock) {
+                const int color = (int)(k / L.G.planeP);
+                const long t = k % L.G.planeP;
+                const T *Dm = gA + mat_off(L.G, NE, color, t);
+                T D[NN], inv[NI];
+#pragma unroll
+                for (int e = 0; e < NN; ++e) D[e] = Dm[e * kTile];
+                block_inverse<T, NC>(D, inv);
+                T *Im = S.Ai + mat_off(L.G, NI, color, t);
+#pragma unroll
+                for (int e = 0; e < NI; ++e) Im[e * kTile] = inv[e];
+            }
         }
         __syncthreads();
     }
     for (int q = 0; q < nops; ++q) {
-        const CoarseOp op = sops[q];
+        const CoarseOp op = ops[q];
         const LevelDev &Ld = lv[op.level];
-        const LevelDev &Lcd = lv[op.level + 1 < kMaxLevels ? op.level + 1 : op.level];
-        const LevelGeom G = Ld.G, Gc = Lcd.G;
-        T *A = (T *)Ld.A, *b = (T *)Ld.b, *x = (T *)Ld.x;
-        T *bcz = (T *)Lcd.b, *xc = (T *)Lcd.x;
-        if (op.kind == COP_SGS) {
-            for (long t = threadIdx.x; t < G.plane; t += kCoarseBlock) {
-                switch (op.mode) {
-                case MODE_NORMAL: sgs_cell<T, NC, MODE_NORMAL>(G, A, b, x, op.color, Gc, xc, t); break;
-                case MODE_ZERO: sgs_cell<T, NC, MODE_ZERO>(G, A, b, x, op.color, Gc, xc, t); break;
-                case MODE_PROLONG: sgs_cell<T, NC, MODE_PROLONG>(G, A, b, x, op.color, Gc, xc, t); break;
-                default: sgs_cell<T, NC, MODE_PROLONG_ZERO>(G, A, b, x, op.color, Gc, xc, t); break;
-                }
-            }
-        } else if (op.kind == COP_RESTRICT) {
-            for (long t = threadIdx.x; t < (long)Gc.nx * Gc.ny; t += kCoarseBlock)
-                restrict_cell<T, NC>(G, A, b, x, Gc, bcz, t);
+        const LevelDev &Lc = lv[op.level < nl ? op.level + 1 : op.level];
+        if (op.kind == COP_RUN) {
+            const LdsLevel<T, NC> F(lds, Ld);
+            coarse_run<T, NC>(op, Ld.G, F.A, F.Ai, F.b, F.x);
+        } else if (Ld.lds_off >= 0) {
+            const LdsLevel<T, NC> F(lds, Ld), Cl(lds, Lc);
+            coarse_op<T, NC, true>(op, Ld.G, Lc.G, F.A, F.Ai, F.b, F.x, Cl.b, Cl.x);
+        } else if (Lc.lds_off >= 0) {
+            const LdsLevel<T, NC> Cl(lds, Lc);
+            coarse_op<T, NC, false>(op, Ld.G, Lc.G, in_global((const T *)Ld.A), nullptr,
+                                    in_global((const T *)Ld.b), in_global((T *)Ld.x), Cl.b, Cl.x);
         } else {
-            for (long t = threadIdx.x; t < G.plane; t += kCoarseBlock)
-                fix_cell<T, NC>(G, op.mode, x, op.color, Gc, xc, t);
+            coarse_op<T, NC, false>(op, Ld.G, Lc.G, in_global((const T *)Ld.A), nullptr,
+                                    in_global((const T *)Ld.b), in_global((T *)Ld.x),
+                                    in_global((T *)Lc.b), in_global((const T *)Lc.x));
         }
         __syncthreads();
     }
     if (l_lds >= 0) {
         for (int l = l_lds; l <= nl; ++l) {
-            const long nv = 2L * NC * lv_g[l].G.plane;
-            const T *b = (const T *)lv[l].b, *x = (const T *)lv[l].x;
-            T *gb = (T *)lv_g[l].b, *gx = (T *)lv_g[l].x;
-            for (long k = threadIdx.x; k < nv; k += kCoarseBlock) { gb[k] = b[k]; gx[k] = x[k]; }
+            const LevelDev &L = lv[l];
+            const LdsLevel<T, NC> S(lds, L);
+            const long nv = 2L * NC * L.G.plane;
+            T *gb = in_global((T *)L.b), *gx = in_global((T *)L.x);
+            for (long k = threadIdx.x; k < nv; k += kCoarseBlock) { gb[k] = S.b[k]; gx[k] = S.x[k]; }
         }
     }
 }
