@@ -32,16 +32,24 @@ SGS_BYTES_2D = 45 * 8 + 24 + 24 + 24
 SGS_BYTES_2D_FP32 = 45 * 4 + 12 + 12 + 12
 
 
+def sgs_source_digest():
+    """sha256 (first 16 hex digits) of the sources the block SGS half-sweep
+    kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("nmg_sgs.h", "nmg_internal.h"):
+        h.update(open(os.path.join(HERE, "paper_1608_06721_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per finest-level SGS launch from the committed rocprofv3
-    counter runs, or None if the kernel source changed since they were taken."""
-    import hashlib
+    counter runs, or None if the kernel's sources changed since they were taken."""
     prof = os.path.join(HERE, "profiles", "sgs_halfsweep_channel1024_f64_pmc.md")
-    src = os.path.join(HERE, "paper_1608_06721_amd", "csrc", "nmg_kernels.hip")
     try:
         fields = dict(l.split(":", 1) for l in open(prof).read().splitlines()
                       if l.startswith(("kernel_source_sha256_16:", "traffic_bytes_per_launch:")))
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        digest = sgs_source_digest()
         if fields["kernel_source_sha256_16"].strip() != digest:
             return None
         return float(fields["traffic_bytes_per_launch"])
