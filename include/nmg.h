@@ -187,6 +187,43 @@ int nmg_timing_enable(nmg_ctx *ctx, int enable, int cap);
 int nmg_timing_read(nmg_ctx *ctx, double *sgs_ms_host, int *sgs_launches_host,
                     long long *sgs_cells_host);
 
+/* ---- Batches of independent problems --------------------------------------
+ * A batch solves n independent steady problems (Algorithm 1 on each) of
+ * possibly different grid sizes and boundary data but one parameter set, in
+ * lockstep: every operation of the Newton step and of the multigrid cycle is
+ * one launch over a work list of (instance, tile) items of all instances
+ * still iterating, and the coarse part of each cycle runs one workgroup per
+ * instance.  Every instance's iterates, statuses and step counts are those
+ * of its own nmg_newton_mg_solve with the same grid, BC and parameters, bit
+ * for bit; an instance leaves the lockstep when its own stop test ends it.
+ * Requirements: all grids have the same dim, and each satisfies
+ * nmg_create's rules with params->n_levels. */
+typedef struct nmg_batch nmg_batch;
+
+/* grids[n], bcs[n] (host arrays), one params for all instances, stream as in
+ * nmg_create.  Allocates one hierarchy per instance plus the work lists. */
+int nmg_batch_create(int n, const nmg_grid *grids, const nmg_bc *bcs,
+                     const nmg_params *params, void *stream, nmg_batch **out);
+void nmg_batch_destroy(nmg_batch *batch);
+const char *nmg_batch_last_error(const nmg_batch *batch);
+
+/* Tile-length autotuner of the batched block SGS half sweep: for every
+ * level launched on its own (the coarse-kernel levels excepted), times
+ * `reps` (1..1000) half sweeps with each tile length 64, 128, 256 and 512
+ * cells on this batch's hierarchy and keeps the fastest.  Results do not
+ * depend on the choice.  tiles_host (nullable, n_levels + 1 ints) receives
+ * the chosen lengths.  Synchronizes the stream. */
+int nmg_batch_autotune(nmg_batch *batch, int reps, int *tiles_host);
+
+/* Newton multigrid solves of every instance: z[k], U[k] are device pointers
+ * (the host arrays z, U hold n of them) with the layouts of
+ * nmg_newton_mg_solve; U[k] in: U0, out: the returned iterate.  stats (host,
+ * n entries, nullable) receives each instance's result as
+ * nmg_newton_mg_solve would.  Returns NMG_OK if every instance converged,
+ * NMG_NOT_CONVERGED if any did not (see stats), or an error. */
+int nmg_batch_newton_mg_solve(nmg_batch *batch, const double *const *z, double *const *U,
+                              double tol, nmg_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,6 +36,8 @@ struct Level {
 
 }  // namespace
 
+struct nmg_batch;
+
 struct nmg_ctx {
     nmg_grid grid;
     nmg_bc bc;
@@ -65,6 +67,31 @@ struct nmg_ctx {
     int l_lds = -1;                   // levels l_lds..NL run from LDS in the coarse kernel
     CoarseOp *d_ops = nullptr;
     LevelDev *d_lv = nullptr;
+    // set on the first instance of a batch: its state machine then drives
+    // batched launches over every instance
+    nmg_batch *batch = nullptr;
+};
+
+struct nmg_batch {
+    int n = 0, dim = 0, nc = 0, NL = 0;
+    bool f32 = false;
+    hipStream_t stream = nullptr;
+    nmg_params prm;
+    std::string err;
+    std::vector<nmg_ctx *> inst;          // inst[0]'s state machine drives the batch
+    std::vector<BatchInst> h_inst;
+    BatchInst *d_inst = nullptr;
+    BatchLevel *d_lv = nullptr;           // [(NL + 1) * n], level-major
+    LevelDev *d_clv = nullptr;            // [n * kMaxLevels] coarse-kernel level tables
+    WorkItem *d_work = nullptr;
+    WorkRange w_cells0{nullptr, 0};       // 256-cell tiles of level 0
+    WorkRange w_plane[kMaxLevels][kNumTiles];   // colour-plane tiles per tile length
+    WorkRange w_ccells[kMaxLevels];       // 256-cell tiles of level l (restriction into l, Galerkin)
+    int tile[kMaxLevels];                 // tile length of the half sweeps per level
+    int *d_active = nullptr, *h_active = nullptr;   // instances still iterating
+    int *d_mask = nullptr, *h_mask = nullptr;       // a second instance mask
+    int *d_roff = nullptr, *d_rcnt = nullptr;       // each instance's level-0 tiles
+    double *d_partial = nullptr, *d_norm = nullptr, *h_norm = nullptr;
 };
 
 namespace {
@@ -151,6 +178,17 @@ int halfsweep(nmg_ctx *c, int l, int color)
         Lv.last = color;
         return NMG_OK;
     }
+    if (c->batch) {
+        nmg_batch *B = c->batch;
+        const int tl = B->tile[l];
+        int ti = 0;
+        while (kTileChoices[ti] != tl) ++ti;
+        HIPCHK(c, launch_b_sgs_half(c->dim, c->f32, mode, tl, B->d_lv + (long)l * B->n,
+                                    B->w_plane[l][ti], B->d_active, color, c->stream));
+        Lv.st[color] = ST_VALID;
+        Lv.last = color;
+        return NMG_OK;
+    }
     // Measurement hook: only full half sweeps (all neighbour blocks read)
     // of the finest level are recorded.
     const int k = c->nrec;
@@ -192,10 +230,17 @@ int materialize(nmg_ctx *c, int l)
         else if (Lv.st[color] == ST_VALID_PP) op = 1;
         else if (Lv.st[color] == ST_ZERO_PP) op = 2;
         if (op < 0) continue;
-        if (c->recording)
+        if (c->recording) {
             c->rec.push_back(CoarseOp{COP_FIX, l, color, op});
-        else
+        } else if (c->batch) {
+            nmg_batch *B = c->batch;
+            int ti = 0;
+            while (kTileChoices[ti] != kBlock) ++ti;
+            HIPCHK(c, launch_b_fix_color(c->dim, c->f32, op, B->d_lv + (long)l * B->n,
+                                         B->w_plane[l][ti], B->d_active, color, c->stream));
+        } else {
             HIPCHK(c, launch_fix_color(c->dim, c->f32, op, Lv.G, Lv.x, color, Lc.G, Lc.x, c->stream));
+        }
         Lv.st[color] = ST_VALID;
         Lv.last = -1;
     }
@@ -222,9 +267,14 @@ int cycle(nmg_ctx *c, int l)
         int prog = (st0 == ST_ZERO && st1 == ST_ZERO) ? 0
                    : (st0 == ST_VALID && st1 == ST_VALID) ? 1 : -1;
         if (prog >= 0 && c->prog_len[prog] > 0) {
-            HIPCHK(c, launch_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[prog],
-                                          c->prog_len[prog], c->d_lv, c->l_lds, c->NL,
-                                          c->stream));
+            if (c->batch)
+                HIPCHK(c, launch_b_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[prog],
+                                                c->prog_len[prog], c->batch->d_clv, c->batch->n,
+                                                c->batch->d_active, c->l_lds, c->NL, c->stream));
+            else
+                HIPCHK(c, launch_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[prog],
+                                              c->prog_len[prog], c->d_lv, c->l_lds, c->NL,
+                                              c->stream));
             c->L[l].st[0] = c->L[l].st[1] = ST_VALID;
             c->L[l].last = -1;
             return NMG_OK;
@@ -239,6 +289,9 @@ int cycle(nmg_ctx *c, int l)
         Level &Lc = c->L[l + 1];
         if (c->recording)
             c->rec.push_back(CoarseOp{COP_RESTRICT, l, 0, 0});
+        else if (c->batch)
+            HIPCHK(c, launch_b_restrict(c->dim, c->f32, c->batch->d_lv + (long)l * c->batch->n,
+                                        c->batch->w_ccells[l + 1], c->batch->d_active, c->stream));
         else
             HIPCHK(c, launch_restrict(c->dim, c->f32, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b, c->stream));
         set_zero(c, l + 1);
@@ -257,9 +310,14 @@ int cycle(nmg_ctx *c, int l)
 
 int build_coarse(nmg_ctx *c)
 {
-    for (int l = 1; l <= c->NL; ++l)
-        HIPCHK(c, launch_galerkin(c->dim, c->f32, c->L[l - 1].G, c->L[l - 1].A, c->L[l].G,
-                                  c->L[l].A, c->stream));
+    for (int l = 1; l <= c->NL; ++l) {
+        if (c->batch)
+            HIPCHK(c, launch_b_galerkin(c->dim, c->f32, c->batch->d_lv + (long)(l - 1) * c->batch->n,
+                                        c->batch->w_ccells[l], c->batch->d_active, c->stream));
+        else
+            HIPCHK(c, launch_galerkin(c->dim, c->f32, c->L[l - 1].G, c->L[l - 1].A, c->L[l].G,
+                                      c->L[l].A, c->stream));
+    }
     for (int l = 0; l <= c->NL; ++l) set_zero(c, l);
     return NMG_OK;
 }
@@ -269,10 +327,10 @@ int build_coarse(nmg_ctx *c)
 // Replace each maximal sequence of alternating half sweeps on the coarsest
 // level (normal, or zero start first) by one COP_RUN, when that level is in
 // LDS and has a thread per cell in the coarse-cycle kernel.
-void merge_runs(nmg_ctx *c)
+void merge_runs(nmg_ctx *c, bool fits)
 {
     const int nl = c->NL;
-    if (c->l_lds < 0 || 2 * c->L[nl].G.plane > kCoarseBlock) return;
+    if (c->l_lds < 0 || !fits) return;
     std::vector<CoarseOp> out;
     int off[2], len[2];
     for (int prog = 0; prog < 2; ++prog) {
@@ -303,14 +361,55 @@ void merge_runs(nmg_ctx *c)
     }
 }
 
-int plan_coarse(nmg_ctx *c)
+long coarse_cells_limit()
 {
     long maxcells = 1024;
     if (const char *e = std::getenv("NMG_COARSE_CELLS")) maxcells = std::atol(e);
-    c->lc = -1;
+    return maxcells;
+}
+
+// First level at or below which the cycle runs in the coarse-cycle kernel.
+int first_coarse_level(const nmg_ctx *c)
+{
+    const long maxcells = coarse_cells_limit();
     for (int l = 1; l <= c->NL; ++l)
-        if (cells(c->L[l].G) <= maxcells) { c->lc = l; break; }
-    if (c->lc < 0) return NMG_OK;
+        if (cells(c->L[l].G) <= maxcells) return l;
+    return -1;
+}
+
+// Coarsest-first levels whose LDS copies fit the kernel (l_lds..NL), or -1.
+int lds_first_level(const nmg_ctx *c, int lc)
+{
+    const long esz = c->f32 ? 4 : 8;
+    long tot = 0;
+    int l_lds = -1;
+    for (int l = c->NL; l >= lc; --l) {
+        tot += lds_level_bytes(c->L[l].G, c->ne, c->nc, esz);
+        if (tot > kCoarseLdsBytes) break;
+        l_lds = l;
+    }
+    return l_lds;
+}
+
+// The coarse-kernel level table of context c with levels l_lds..NL in LDS.
+void coarse_level_table(const nmg_ctx *c, int l_lds, LevelDev *lv)
+{
+    long off = 0;
+    for (int l = 0; l < kMaxLevels; ++l) {
+        const Level &Lv = c->L[l <= c->NL ? l : c->NL];
+        lv[l] = LevelDev{Lv.G, Lv.A, Lv.b, Lv.x, -1};
+        if (l_lds >= 0 && l >= l_lds && l <= c->NL) {
+            lv[l].lds_off = off;
+            off += lds_level_bytes(Lv.G, c->ne, c->nc, c->f32 ? 4 : 8);
+        }
+    }
+}
+
+// Record the two coarse programs of context c from level c->lc (with the
+// LDS plan c->l_lds) and upload the operation list.  fits: the coarsest level
+// has a thread per cell (merged runs allowed).
+int record_coarse(nmg_ctx *c, bool fits)
+{
     Level saved[16];
     for (int l = 0; l <= c->NL; ++l) saved[l] = c->L[l];
     c->rec.clear();
@@ -332,32 +431,23 @@ int plan_coarse(nmg_ctx *c)
         c->rec.clear();
         return NMG_OK;
     }
-    // the coarsest levels whose data fit the kernel's LDS run from LDS
-    {
-        const long esz = c->f32 ? 4 : 8;
-        long tot = 0;
-        c->l_lds = -1;
-        for (int l = c->NL; l >= c->lc; --l) {
-            tot += lds_level_bytes(c->L[l].G, c->ne, c->nc, esz);
-            if (tot > kCoarseLdsBytes) break;
-            c->l_lds = l;
-        }
-    }
-    merge_runs(c);
-    LevelDev lv[kMaxLevels];
-    long off = 0;
-    for (int l = 0; l < kMaxLevels; ++l) {
-        const Level &Lv = c->L[l <= c->NL ? l : c->NL];
-        lv[l] = LevelDev{Lv.G, Lv.A, Lv.b, Lv.x, -1};
-        if (c->l_lds >= 0 && l >= c->l_lds && l <= c->NL) {
-            lv[l].lds_off = off;
-            off += lds_level_bytes(Lv.G, c->ne, c->nc, c->f32 ? 4 : 8);
-        }
-    }
+    merge_runs(c, fits);
     size_t ob = sizeof(CoarseOp) * c->rec.size();
-    if (hipMalloc(&c->d_ops, ob) != hipSuccess || hipMalloc(&c->d_lv, sizeof lv) != hipSuccess)
-        return fail(c, NMG_ENOMEM, "coarse-cycle tables");
+    if (hipMalloc(&c->d_ops, ob) != hipSuccess) return fail(c, NMG_ENOMEM, "coarse-cycle program");
     HIPCHK(c, hipMemcpy(c->d_ops, c->rec.data(), ob, hipMemcpyHostToDevice));
+    return NMG_OK;
+}
+
+int plan_coarse(nmg_ctx *c)
+{
+    c->lc = first_coarse_level(c);
+    if (c->lc < 0) return NMG_OK;
+    c->l_lds = lds_first_level(c, c->lc);
+    int rc = record_coarse(c, 2 * c->L[c->NL].G.plane <= kCoarseBlock);
+    if (rc || c->lc < 0) return rc;
+    LevelDev lv[kMaxLevels];
+    coarse_level_table(c, c->l_lds, lv);
+    if (hipMalloc(&c->d_lv, sizeof lv) != hipSuccess) return fail(c, NMG_ENOMEM, "coarse-cycle tables");
     HIPCHK(c, hipMemcpy(c->d_lv, lv, sizeof lv, hipMemcpyHostToDevice));
     return NMG_OK;
 }
@@ -394,6 +484,9 @@ int count_pinned(nmg_ctx *c, const double *z, const double *U, int *n)
     return rc;
 }
 
+int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params, void *stream,
+               bool plan, nmg_ctx **out);
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -404,6 +497,16 @@ int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
 {
     if (!out) return NMG_EINVAL;
     *out = nullptr;
+    return create_ctx(grid, bc, params, stream, true, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params, void *stream,
+               bool plan, nmg_ctx **out)
+{
     std::string msg;
     int rc = check_params(grid, bc, params, msg);
     if (rc) return rc;
@@ -482,7 +585,7 @@ int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
         nmg_destroy(c);
         return NMG_ENOMEM;
     }
-    rc = plan_coarse(c);
+    rc = plan ? plan_coarse(c) : NMG_OK;
     if (rc) {
         nmg_destroy(c);
         return rc;
@@ -490,6 +593,10 @@ int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     *out = c;
     return NMG_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 void nmg_destroy(nmg_ctx *c)
 {
@@ -675,6 +782,401 @@ int nmg_timing_read(nmg_ctx *c, double *ms_host, int *launches_host, long long *
     if (ms_host) *ms_host = tot;
     if (launches_host) *launches_host = c->nrec;
     if (cells_host) *cells_host = cl;
+    return NMG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent problems.  Every instance has its own hierarchy
+// (its own context); the first instance's state machine issues each
+// operation of Algorithm 0 and Algorithm 1 once, and each operation is one
+// launch over a work list of (instance, tile) items covering every instance
+// still iterating.  All instances share the solver parameters, so the
+// sequence of operations is the same for each; the coarse-cycle kernel runs
+// one workgroup per instance.
+
+namespace {
+
+int bfail(nmg_batch *b, int code, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return bfail(b, NMG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+// Error of the driving context (its state machine's launches) moved to the batch.
+int bctx(nmg_batch *b, int rc)
+{
+    if (rc) b->err = b->inst[0]->err;
+    return rc;
+}
+
+struct RangeBuilder {
+    std::vector<WorkItem> items;
+    std::vector<std::pair<WorkRange *, long>> refs;
+    // For each instance k, ceil(units[k] / tile) consecutive items.
+    void add(WorkRange *w, const std::vector<long> &units, int tile)
+    {
+        const long off = (long)items.size();
+        for (size_t k = 0; k < units.size(); ++k) {
+            const long nt = (units[k] + tile - 1) / tile;
+            for (long t = 0; t < nt; ++t) items.push_back(WorkItem{(int)k, (int)t});
+        }
+        w->n = (int)((long)items.size() - off);
+        refs.emplace_back(w, off);
+    }
+};
+
+int upload_mask(nmg_batch *b, int *d, const int *h)
+{
+    BHIPCHK(b, hipMemcpyAsync(d, h, sizeof(int) * b->n, hipMemcpyHostToDevice, b->stream));
+    return NMG_OK;
+}
+
+// Per-instance sums of the level-0 partials into h_norm (synchronizes).
+int batch_norms(nmg_batch *b, const int *d_which)
+{
+    BHIPCHK(b, launch_b_reduce(b->d_partial, b->d_roff, b->d_rcnt, b->n, d_which, b->d_norm,
+                               b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->h_norm, b->d_norm, sizeof(double) * b->n, hipMemcpyDeviceToHost,
+                              b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    return NMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nmg_batch_create(int n, const nmg_grid *grids, const nmg_bc *bcs, const nmg_params *params,
+                     void *stream, nmg_batch **out)
+{
+    if (!out) return NMG_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > 65536 || !grids || !bcs || !params) return NMG_EINVAL;
+    for (int k = 1; k < n; ++k)
+        if (grids[k].dim != grids[0].dim) return NMG_EINVAL;
+    nmg_batch *b = new (std::nothrow) nmg_batch();
+    if (!b) return NMG_ENOMEM;
+    b->n = n;
+    b->stream = (hipStream_t)stream;
+    b->prm = *params;
+    b->dim = grids[0].dim;
+    b->nc = b->dim == 1 ? 2 : 3;
+    b->NL = params->n_levels;
+    b->f32 = params->inner_fp32 != 0;
+    for (int l = 0; l < kMaxLevels; ++l) b->tile[l] = kBlock;
+    for (int k = 0; k < n; ++k) {
+        nmg_ctx *c = nullptr;
+        int rc = create_ctx(&grids[k], &bcs[k], params, stream, false, &c);
+        if (rc) {
+            nmg_batch_destroy(b);
+            return rc;
+        }
+        b->inst.push_back(c);
+    }
+    nmg_ctx *t = b->inst[0];
+    t->batch = b;
+    const int NL = b->NL;
+    auto geom = [&](int k, int l) -> const LevelGeom & { return b->inst[k]->L[l].G; };
+
+    // one coarse plan for every instance: the first level where all have at
+    // most the limit's cells, LDS levels that fit every instance
+    t->lc = -1;
+    const long maxcells = coarse_cells_limit();
+    for (int l = 1; l <= NL && t->lc < 0; ++l) {
+        bool all = true;
+        for (int k = 0; k < n; ++k) all = all && cells(geom(k, l)) <= maxcells;
+        if (all) t->lc = l;
+    }
+    if (t->lc >= 0) {
+        int l_lds = -2;
+        bool fits = true;
+        for (int k = 0; k < n; ++k) {
+            const int lk = lds_first_level(b->inst[k], t->lc);
+            if (lk < 0) { l_lds = -1; break; }
+            l_lds = lk > l_lds ? lk : l_lds;
+        }
+        for (int k = 0; k < n; ++k) fits = fits && 2 * geom(k, NL).plane <= kCoarseBlock;
+        t->l_lds = l_lds < 0 ? -1 : l_lds;
+        int rc = record_coarse(t, fits);
+        if (rc) {
+            b->err = t->err;
+            nmg_batch_destroy(b);
+            return rc;
+        }
+    }
+    if (t->lc >= 0) {
+        std::vector<LevelDev> clv((size_t)n * kMaxLevels);
+        for (int k = 0; k < n; ++k) coarse_level_table(b->inst[k], t->l_lds, &clv[(size_t)k * kMaxLevels]);
+        if (hipMalloc(&b->d_clv, sizeof(LevelDev) * clv.size()) != hipSuccess) {
+            nmg_batch_destroy(b);
+            return NMG_ENOMEM;
+        }
+        if (hipMemcpy(b->d_clv, clv.data(), sizeof(LevelDev) * clv.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            nmg_batch_destroy(b);
+            return NMG_EHIP;
+        }
+    }
+
+    // work lists
+    RangeBuilder rb;
+    std::vector<long> u(n);
+    for (int k = 0; k < n; ++k) u[k] = cells(geom(k, 0));
+    rb.add(&b->w_cells0, u, kBlock);
+    std::vector<int> roff(n), rcnt(n);
+    {
+        long pos = 0;
+        for (int k = 0; k < n; ++k) {
+            roff[k] = (int)pos;
+            rcnt[k] = (int)((u[k] + kBlock - 1) / kBlock);
+            pos += rcnt[k];
+        }
+    }
+    for (int l = 0; l <= NL; ++l) {
+        for (int k = 0; k < n; ++k) u[k] = geom(k, l).plane;
+        for (int ti = 0; ti < kNumTiles; ++ti) rb.add(&b->w_plane[l][ti], u, kTileChoices[ti]);
+        if (l >= 1) {
+            for (int k = 0; k < n; ++k) u[k] = cells(geom(k, l));
+            rb.add(&b->w_ccells[l], u, kBlock);
+        }
+    }
+    std::vector<BatchLevel> blv((size_t)(NL + 1) * n);
+    for (int l = 0; l <= NL; ++l)
+        for (int k = 0; k < n; ++k) {
+            const Level &Lf = b->inst[k]->L[l];
+            const Level &Lc = b->inst[k]->L[l < NL ? l + 1 : l];
+            blv[(size_t)l * n + k] = BatchLevel{Lf.G, Lc.G, Lf.A, Lf.b, Lf.x, Lc.A, Lc.b, Lc.x};
+        }
+    b->h_inst.resize(n);
+    for (int k = 0; k < n; ++k) {
+        nmg_ctx *c = b->inst[k];
+        b->h_inst[k] = BatchInst{c->P, c->L[0].G, nullptr, nullptr, c->Ulast, c->iso,
+                                 c->L[0].A, c->L[0].b, c->L[0].x};
+    }
+    bool ok = hipMalloc(&b->d_work, sizeof(WorkItem) * rb.items.size()) == hipSuccess &&
+              hipMalloc(&b->d_lv, sizeof(BatchLevel) * blv.size()) == hipSuccess &&
+              hipMalloc(&b->d_inst, sizeof(BatchInst) * n) == hipSuccess &&
+              hipMalloc(&b->d_active, sizeof(int) * n) == hipSuccess &&
+              hipMalloc(&b->d_mask, sizeof(int) * n) == hipSuccess &&
+              hipHostMalloc(&b->h_active, sizeof(int) * n, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&b->h_mask, sizeof(int) * n, hipHostMallocDefault) == hipSuccess &&
+              hipMalloc(&b->d_roff, sizeof(int) * n) == hipSuccess &&
+              hipMalloc(&b->d_rcnt, sizeof(int) * n) == hipSuccess &&
+              hipMalloc(&b->d_partial, sizeof(double) * (b->w_cells0.n + 1)) == hipSuccess &&
+              hipMalloc(&b->d_norm, sizeof(double) * n) == hipSuccess &&
+              hipHostMalloc(&b->h_norm, sizeof(double) * n, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        nmg_batch_destroy(b);
+        return NMG_ENOMEM;
+    }
+    ok = hipMemcpy(b->d_work, rb.items.data(), sizeof(WorkItem) * rb.items.size(),
+                   hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_lv, blv.data(), sizeof(BatchLevel) * blv.size(), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         hipMemcpy(b->d_roff, roff.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_rcnt, rcnt.data(), sizeof(int) * n, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        nmg_batch_destroy(b);
+        return NMG_EHIP;
+    }
+    for (auto &r : rb.refs) r.first->items = b->d_work + r.second;
+    for (int k = 0; k < n; ++k) b->h_active[k] = b->h_mask[k] = 1;
+    *out = b;
+    return NMG_OK;
+}
+
+void nmg_batch_destroy(nmg_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    for (nmg_ctx *c : b->inst) {
+        c->batch = nullptr;
+        nmg_destroy(c);
+    }
+    if (b->d_inst) (void)hipFree(b->d_inst);
+    if (b->d_lv) (void)hipFree(b->d_lv);
+    if (b->d_clv) (void)hipFree(b->d_clv);
+    if (b->d_work) (void)hipFree(b->d_work);
+    if (b->d_active) (void)hipFree(b->d_active);
+    if (b->d_mask) (void)hipFree(b->d_mask);
+    if (b->h_active) (void)hipHostFree(b->h_active);
+    if (b->h_mask) (void)hipHostFree(b->h_mask);
+    if (b->d_roff) (void)hipFree(b->d_roff);
+    if (b->d_rcnt) (void)hipFree(b->d_rcnt);
+    if (b->d_partial) (void)hipFree(b->d_partial);
+    if (b->d_norm) (void)hipFree(b->d_norm);
+    if (b->h_norm) (void)hipHostFree(b->h_norm);
+    delete b;
+}
+
+const char *nmg_batch_last_error(const nmg_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+int nmg_batch_autotune(nmg_batch *b, int reps, int *tiles_out)
+{
+    if (!b) return NMG_EINVAL;
+    if (reps < 1 || reps > 1000) return bfail(b, NMG_EINVAL, "reps out of range");
+    nmg_ctx *t = b->inst[0];
+    for (int k = 0; k < b->n; ++k) b->h_active[k] = 1;
+    int rc = upload_mask(b, b->d_active, b->h_active);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return bfail(b, NMG_EHIP, "hipEventCreate failed");
+    }
+    rc = NMG_OK;
+    for (int l = 0; l <= b->NL && !rc; ++l) {
+        b->tile[l] = kBlock;
+        if (t->lc >= 0 && l >= t->lc) continue;      // runs inside the coarse-cycle kernel
+        float best = 0.0f;
+        for (int ti = 0; ti < kNumTiles && !rc; ++ti) {
+            const BatchLevel *lv = b->d_lv + (long)l * b->n;
+            auto sweep = [&]() {
+                return launch_b_sgs_half(b->dim, b->f32, MODE_NORMAL, kTileChoices[ti], lv,
+                                         b->w_plane[l][ti], b->d_active, 0, b->stream);
+            };
+            float ms = 0.0f;
+            if (sweep() != hipSuccess || hipEventRecord(e0, b->stream) != hipSuccess) { rc = NMG_EHIP; break; }
+            for (int r = 0; r < reps && !rc; ++r)
+                if (sweep() != hipSuccess) rc = NMG_EHIP;
+            if (rc || hipEventRecord(e1, b->stream) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = NMG_EHIP;
+                break;
+            }
+            if (ti == 0 || ms < best) {
+                best = ms;
+                b->tile[l] = kTileChoices[ti];
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return bfail(b, rc, "autotune launch failed");
+    // the sweeps above changed the corrections: every cycle starts from zero
+    for (int l = 0; l <= b->NL; ++l) set_zero(t, l);
+    if (tiles_out)
+        for (int l = 0; l <= b->NL; ++l) tiles_out[l] = b->tile[l];
+    return NMG_OK;
+}
+
+int nmg_batch_newton_mg_solve(nmg_batch *b, const double *const *z, double *const *U, double tol,
+                              nmg_stats *stats)
+{
+    if (!b) return NMG_EINVAL;
+    if (!z || !U) return bfail(b, NMG_EINVAL, "null z or U array");
+    const int n = b->n;
+    for (int k = 0; k < n; ++k) {
+        if (!z[k] || !U[k]) return bfail(b, NMG_EINVAL, "null z or U");
+        b->h_inst[k].z = z[k];
+        b->h_inst[k].U = U[k];
+    }
+    nmg_ctx *t = b->inst[0];
+    const nmg_params &p = b->prm;
+    const int dim = b->dim;
+    BHIPCHK(b, hipMemcpyAsync(b->d_inst, b->h_inst.data(), sizeof(BatchInst) * n,
+                              hipMemcpyHostToDevice, b->stream));
+    for (int k = 0; k < n; ++k) b->h_active[k] = 1;
+    int rc = upload_mask(b, b->d_active, b->h_active);
+    if (rc) return rc;
+    std::vector<int> status(n, NMG_NOT_CONVERGED), steps(n, 0);
+    std::vector<double> res(n, 0.0), res0(n, 0.0);
+    int nactive = n;
+    BHIPCHK(b, launch_b_threshold(dim, b->d_inst, b->w_cells0, b->d_active, b->stream));
+    int ti256 = 0;
+    while (kTileChoices[ti256] != kBlock) ++ti256;
+    int it = 0;
+    for (it = 0; it < p.max_newton && nactive > 0; ++it) {
+        BHIPCHK(b, launch_b_copy_state(dim, b->d_inst, b->w_cells0, b->d_active, 0, b->stream));
+        const int order[4] = {0, 1, 1, 0};
+        for (int s = 0; s < p.blu_sweeps; ++s)
+            for (int q = 0; q < 4; ++q)
+                BHIPCHK(b, launch_b_blu_half(dim, b->d_inst, b->w_plane[0][ti256], b->d_active,
+                                             order[q], b->stream));
+        BHIPCHK(b, launch_b_isolated(dim, b->d_inst, b->w_cells0, b->d_active, b->stream));
+        BHIPCHK(b, launch_b_assemble(dim, b->f32, b->d_inst, b->w_cells0, b->d_active,
+                                     b->d_partial, b->stream));
+        if ((rc = bctx(b, build_coarse(t)))) return rc;
+        if ((rc = batch_norms(b, b->d_active))) return rc;
+        bool restore = false, changed = false;
+        for (int k = 0; k < n; ++k) {
+            b->h_mask[k] = 0;
+            if (!b->h_active[k]) continue;
+            const double r = b->h_norm[k];
+            if (stats && stats[k].res_hist && it < stats[k].hist_cap) stats[k].res_hist[it] = r;
+            if (it == 0) res0[k] = r;
+            res[k] = r;
+            int st = NMG_NOT_CONVERGED;
+            bool done = true;
+            if (!std::isfinite(r)) {
+                st = NMG_ENONFINITE;
+                b->h_mask[k] = 1;
+                restore = true;
+            } else if (r < tol) {
+                st = NMG_OK;
+            } else if (r > 1e8 * res0[k]) {
+                st = NMG_EDIVERGED;
+            } else {
+                done = false;
+            }
+            if (done) {
+                status[k] = st;
+                steps[k] = it;
+                b->h_active[k] = 0;
+                --nactive;
+                changed = true;
+            }
+        }
+        if (restore) {
+            if ((rc = upload_mask(b, b->d_mask, b->h_mask))) return rc;
+            BHIPCHK(b, launch_b_copy_state(dim, b->d_inst, b->w_cells0, b->d_mask, 1, b->stream));
+        }
+        if (changed && (rc = upload_mask(b, b->d_active, b->h_active))) return rc;
+        if (nactive == 0) break;
+        set_zero(t, 0);
+        for (int m = 0; m < p.n_mg; ++m)
+            if ((rc = bctx(b, cycle(t, 0)))) return rc;
+        if ((rc = bctx(b, materialize(t, 0)))) return rc;
+        BHIPCHK(b, launch_b_update(dim, b->f32, b->d_inst, b->w_cells0, b->d_active, b->stream));
+    }
+    // instances that used every Newton step: residual of the final state
+    if (nactive > 0) {
+        for (int k = 0; k < n; ++k) {
+            if (b->h_active[k]) steps[k] = p.max_newton;
+            b->h_mask[k] = b->h_active[k];
+        }
+        if ((rc = upload_mask(b, b->d_mask, b->h_mask))) return rc;
+        BHIPCHK(b, launch_b_residual(dim, b->d_inst, b->w_cells0, b->d_mask, b->d_partial, b->stream));
+        if ((rc = batch_norms(b, b->d_mask))) return rc;
+        for (int k = 0; k < n; ++k)
+            if (b->h_mask[k]) res[k] = b->h_norm[k];
+    }
+    if (stats) {
+        for (int k = 0; k < n; ++k) b->h_mask[k] = 1;
+        if ((rc = upload_mask(b, b->d_mask, b->h_mask))) return rc;
+        BHIPCHK(b, launch_b_isolated(dim, b->d_inst, b->w_cells0, b->d_mask, b->stream));
+        BHIPCHK(b, launch_b_count_iso(b->d_inst, b->w_cells0, b->d_mask, b->d_partial, b->stream));
+        if ((rc = batch_norms(b, b->d_mask))) return rc;
+        for (int k = 0; k < n; ++k) {
+            stats[k].n_pinned = (int)b->h_norm[k];
+            stats[k].newton_steps = steps[k];
+            stats[k].status = status[k];
+            stats[k].res_l1 = res[k];
+        }
+    }
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    for (int k = 0; k < n; ++k)
+        if (status[k] != NMG_OK) return NMG_NOT_CONVERGED;
     return NMG_OK;
 }
 

@@ -131,6 +131,77 @@ hipError_t launch_fix_color(int dim, bool f32, int op, const LevelGeom &G, void 
 hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
                                const LevelDev *lv, int l_lds, int nl, hipStream_t s);
 
+// ---- batches of independent problems -------------------------------------
+// One instance of a batch at the Newton level.
+struct BatchInst {
+    Phys P;
+    LevelGeom G0;               // level 0 of its hierarchy
+    const double *z;
+    double *U, *Ulast;
+    unsigned char *iso;
+    void *A, *b, *x;            // level-0 hierarchy arrays
+};
+
+// One instance of a batch at multigrid level l: the level, the next coarser
+// level (the level itself at the coarsest) and their arrays.
+struct BatchLevel {
+    LevelGeom G, Gc;
+    void *A, *b, *x;
+    void *Ac, *bc, *xc;
+};
+
+// One tile of one instance: a batched launch runs one block per work item.
+struct WorkItem {
+    int inst, tile;
+};
+
+// A contiguous range of a work list (the work items of one launch).
+struct WorkRange {
+    const WorkItem *items;
+    int n;
+};
+
+// Tile lengths the batched half sweep can be launched with.
+constexpr int kNumTiles = 4;
+constexpr int kTileChoices[kNumTiles] = {64, 128, 256, 512};
+
+// Batched launchers: every block handles one work item and skips instances
+// whose active flag is 0.
+hipError_t launch_b_isolated(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                             hipStream_t s);
+hipError_t launch_b_assemble(int dim, bool f32, const BatchInst *bi, WorkRange w,
+                             const int *active, double *partial, hipStream_t s);
+hipError_t launch_b_residual(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                             double *partial, hipStream_t s);
+hipError_t launch_b_count_iso(const BatchInst *bi, WorkRange w, const int *active,
+                              double *partial, hipStream_t s);
+// Per-instance sums of the partials: out[k] = sum of partial[off[k] .. off[k] + cnt[k])
+// in the order of launch_reduce.
+hipError_t launch_b_reduce(const double *partial, const int *off, const int *cnt, int n,
+                           const int *active, double *out, hipStream_t s);
+hipError_t launch_b_blu_half(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                             int color, hipStream_t s);
+hipError_t launch_b_update(int dim, bool f32, const BatchInst *bi, WorkRange w,
+                           const int *active, hipStream_t s);
+hipError_t launch_b_threshold(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                              hipStream_t s);
+// dir 0: Ulast = U, dir 1: U = Ulast.
+hipError_t launch_b_copy_state(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                               int dir, hipStream_t s);
+hipError_t launch_b_sgs_half(int dim, bool f32, int mode, int tile, const BatchLevel *lv,
+                             WorkRange w, const int *active, int color, hipStream_t s);
+hipError_t launch_b_restrict(int dim, bool f32, const BatchLevel *lv, WorkRange w,
+                             const int *active, hipStream_t s);
+hipError_t launch_b_fix_color(int dim, bool f32, int op, const BatchLevel *lv, WorkRange w,
+                              const int *active, int color, hipStream_t s);
+hipError_t launch_b_galerkin(int dim, bool f32, const BatchLevel *lv, WorkRange w,
+                             const int *active, hipStream_t s);
+// The coarse-cycle kernel with one workgroup per instance: workgroup k uses
+// the level table lv + k * kMaxLevels and skips an inactive instance.
+hipError_t launch_b_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
+                                 const LevelDev *lv, int ninst, const int *active, int l_lds,
+                                 int nl, hipStream_t s);
+
 // Bytes of one level's blocks, right-hand side and correction (both colours)
 // for the scalar size esz.
 inline long level_bytes(const LevelGeom &G, int ne, int nc, long esz)

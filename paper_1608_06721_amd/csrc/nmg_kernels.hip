@@ -331,14 +331,14 @@ __device__ __forceinline__ double l1norm(const double *Rc)
 // ---------------------------------------------------------------------------
 // Kernels on the natural (public) layout.
 
+// Isolation flag of cell idx: zero reconstructed depth on both sides of
+// every face.
 template <int NC>
-__global__ void __launch_bounds__(kBlock) k_isolated(Phys P, const double *__restrict__ z,
-                                                     const double *__restrict__ U,
-                                                     unsigned char *__restrict__ iso)
+__device__ __forceinline__ void isolated_cell(const Phys &P, const double *__restrict__ z,
+                                              const double *__restrict__ U,
+                                              unsigned char *__restrict__ iso, long idx)
 {
     const int NF = (NC == 2) ? 2 : 4;
-    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= (long)P.nx * P.ny) return;
     int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
     double qi[NC];
     load_state<NC>(P, U, idx, qi);
@@ -363,6 +363,16 @@ __global__ void __launch_bounds__(kBlock) k_isolated(Phys P, const double *__res
     iso[idx] = res;
 }
 
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_isolated(Phys P, const double *__restrict__ z,
+                                                     const double *__restrict__ U,
+                                                     unsigned char *__restrict__ iso)
+{
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (long)P.nx * P.ny) return;
+    isolated_cell<NC>(P, z, U, iso, idx);
+}
+
 // Stores the off-diagonal blocks of one cell in the colour-split layout,
 // applying the pinning rules: an isolated cell gets a zero row, a dry cell
 // under the dry-cell pin zero momentum rows, and the column of an isolated
@@ -379,25 +389,22 @@ struct OffStore {
     }
 };
 
-// The blocks and b are computed in FP64 and stored in the hierarchy's
-// precision T (rounded to nearest when T is float).
+// Residual, Jacobian blocks and right-hand side of cell idx; returns
+// ||R_i||_1.  The blocks and b are computed in FP64 and stored in the
+// hierarchy's precision T (rounded to nearest when T is float).
 template <int NC, class T>
-__global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
-                                                     const double *__restrict__ z,
-                                                     const double *__restrict__ U,
-                                                     const unsigned char *__restrict__ iso,
-                                                     T *__restrict__ A,
-                                                     T *__restrict__ b,
-                                                     double *__restrict__ R_out,
-                                                     double *__restrict__ partial)
+__device__ __forceinline__ double assemble_cell(const Phys &P, const LevelGeom &G,
+                                                const double *__restrict__ z,
+                                                const double *__restrict__ U,
+                                                const unsigned char *__restrict__ iso,
+                                                T *__restrict__ A, T *__restrict__ b,
+                                                double *__restrict__ R_out, long idx)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const int NE = (NF + 1) * NC * NC;
-    const int xb = xcd_block(blockIdx.x, gridDim.x);
-    long idx = (long)xb * kBlock + threadIdx.x;
     const long N = (long)P.nx * P.ny;
     double nrm = 0.0;
-    if (idx < N) {
+    {
         int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
         const int color = (i + j) & 1;
         const long slot = (long)j * G.W + (i >> 1);
@@ -440,22 +447,37 @@ __global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
             for (int c = 0; c < NC; ++c) st.Ac[(r * NC + c) * kTile] = T(D[r][c]);
         }
     }
+    return nrm;
+}
+
+template <int NC, class T>
+__global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
+                                                     const double *__restrict__ z,
+                                                     const double *__restrict__ U,
+                                                     const unsigned char *__restrict__ iso,
+                                                     T *__restrict__ A,
+                                                     T *__restrict__ b,
+                                                     double *__restrict__ R_out,
+                                                     double *__restrict__ partial)
+{
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    long idx = (long)xb * kBlock + threadIdx.x;
+    double nrm = 0.0;
+    if (idx < (long)P.nx * P.ny) nrm = assemble_cell<NC, T>(P, G, z, U, iso, A, b, R_out, idx);
     double s = block_sum(nrm);
     if (threadIdx.x == 0) partial[xb] = s;
 }
 
+// Residual R_i (eq:Res) of cell idx, optionally stored; returns ||R_i||_1.
 template <int NC>
-__global__ void __launch_bounds__(kBlock) k_residual(Phys P, const double *__restrict__ z,
-                                                     const double *__restrict__ U,
-                                                     double *__restrict__ R_out,
-                                                     double *__restrict__ partial)
+__device__ __forceinline__ double residual_cell(const Phys &P, const double *__restrict__ z,
+                                                const double *__restrict__ U,
+                                                double *__restrict__ R_out, long idx)
 {
     const int NF = (NC == 2) ? 2 : 4;
-    const int xb = xcd_block(blockIdx.x, gridDim.x);
-    long idx = (long)xb * kBlock + threadIdx.x;
     const long N = (long)P.nx * P.ny;
     double nrm = 0.0;
-    if (idx < N) {
+    {
         int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
         double qi[NC];
         load_state<NC>(P, U, idx, qi);
@@ -485,6 +507,19 @@ __global__ void __launch_bounds__(kBlock) k_residual(Phys P, const double *__res
         }
         nrm = l1norm<NC>(Rc);
     }
+    return nrm;
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_residual(Phys P, const double *__restrict__ z,
+                                                     const double *__restrict__ U,
+                                                     double *__restrict__ R_out,
+                                                     double *__restrict__ partial)
+{
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    long idx = (long)xb * kBlock + threadIdx.x;
+    double nrm = 0.0;
+    if (idx < (long)P.nx * P.ny) nrm = residual_cell<NC>(P, z, U, R_out, idx);
     double s = block_sum(nrm);
     if (threadIdx.x == 0) partial[xb] = s;
 }
@@ -511,13 +546,10 @@ __global__ void __launch_bounds__(kBlock) k_count_u8(const unsigned char *__rest
 // Step 2.1): U_i -= (alpha ||R_i||_1 I + dR_i/dU_i)^-1 R_i, then the dry
 // threshold.  Cells of one colour only read the other colour.
 template <int NC>
-__global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__restrict__ z,
-                                                     double *__restrict__ U, int color)
+__device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict__ z,
+                                         double *__restrict__ U, int color, long t)
 {
     const int W = (P.nx + 1) / 2;
-    const int xb = xcd_block(blockIdx.x, gridDim.x);
-    long t = (long)xb * kBlock + threadIdx.x;
-    if (t >= (long)W * P.ny) return;
     int j = (int)(t / W), k = (int)(t % W);
     int i = 2 * k + ((j + color) & 1);
     if (i >= P.nx) return;
@@ -554,15 +586,24 @@ __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__res
     for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
 }
 
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__restrict__ z,
+                                                     double *__restrict__ U, int color)
+{
+    const int W = (P.nx + 1) / 2;
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    long t = (long)xb * kBlock + threadIdx.x;
+    if (t >= (long)W * P.ny) return;
+    blu_cell<NC>(P, z, U, color, t);
+}
+
 // Relaxed update U += tau_i dU (positivity-limited tau_i) and dry threshold.
 template <int NC, class T>
-__global__ void __launch_bounds__(kBlock) k_update(Phys P, LevelGeom G,
-                                                   const T *__restrict__ x,
-                                                   double *__restrict__ U)
+__device__ __forceinline__ void update_cell(const Phys &P, const LevelGeom &G,
+                                            const T *__restrict__ x, double *__restrict__ U,
+                                            long idx)
 {
-    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
     const long N = (long)P.nx * P.ny;
-    if (idx >= N) return;
     int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
     const int color = (i + j) & 1;
     const T *xs = x + (long)color * NC * G.plane + (long)j * G.W + (i >> 1);
@@ -586,16 +627,32 @@ __global__ void __launch_bounds__(kBlock) k_update(Phys P, LevelGeom G,
     for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
 }
 
-template <int NC>
-__global__ void __launch_bounds__(kBlock) k_threshold(Phys P, double *__restrict__ U)
+template <int NC, class T>
+__global__ void __launch_bounds__(kBlock) k_update(Phys P, LevelGeom G,
+                                                   const T *__restrict__ x,
+                                                   double *__restrict__ U)
 {
     long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (long)P.nx * P.ny) return;
+    update_cell<NC, T>(P, G, x, U, idx);
+}
+
+template <int NC>
+__device__ __forceinline__ void threshold_cell(const Phys &P, double *__restrict__ U, long idx)
+{
     const long N = (long)P.nx * P.ny;
-    if (idx >= N) return;
     if (U[idx] < P.h_eps) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) U[c * N + idx] = 0.0;
     }
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_threshold(Phys P, double *__restrict__ U)
+{
+    long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= (long)P.nx * P.ny) return;
+    threshold_cell<NC>(P, U, idx);
 }
 
 // ---------------------------------------------------------------------------
@@ -690,14 +747,12 @@ __global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const T *__res
 // Galerkin coarse blocks (eq:ProjectAR, left) with the child-pair order of
 // the definition: children of I (SW, SE, NW, NE), then children of J.
 template <class T, int NC>
-__global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const T *__restrict__ Af,
-                                                     LevelGeom Gc, T *__restrict__ Ac)
+__device__ __forceinline__ void galerkin_cell(const LevelGeom &Gf, const T *__restrict__ Af,
+                                              const LevelGeom &Gc, T *__restrict__ Ac, long t)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const int NE = (NF + 1) * NC * NC;
     const int NN = NC * NC;
-    long t = (long)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= (long)Gc.nx * Gc.ny) return;
     const int I = (int)(t % Gc.nx), J = (int)(t / Gc.nx);
     // child (ci, cj) block blk entry e -> pointer
     auto ent = [&](int ci, int cj, int blk, int e) -> T {
@@ -750,6 +805,15 @@ __global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const T *__re
         out[(BS * NN + e) * kTile] = s;
         out[(BN * NN + e) * kTile] = n;
     }
+}
+
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const T *__restrict__ Af,
+                                                     LevelGeom Gc, T *__restrict__ Ac)
+{
+    long t = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (long)Gc.nx * Gc.ny) return;
+    galerkin_cell<T, NC>(Gf, Af, Gc, Ac, t);
 }
 
 template <class T, int NC>
@@ -916,10 +980,14 @@ struct LdsLevel {
 // formed in the branch that uses it, from the LDS array or from the level
 // table, so each access compiles to an LDS or a global load, never a generic
 // one.  The operation list and level table are read with uniform loads.
+//
+// In a batch, workgroup k runs instance k with the level table
+// lv + k * kMaxLevels and does nothing if active[k] is 0.
 template <class T, int NC>
 __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *__restrict__ ops,
                                                                int nops,
                                                                const LevelDev *__restrict__ lv,
+                                                               const int *__restrict__ active,
                                                                int l_lds, int nl)
 {
     constexpr int NF = (NC == 2) ? 2 : 4;
@@ -927,6 +995,8 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
     constexpr int NE = (NF + 1) * NN;
     constexpr int NI = inv_entries(NC);
     __shared__ __attribute__((aligned(16))) char lds[kCoarseLdsBytes];
+    if (active && !active[blockIdx.x]) return;
+    lv += (long)blockIdx.x * kMaxLevels;
     if (l_lds >= 0) {
         for (int l = l_lds; l <= nl; ++l) {
             const LevelDev &L = lv[l];
@@ -1038,6 +1108,211 @@ __global__ void __launch_bounds__(kBlock) k_mat_from_tiled(int ne, LevelGeom G,
     int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
     const T *o = s + mat_off(G, ne, (i + j) & 1, (long)j * G.W + (i >> 1));
     for (int e = 0; e < ne; ++e) v[e * N + idx] = double(o[e * kTile]);
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched kernels: one block per work item (instance, tile), in XCD-aware
+// order; the per-cell work is the same function as in the single-problem
+// kernels, so every instance's results are those of its own solve.  Tiles of
+// the reduction kernels are the 256-cell blocks of the single kernels, and an
+// instance's tiles are contiguous in the work list, so its partial sums are
+// the single kernel's partial sums.
+
+__device__ __forceinline__ WorkItem work_item(const WorkRange &w, int &pos)
+{
+    pos = xcd_block(blockIdx.x, gridDim.x);
+    return w.items[pos];
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) kb_isolated(const BatchInst *__restrict__ bi,
+                                                      WorkRange w, const int *__restrict__ active)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchInst &I = bi[it.inst];
+    const long idx = (long)it.tile * kBlock + threadIdx.x;
+    if (idx < (long)I.P.nx * I.P.ny) isolated_cell<NC>(I.P, I.z, I.U, I.iso, idx);
+}
+
+template <int NC, class T>
+__global__ void __launch_bounds__(kBlock) kb_assemble(const BatchInst *__restrict__ bi,
+                                                      WorkRange w, const int *__restrict__ active,
+                                                      double *__restrict__ partial)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchInst &I = bi[it.inst];
+    const long idx = (long)it.tile * kBlock + threadIdx.x;
+    double nrm = 0.0;
+    if (idx < (long)I.P.nx * I.P.ny)
+        nrm = assemble_cell<NC, T>(I.P, I.G0, I.z, I.U, I.iso, (T *)I.A, (T *)I.b, nullptr, idx);
+    double s = block_sum(nrm);
+    if (threadIdx.x == 0) partial[pos] = s;
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) kb_residual(const BatchInst *__restrict__ bi,
+                                                      WorkRange w, const int *__restrict__ active,
+                                                      double *__restrict__ partial)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchInst &I = bi[it.inst];
+    const long idx = (long)it.tile * kBlock + threadIdx.x;
+    double nrm = 0.0;
+    if (idx < (long)I.P.nx * I.P.ny) nrm = residual_cell<NC>(I.P, I.z, I.U, nullptr, idx);
+    double s = block_sum(nrm);
+    if (threadIdx.x == 0) partial[pos] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) kb_count_iso(const BatchInst *__restrict__ bi,
+                                                       WorkRange w,
+                                                       const int *__restrict__ active,
+                                                       double *__restrict__ partial)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchInst &I = bi[it.inst];
+    const long idx = (long)it.tile * kBlock + threadIdx.x;
+    double c = (idx < (long)I.P.nx * I.P.ny && I.iso[idx]) ? 1.0 : 0.0;
+    double s = block_sum(c);
+    if (threadIdx.x == 0) partial[pos] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) kb_reduce(const double *__restrict__ partial,
+                                                    const int *__restrict__ off,
+                                                    const int *__restrict__ cnt,
+                                                    const int *__restrict__ active,
+                                                    double *__restrict__ out)
+{
+    const int k = blockIdx.x;
+    if (!active[k]) return;
+    const double *p = partial + off[k];
+    const int n = cnt[k];
+    double v = 0.0;
+    for (int q = threadIdx.x; q < n; q += kBlock) v = v + p[q];
+    double s = block_sum(v);
+    if (threadIdx.x == 0) out[k] = s;
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) kb_blu_half(const BatchInst *__restrict__ bi,
+                                                      WorkRange w, const int *__restrict__ active,
+                                                      int color)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchInst &I = bi[it.inst];
+    const long t = (long)it.tile * kBlock + threadIdx.x;
+    if (t < I.G0.plane) blu_cell<NC>(I.P, I.z, I.U, color, t);
+}
+
+template <int NC, class T>
+__global__ void __launch_bounds__(kBlock) kb_update(const BatchInst *__restrict__ bi,
+                                                    WorkRange w, const int *__restrict__ active)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchInst &I = bi[it.inst];
+    const long idx = (long)it.tile * kBlock + threadIdx.x;
+    if (idx < (long)I.P.nx * I.P.ny) update_cell<NC, T>(I.P, I.G0, (const T *)I.x, I.U, idx);
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) kb_threshold(const BatchInst *__restrict__ bi,
+                                                       WorkRange w,
+                                                       const int *__restrict__ active)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchInst &I = bi[it.inst];
+    const long idx = (long)it.tile * kBlock + threadIdx.x;
+    if (idx < (long)I.P.nx * I.P.ny) threshold_cell<NC>(I.P, I.U, idx);
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) kb_copy_state(const BatchInst *__restrict__ bi,
+                                                        WorkRange w,
+                                                        const int *__restrict__ active, int dir)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchInst &I = bi[it.inst];
+    const long N = (long)I.P.nx * I.P.ny;
+    const long idx = (long)it.tile * kBlock + threadIdx.x;
+    if (idx >= N) return;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (dir == 0)
+            I.Ulast[c * N + idx] = I.U[c * N + idx];
+        else
+            I.U[c * N + idx] = I.Ulast[c * N + idx];
+    }
+}
+
+template <class T, int NC, int MODE, int TB>
+__global__ void __launch_bounds__(TB) kb_sgs_half(const BatchLevel *__restrict__ lv, WorkRange w,
+                                                  const int *__restrict__ active, int color)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchLevel &L = lv[it.inst];
+    const long t = (long)it.tile * TB + threadIdx.x;
+    if (t < L.G.plane)
+        sgs_cell<T, NC, MODE>(L.G, (const T *)L.A, nullptr, (const T *)L.b, (T *)L.x, color, L.Gc,
+                              (const T *)L.xc, t);
+}
+
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) kb_restrict(const BatchLevel *__restrict__ lv,
+                                                      WorkRange w,
+                                                      const int *__restrict__ active)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchLevel &L = lv[it.inst];
+    const long t = (long)it.tile * kBlock + threadIdx.x;
+    if (t < (long)L.Gc.nx * L.Gc.ny)
+        restrict_cell<T, NC>(L.G, (const T *)L.A, (const T *)L.b, (const T *)L.x, L.Gc, (T *)L.bc, t);
+}
+
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) kb_fix_color(const BatchLevel *__restrict__ lv,
+                                                       WorkRange w,
+                                                       const int *__restrict__ active, int op,
+                                                       int color)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchLevel &L = lv[it.inst];
+    const long t = (long)it.tile * kBlock + threadIdx.x;
+    if (t < L.G.plane) fix_cell<T, NC>(L.G, op, (T *)L.x, color, L.Gc, (const T *)L.xc, t);
+}
+
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) kb_galerkin(const BatchLevel *__restrict__ lv,
+                                                      WorkRange w,
+                                                      const int *__restrict__ active)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchLevel &L = lv[it.inst];
+    const long t = (long)it.tile * kBlock + threadIdx.x;
+    if (t < (long)L.Gc.nx * L.Gc.ny) galerkin_cell<T, NC>(L.G, (const T *)L.A, L.Gc, (T *)L.Ac, t);
 }
 
 }  // namespace
@@ -1191,7 +1466,7 @@ hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
 #define NMG_COARSE(T, NC)                                                                     \
     do {                                                                                      \
         hipLaunchKernelGGL((k_coarse_cycle<T, NC>), dim3(1), dim3(kCoarseBlock), 0, s, ops,   \
-                           nops, lv, l_lds, nl);                                              \
+                           nops, lv, nullptr, l_lds, nl);                                     \
         return hipGetLastError();                                                             \
     } while (0)
     if (f32) {
@@ -1201,6 +1476,186 @@ hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
     if (dim == 1) NMG_COARSE(double, 2);
     NMG_COARSE(double, 3);
 #undef NMG_COARSE
+}
+
+
+// ---- batched launchers ----
+
+#define NMG_BLAUNCH(kern, ...)                                                         \
+    do {                                                                               \
+        if (w.n <= 0) return hipSuccess;                                               \
+        hipLaunchKernelGGL(kern, dim3(w.n), dim3(kBlock), 0, s, __VA_ARGS__);          \
+        return hipGetLastError();                                                      \
+    } while (0)
+
+hipError_t launch_b_isolated(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                             hipStream_t s)
+{
+    if (dim == 1) NMG_BLAUNCH(kb_isolated<2>, bi, w, active);
+    NMG_BLAUNCH(kb_isolated<3>, bi, w, active);
+}
+
+hipError_t launch_b_assemble(int dim, bool f32, const BatchInst *bi, WorkRange w,
+                             const int *active, double *partial, hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) NMG_BLAUNCH((kb_assemble<2, float>), bi, w, active, partial);
+        NMG_BLAUNCH((kb_assemble<3, float>), bi, w, active, partial);
+    }
+    if (dim == 1) NMG_BLAUNCH((kb_assemble<2, double>), bi, w, active, partial);
+    NMG_BLAUNCH((kb_assemble<3, double>), bi, w, active, partial);
+}
+
+hipError_t launch_b_residual(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                             double *partial, hipStream_t s)
+{
+    if (dim == 1) NMG_BLAUNCH(kb_residual<2>, bi, w, active, partial);
+    NMG_BLAUNCH(kb_residual<3>, bi, w, active, partial);
+}
+
+hipError_t launch_b_count_iso(const BatchInst *bi, WorkRange w, const int *active,
+                              double *partial, hipStream_t s)
+{
+    NMG_BLAUNCH(kb_count_iso, bi, w, active, partial);
+}
+
+hipError_t launch_b_reduce(const double *partial, const int *off, const int *cnt, int n,
+                           const int *active, double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_reduce, dim3(n), dim3(kBlock), 0, s, partial, off, cnt, active, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_blu_half(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                             int color, hipStream_t s)
+{
+    if (dim == 1) NMG_BLAUNCH(kb_blu_half<2>, bi, w, active, color);
+    NMG_BLAUNCH(kb_blu_half<3>, bi, w, active, color);
+}
+
+hipError_t launch_b_update(int dim, bool f32, const BatchInst *bi, WorkRange w,
+                           const int *active, hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) NMG_BLAUNCH((kb_update<2, float>), bi, w, active);
+        NMG_BLAUNCH((kb_update<3, float>), bi, w, active);
+    }
+    if (dim == 1) NMG_BLAUNCH((kb_update<2, double>), bi, w, active);
+    NMG_BLAUNCH((kb_update<3, double>), bi, w, active);
+}
+
+hipError_t launch_b_threshold(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                              hipStream_t s)
+{
+    if (dim == 1) NMG_BLAUNCH(kb_threshold<2>, bi, w, active);
+    NMG_BLAUNCH(kb_threshold<3>, bi, w, active);
+}
+
+hipError_t launch_b_copy_state(int dim, const BatchInst *bi, WorkRange w, const int *active,
+                               int dir, hipStream_t s)
+{
+    if (dim == 1) NMG_BLAUNCH(kb_copy_state<2>, bi, w, active, dir);
+    NMG_BLAUNCH(kb_copy_state<3>, bi, w, active, dir);
+}
+
+template <class T, int NC, int TB>
+static hipError_t bsgs_mode(int mode, const BatchLevel *lv, WorkRange w, const int *active,
+                            int color, hipStream_t s)
+{
+    if (w.n <= 0) return hipSuccess;
+    switch (mode) {
+    case MODE_NORMAL:
+        hipLaunchKernelGGL((kb_sgs_half<T, NC, MODE_NORMAL, TB>), dim3(w.n), dim3(TB), 0, s, lv, w, active, color);
+        break;
+    case MODE_ZERO:
+        hipLaunchKernelGGL((kb_sgs_half<T, NC, MODE_ZERO, TB>), dim3(w.n), dim3(TB), 0, s, lv, w, active, color);
+        break;
+    case MODE_PROLONG:
+        hipLaunchKernelGGL((kb_sgs_half<T, NC, MODE_PROLONG, TB>), dim3(w.n), dim3(TB), 0, s, lv, w, active, color);
+        break;
+    default:
+        hipLaunchKernelGGL((kb_sgs_half<T, NC, MODE_PROLONG_ZERO, TB>), dim3(w.n), dim3(TB), 0, s, lv, w, active, color);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <class T, int NC>
+static hipError_t bsgs_tile(int mode, int tile, const BatchLevel *lv, WorkRange w,
+                            const int *active, int color, hipStream_t s)
+{
+    switch (tile) {
+    case 64: return bsgs_mode<T, NC, 64>(mode, lv, w, active, color, s);
+    case 128: return bsgs_mode<T, NC, 128>(mode, lv, w, active, color, s);
+    case 256: return bsgs_mode<T, NC, 256>(mode, lv, w, active, color, s);
+    case 512: return bsgs_mode<T, NC, 512>(mode, lv, w, active, color, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_b_sgs_half(int dim, bool f32, int mode, int tile, const BatchLevel *lv,
+                             WorkRange w, const int *active, int color, hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) return bsgs_tile<float, 2>(mode, tile, lv, w, active, color, s);
+        return bsgs_tile<float, 3>(mode, tile, lv, w, active, color, s);
+    }
+    if (dim == 1) return bsgs_tile<double, 2>(mode, tile, lv, w, active, color, s);
+    return bsgs_tile<double, 3>(mode, tile, lv, w, active, color, s);
+}
+
+hipError_t launch_b_restrict(int dim, bool f32, const BatchLevel *lv, WorkRange w,
+                             const int *active, hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) NMG_BLAUNCH((kb_restrict<float, 2>), lv, w, active);
+        NMG_BLAUNCH((kb_restrict<float, 3>), lv, w, active);
+    }
+    if (dim == 1) NMG_BLAUNCH((kb_restrict<double, 2>), lv, w, active);
+    NMG_BLAUNCH((kb_restrict<double, 3>), lv, w, active);
+}
+
+hipError_t launch_b_fix_color(int dim, bool f32, int op, const BatchLevel *lv, WorkRange w,
+                              const int *active, int color, hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) NMG_BLAUNCH((kb_fix_color<float, 2>), lv, w, active, op, color);
+        NMG_BLAUNCH((kb_fix_color<float, 3>), lv, w, active, op, color);
+    }
+    if (dim == 1) NMG_BLAUNCH((kb_fix_color<double, 2>), lv, w, active, op, color);
+    NMG_BLAUNCH((kb_fix_color<double, 3>), lv, w, active, op, color);
+}
+
+hipError_t launch_b_galerkin(int dim, bool f32, const BatchLevel *lv, WorkRange w,
+                             const int *active, hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) NMG_BLAUNCH((kb_galerkin<float, 2>), lv, w, active);
+        NMG_BLAUNCH((kb_galerkin<float, 3>), lv, w, active);
+    }
+    if (dim == 1) NMG_BLAUNCH((kb_galerkin<double, 2>), lv, w, active);
+    NMG_BLAUNCH((kb_galerkin<double, 3>), lv, w, active);
+}
+
+hipError_t launch_b_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
+                                 const LevelDev *lv, int ninst, const int *active, int l_lds,
+                                 int nl, hipStream_t s)
+{
+    if (ninst <= 0) return hipSuccess;
+#define NMG_BCOARSE(T, NC)                                                                    \
+    do {                                                                                      \
+        hipLaunchKernelGGL((k_coarse_cycle<T, NC>), dim3(ninst), dim3(kCoarseBlock), 0, s,    \
+                           ops, nops, lv, active, l_lds, nl);                                 \
+        return hipGetLastError();                                                             \
+    } while (0)
+    if (f32) {
+        if (dim == 1) NMG_BCOARSE(float, 2);
+        NMG_BCOARSE(float, 3);
+    }
+    if (dim == 1) NMG_BCOARSE(double, 2);
+    NMG_BCOARSE(double, 3);
+#undef NMG_BCOARSE
 }
 
 hipError_t launch_vec_to_split(int nc, bool f32, const LevelGeom &G, const double *v, void *split,

@@ -53,7 +53,8 @@ _lib = None
 EXPORTS = ["nmg_create", "nmg_destroy", "nmg_last_error", "nmg_residual",
            "nmg_assemble_residual_jacobian", "nmg_mg_vcycle", "nmg_sgs", "nmg_blu_sweep",
            "nmg_newton_mg_solve", "nmg_load_system", "nmg_get_system", "nmg_timing_enable",
-           "nmg_timing_read"]
+           "nmg_timing_read", "nmg_batch_create", "nmg_batch_destroy", "nmg_batch_last_error",
+           "nmg_batch_autotune", "nmg_batch_newton_mg_solve"]
 
 
 def library_path() -> str:
@@ -85,6 +86,15 @@ def lib():
         L.nmg_timing_enable.argtypes = [vp, C.c_int, C.c_int]
         L.nmg_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                       C.POINTER(C.c_longlong)]
+        L.nmg_batch_create.argtypes = [C.c_int, C.POINTER(nmg_grid), C.POINTER(nmg_bc),
+                                       C.POINTER(nmg_params), vp, C.POINTER(vp)]
+        L.nmg_batch_destroy.argtypes = [vp]
+        L.nmg_batch_destroy.restype = None
+        L.nmg_batch_last_error.argtypes = [vp]
+        L.nmg_batch_last_error.restype = C.c_char_p
+        L.nmg_batch_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int)]
+        L.nmg_batch_newton_mg_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.c_double,
+                                                C.POINTER(nmg_stats)]
         _lib = L
     return _lib
 
@@ -104,6 +114,27 @@ class NMGError(RuntimeError):
         self.code = code
 
 
+def _grid(dim, nx, ny, x0, x1, y0, y1):
+    return nmg_grid(int(dim), int(nx), int(ny), x0, x1, y0, y1)
+
+
+def _bc(bc):
+    b = nmg_bc()
+    for k, s in enumerate(bc):
+        b.side[k] = nmg_side(int(s[0]), float(s[1]), float(s[2]), float(s[3]))
+    return b
+
+
+def _params(params):
+    return nmg_params(int(params["flux"]), params["g"], params["alpha"], params["fd_eps"],
+                      params["tau"], params["h_eps"], params["eps_r"], int(params["n_levels"]),
+                      int(params["nu1"]), int(params["nu2"]), int(params["nu_coarse"]),
+                      int(params["n_mg"]), int(params["blu_sweeps"]),
+                      int(params["max_newton"]), int(params["dry_pin"]),
+                      float(params["pos_theta"]), int(params.get("inner_fp32", 0)),
+                      int(params.get("gamma", 1)))
+
+
 class Context:
     """One grid / boundary condition / parameter set (nmg_create)."""
 
@@ -112,17 +143,9 @@ class Context:
         self.nc = 2 if self.dim == 1 else 3
         self.nb = 3 if self.dim == 1 else 5
         self.n_levels = int(params["n_levels"])
-        g = nmg_grid(self.dim, self.nx, self.ny, x0, x1, y0, y1)
-        b = nmg_bc()
-        for k, s in enumerate(bc):
-            b.side[k] = nmg_side(int(s[0]), float(s[1]), float(s[2]), float(s[3]))
-        p = nmg_params(int(params["flux"]), params["g"], params["alpha"], params["fd_eps"],
-                       params["tau"], params["h_eps"], params["eps_r"], int(params["n_levels"]),
-                       int(params["nu1"]), int(params["nu2"]), int(params["nu_coarse"]),
-                       int(params["n_mg"]), int(params["blu_sweeps"]),
-                       int(params["max_newton"]), int(params["dry_pin"]),
-                       float(params["pos_theta"]), int(params.get("inner_fp32", 0)),
-                       int(params.get("gamma", 1)))
+        g = _grid(self.dim, self.nx, self.ny, x0, x1, y0, y1)
+        b = _bc(bc)
+        p = _params(params)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -224,3 +247,79 @@ def newton_mg_solve(prob, z, U, tol, stream=None, **overrides):
         return ctx.newton_mg_solve(z, U, tol)
     finally:
         ctx.close()
+
+
+class Batch:
+    """Independent problems solved in lockstep (nmg_batch_create): each
+    problem's own grid and boundary data, one parameter set for all."""
+
+    def __init__(self, probs, params: Optional[dict] = None, stream=None, **overrides):
+        n = len(probs)
+        if n < 1:
+            raise ValueError("empty batch")
+        params = dict(params if params is not None else probs[0].params)
+        params.update(overrides)
+        self.n = n
+        self.params = params
+        grids = (nmg_grid * n)(*[_grid(p.dim, p.nx, p.ny, p.x0, p.x1, p.y0, p.y1) for p in probs])
+        bcs = (nmg_bc * n)(*[_bc(p.bc) for p in probs])
+        prm = _params(params)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        rc = lib().nmg_batch_create(n, grids, bcs, C.byref(prm), C.c_void_p(stream.cuda_stream),
+                                    C.byref(h))
+        if rc != 0:
+            raise NMGError(rc, "nmg_batch_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nmg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, ok=(0,)):
+        if rc not in ok:
+            msg = lib().nmg_batch_last_error(self._h)
+            raise NMGError(rc, msg.decode() if msg else "")
+        return rc
+
+    def autotune(self, reps=5):
+        """Pick the tile length of the batched half sweep per level; returns
+        the chosen lengths (levels 0..n_levels)."""
+        nl = int(self.params["n_levels"])
+        out = (C.c_int * (nl + 1))()
+        self._check(lib().nmg_batch_autotune(self._h, int(reps), out))
+        return list(out)
+
+    def newton_mg_solve(self, zs, Us, tol, hist_cap=0):
+        """Solve every instance in place from Us[k]; returns one result dict
+        per instance (as Context.newton_mg_solve)."""
+        if len(zs) != self.n or len(Us) != self.n:
+            raise ValueError("need one z and one U per instance")
+        zp = (C.c_void_p * self.n)(*[_ptr(z, "z") for z in zs])
+        up = (C.c_void_p * self.n)(*[_ptr(u, "U") for u in Us])
+        hists = [(C.c_double * max(hist_cap, 1))() for _ in range(self.n)]
+        st = (nmg_stats * self.n)()
+        for k in range(self.n):
+            st[k] = nmg_stats(0, 0, 0, 0.0,
+                              C.cast(hists[k], C.POINTER(C.c_double)) if hist_cap else None,
+                              int(hist_cap))
+        rc = lib().nmg_batch_newton_mg_solve(self._h, zp, up, float(tol), st)
+        self._check(rc, ok=(0, 1))
+        out = []
+        for k in range(self.n):
+            s = st[k]
+            n = s.newton_steps
+            nh = min(n + 1 if s.status in (0, -4, -5) else n, hist_cap)
+            out.append(dict(status=STATUS.get(s.status, s.status), newton_steps=n,
+                            n_pinned=s.n_pinned, res_l1=s.res_l1,
+                            res_hist=[hists[k][q] for q in range(nh)]))
+        return out

@@ -206,6 +206,29 @@ def channel(nx: int = 1024, ny: int = 1024, seed: int = CHANNEL_SEED, qn: float 
                    default_params(2, **kw), z, U0)
 
 
+BATCH_SEED = CHANNEL_SEED + 1
+
+
+def batch_channels(n: int = 64, sizes=(128, 256, 384, 512), q_range=(0.5, 2.0),
+                   seed: int = BATCH_SEED, bump_width=(0.2, 0.8), mound_amp: float = 0.8,
+                   **kw) -> list:
+    """A batch of independent steady channel problems of uneven size: for
+    instance k, nx and ny are drawn independently from `sizes`, the bed is
+    channel_bed with seed + k, and the inflow discharge is drawn from
+    U[q_range]; everything else (and every solver parameter in kw) as in
+    channel()."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    probs = []
+    for k in range(n):
+        nx = int(rng.choice(sizes))
+        ny = int(rng.choice(sizes))
+        q = float(rng.uniform(*q_range))
+        p = channel(nx, ny, seed=seed + k, qn=q, bump_width=bump_width, mound_amp=mound_amp, **kw)
+        p.name = "batch%d_%dx%d_q%.3f" % (k, nx, ny, q)
+        probs.append(p)
+    return probs
+
+
 def random_state(dim: int, nx: int, ny: int, seed: int, hmin=0.5, hmax=2.0, umax=0.5):
     """Smooth-ish random wet state (h in [hmin, hmax], |u|, |v| < umax) and
     bed in [0, 0.2], for unit tests of the discretization."""
