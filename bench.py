@@ -107,6 +107,45 @@ def timed_solves(ctx, z, U0, steps, warmup, tol, cap):
     return dt, stats, ctx.timing_read()
 
 
+def batched(args):
+    """Batched solves of uneven independent problems: `args.batch` steady
+    channels with sizes from {128, 256, 384, 512}^2, their own beds and
+    inflow discharges U[0.5, 2], FP32 inner W-cycle, FP64 outer, one batch
+    solve (after an untimed one) with autotuned tiles."""
+    import collections
+    import torch
+    from paper_1608_06721_amd import nmg
+    from paper_1608_06721_amd import workloads as W
+    probs = W.batch_channels(args.batch, n_levels=args.batch_levels, gamma=2, inner_fp32=1,
+                             max_newton=args.batch_max_newton)
+    b = nmg.Batch(probs)
+    tiles = b.autotune(reps=5)
+    zs = [torch.from_numpy(p.z).cuda() for p in probs]
+    U0s = [torch.from_numpy(p.U0).cuda() for p in probs]
+    b.newton_mg_solve(zs, [u.clone() for u in U0s], args.tol)
+    Us = [u.clone() for u in U0s]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = b.newton_mg_solve(zs, Us, args.tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    b.close()
+    counts = collections.Counter(r["status"] for r in res)
+    steps = [r["newton_steps"] for r in res]
+    print("[bench] batched: %d instances in %.3f s, %s" % (len(probs), dt, dict(counts)),
+          file=sys.stderr, flush=True)
+    return {
+        "value": len(probs) / dt, "unit": "solves/s", "instances": len(probs),
+        "cells": int(sum(p.nx * p.ny for p in probs)), "ms_per_batch": 1e3 * dt,
+        "statuses": dict(counts), "newton_steps_mean": float(sum(steps)) / len(steps),
+        "newton_steps_max": max(steps), "max_newton": args.batch_max_newton,
+        "n_levels": args.batch_levels, "cycle": "W(2,2), nu_coarse=10, n_mg=3",
+        "dtype": "f32 inner / f64 outer", "tiles": tiles,
+        "workload": "batch of %d channels, sizes {128,256,384,512}^2, q U[0.5,2] (seed %d)"
+                    % (len(probs), W.BATCH_SEED),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +165,10 @@ def main():
     ap.add_argument("--bump-width", type=float, nargs=2, default=[0.2, 0.8])
     ap.add_argument("--mound-amp", type=float, default=0.8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="instances of the batched-solve workload (0: skip it)")
+    ap.add_argument("--batch-levels", type=int, default=5)
+    ap.add_argument("--batch-max-newton", type=int, default=150)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--timing-cap", type=int, default=20000)
     ap.add_argument("--kernel-probe", action="store_true",
@@ -256,6 +299,8 @@ def main():
                                                            dt32 / args.steps),
           file=sys.stderr, flush=True)
     ctx32.close()
+    if args.batch > 0:
+        out["batched"] = batched(args)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, n_newton, args.cpu_budget)

@@ -145,3 +145,27 @@ def test_batch_nonfinite_instance_leaves_the_others_alone(nmg):
     assert rb[1]["status"] == "ENONFINITE" and rb[1]["newton_steps"] == 0
     check_vs_oracle(probs, Ub, rb, 1e-10)
     check_vs_single(nmg, probs, Ub, rb, 1e-10)
+
+
+def test_full_size_batch_sampled(nmg):
+    """The 64-instance workload of the benchmark (sizes up to 512^2, FP32
+    inner W-cycle) in its launch configuration (autotuned tiles): sampled
+    instances equal their single solves bit for bit, and the smallest one
+    also the oracle's."""
+    probs = W.batch_channels(64, n_levels=5, gamma=2, inner_fp32=1, max_newton=150)
+    b = nmg.Batch(probs)
+    say("full batch tiles", b.autotune(reps=2))
+    zs = [dev(p.z) for p in probs]
+    Us = [dev(p.U0) for p in probs]
+    res = b.newton_mg_solve(zs, Us, 1e-10, hist_cap=200)
+    b.close()
+    Ub = [host(u) for u in Us]
+    cells = [p.nx * p.ny for p in probs]
+    small = int(np.argmin(cells))
+    large = int(np.argmax(cells))
+    odd = [k for k, r in enumerate(res) if r["status"] != "OK"][:1]
+    sample = sorted({small, large, *odd})
+    say("sample", [(probs[k].name, res[k]["status"], res[k]["newton_steps"]) for k in sample])
+    check_vs_single(nmg, [probs[k] for k in sample], [Ub[k] for k in sample],
+                    [res[k] for k in sample], 1e-10)
+    check_vs_oracle([probs[small]], [Ub[small]], [res[small]], 1e-10)
