@@ -258,3 +258,22 @@ def newton_solve(prob, U0=None, tol=1e-10, params=None, hist_cap=10000):
     nh = min(n + 1, hist_cap) if st.status in (0, -4, -5) else min(n, hist_cap)
     return U, dict(status=STATUS.get(rc, rc), newton_steps=n, n_pinned=st.n_pinned,
                    res_l1=st.res_l1, res_hist=hist[:nh].copy())
+
+
+# --- sensitivities ---------------------------------------------------------------
+def transpose_blocks(A):
+    """Exact block transpose of a level matrix (the adjoint system's matrix)."""
+    dim, nx, ny, nc, nb = _dims(A)
+    At = np.zeros_like(_f64(A))
+    lib().orc_transpose_blocks(C.c_int(dim), C.c_int(nx), C.c_int(ny), _dp(_f64(A)), _dp(At))
+    return At
+
+
+def bed_vjp(prob, U, lam, params=None):
+    """(dR/dz)^T lam [ny][nx] by forward differences in the bed, rows pinned
+    as in the assembly."""
+    p = params_struct(params or prob.params)
+    out = np.zeros((prob.ny, prob.nx))
+    _check(lib().orc_bed_vjp(C.byref(_grid(prob)), _bc(prob), C.byref(p), _dp(_f64(prob.z)),
+                             _dp(_f64(U)), _dp(_f64(lam)), _dp(out)), "bed_vjp")
+    return out

@@ -662,3 +662,104 @@ int orc_newton_solve(const orc_grid *gr, const orc_side bc[4], const orc_params 
     free(A); free(b); free(Ulast); free(iso);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sensitivities.  At a steady state R(U, z) = 0 (eq:Res), an objective
+ * J(U, z) has the bed derivative dJ/dz = dJ/dz|_U - lam^T dR/dz, where lam
+ * solves (dR/dU)^T lam = (dJ/dU)^T and dR/dU is the assembled Newton matrix
+ * of eq:MatrixForm (the linearization the solver itself uses).  Pinned rows
+ * of that matrix (isolated cells, the momentum of exactly dry cells) are
+ * unknowns held fixed by the linearization, so their rows of dR/dz are
+ * pinned the same way. */
+
+static const int OPP[4] = {FE, FW, FN, FS};   /* face of the neighbour that faces back */
+
+void orc_transpose_blocks(int dim, int nx, int ny, const double *A, double *At)
+{
+    int nc = dim == 1 ? 2 : 3, nf = dim == 1 ? 2 : 4, N = nx * ny, ni, nj;
+#define TIDX(b, r, c, idx) ((((size_t)(b) * nc + (r)) * nc + (c)) * N + (idx))
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int idx = j * nx + i;
+            for (int r = 0; r < nc; ++r)
+                for (int c = 0; c < nc; ++c) {
+                    At[TIDX(0, r, c, idx)] = A[TIDX(0, c, r, idx)];
+                    for (int f = 0; f < nf; ++f) {
+                        double v = 0.0;
+                        if (nbr(dim, nx, ny, i, j, f, &ni, &nj))
+                            v = A[TIDX(OPP[f] + 1, c, r, nj * nx + ni)];
+                        At[TIDX(f + 1, r, c, idx)] = v;
+                    }
+                }
+        }
+#undef TIDX
+}
+
+/* Row pins of the Newton matrix applied to one row's bed derivative d. */
+static void pin_row(const prob *P, const unsigned char *iso, const double *U, int idx, double *d)
+{
+    if (iso[idx]) {
+        for (int r = 0; r < P->nc; ++r) d[r] = 0.0;
+    } else if (P->p->dry_pin && U[idx] == 0.0) {
+        for (int r = 1; r < P->nc; ++r) d[r] = 0.0;
+    }
+}
+
+/* For each cell j, with its bed raised to z_j + eps (eps = fd_eps, the
+ * absolute step of eq:NumerDiff):
+ *   dR_j/dz_j = sum over j's faces (W, E, S, N) of |e| (T(z_j + eps) - T) / eps,
+ *     a boundary face's ghost carrying the raised bed (ghost bed = own bed);
+ *   dR_i/dz_j = |e| (T(z_j + eps) - T) / eps for each neighbour i, T being i's
+ *     edge term on its face towards j;
+ * then out_j = lam_j . dR_j/dz_j + sum over j's neighbours (W, E, S, N) of
+ * lam_i . dR_i/dz_j, each dot product over the components in order. */
+int orc_bed_vjp(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
+                const double *z, const double *U, const double *lam, double *out)
+{
+    prob P;
+    if (setup(&P, gr, bc, p, z)) return ORC_EINVAL;
+    int nx = gr->nx, ny = gr->ny, nc = P.nc, N = P.N, ni, nj;
+    double *zw = (double *)malloc(sizeof(double) * (size_t)N);
+    unsigned char *iso = (unsigned char *)malloc((size_t)N);
+    if (!zw || !iso) { free(zw); free(iso); return ORC_EINVAL; }
+    memcpy(zw, z, sizeof(double) * (size_t)N);
+    orc_isolated(gr, bc, p, z, U, iso);
+    P.z = zw;
+    const double eps = p->fd_eps;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int idx = j * nx + i;
+            double Uo[3], Un[3] = {0, 0, 0}, T0[3], Tp[3], d[3];
+            load_cell(&P, U, idx, Uo);
+            for (int r = 0; r < nc; ++r) d[r] = 0.0;
+            for (int f = 0; f < P.nf; ++f) {
+                double e = P.elen[f];
+                if (nbr(gr->dim, nx, ny, i, j, f, &ni, &nj)) load_cell(&P, U, nj * nx + ni, Un);
+                cell_edge(&P, i, j, f, Uo, Un, T0);
+                zw[idx] = z[idx] + eps;
+                cell_edge(&P, i, j, f, Uo, Un, Tp);
+                zw[idx] = z[idx];
+                for (int r = 0; r < nc; ++r) d[r] = d[r] + e * ((Tp[r] - T0[r]) / eps);
+            }
+            pin_row(&P, iso, U, idx, d);
+            double acc = 0.0;
+            for (int r = 0; r < nc; ++r) acc = acc + lam[r * N + idx] * d[r];
+            for (int f = 0; f < P.nf; ++f) {
+                if (!nbr(gr->dim, nx, ny, i, j, f, &ni, &nj)) continue;
+                int nidx = nj * nx + ni, g = OPP[f];
+                double e = P.elen[g];
+                load_cell(&P, U, nidx, Un);
+                cell_edge(&P, ni, nj, g, Un, Uo, T0);
+                zw[idx] = z[idx] + eps;
+                cell_edge(&P, ni, nj, g, Un, Uo, Tp);
+                zw[idx] = z[idx];
+                for (int r = 0; r < nc; ++r) d[r] = e * ((Tp[r] - T0[r]) / eps);
+                pin_row(&P, iso, U, nidx, d);
+                for (int r = 0; r < nc; ++r) acc = acc + lam[r * N + nidx] * d[r];
+            }
+            out[idx] = acc;
+        }
+    free(zw);
+    free(iso);
+    return ORC_OK;
+}

@@ -103,6 +103,15 @@ void orc_threshold(const orc_grid *gr, const orc_params *p, double *U);
 int orc_newton_solve(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
                      const double *z, double *U, double tol, orc_stats *st);
 
+/* --- sensitivities (adjoint of the steady state) ------------------------- */
+/* Exact block transpose: At's block at cell i towards neighbour j is A's
+ * block at j towards i, transposed; diagonal blocks transposed in place. */
+void orc_transpose_blocks(int dim, int nx, int ny, const double *A, double *At);
+/* out = (dR/dz)^T lam by forward differences of the edge terms in the bed,
+ * rows pinned as in orc_assemble (see the definition). */
+int orc_bed_vjp(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
+                const double *z, const double *U, const double *lam, double *out);
+
 #ifdef __cplusplus
 }
 #endif
