@@ -175,6 +175,35 @@ int nmg_load_system(nmg_ctx *ctx, const double *A0, const double *b0);
  * ny >> level in 2D).  Coarse right-hand sides are those of the last cycle. */
 int nmg_get_system(nmg_ctx *ctx, int level, double *A, double *b);
 
+/* ---- Sensitivities of the steady state ------------------------------------
+ * At a steady state R(U, z) = 0 an objective J(U, z) has the bed gradient
+ * dJ/dz = dJ/dz|_U - (dR/dz)^T lambda, with (dR/dU)^T lambda = (dJ/dU)^T and
+ * dR/dU the Newton matrix of eq:MatrixForm at (z, U) (the linearization the
+ * solver uses, pinned rows included). */
+
+/* Adjoint solve: assembles the Newton matrix at (z, U), transposes it block
+ * by block (the transpose's block at cell i towards j is the transpose of
+ * the block at j towards i), builds its Galerkin levels (which are the
+ * transposes of the original's) and runs multigrid cycles of the context's
+ * kind on A^T lambda = g from the given lambda (in/out, cell-vector layout)
+ * until ||g - A^T lambda||_1 <= tol ||g - A^T lambda_in||_1 or max_cycles
+ * cycles.  cycles_host and rel_res_host (nullable) receive the number of
+ * cycles and the final relative residual.  The transposed system stays in
+ * the context (nmg_get_system shows it).  Synchronizes the stream. */
+int nmg_adjoint_solve(nmg_ctx *ctx, const double *z, const double *U, const double *g,
+                      double *lambda, double tol, int max_cycles, int *cycles_host,
+                      double *rel_res_host);
+
+/* out[ny][nx] = (dR/dz)^T lambda at (z, U): forward differences of the edge
+ * terms in the bed with the absolute step fd_eps, face by face as the
+ * Jacobian assembly differentiates in U (a boundary face's ghost carries the
+ * raised bed), rows pinned as in the Newton matrix (isolated cell: zero row;
+ * exactly dry cell with dry_pin: zero momentum rows).  out_j sums
+ * lambda_j . dR_j/dz_j, then lambda_i . dR_i/dz_j over j's neighbours in W,
+ * E, S, N order.  Stream-ordered, no synchronization. */
+int nmg_bed_vjp(nmg_ctx *ctx, const double *z, const double *U, const double *lambda,
+                double *out);
+
 /* Measurement hooks.  With enable = 1 the library records a pair of
  * hipEvents on its stream around each full finest-level block SGS half
  * sweep (one that reads every neighbour block), for at most `cap`

@@ -47,6 +47,9 @@ struct nmg_ctx {
     int dim = 0, nc = 0, nb = 0, ne = 0, NL = 0;
     bool f32 = false;                 // FP32 inner V-cycle
     Level L[16];
+    void *pool = nullptr;             // the hierarchy's allocation
+    void *At_alloc = nullptr;         // second level-0 matrix (adjoint transpose), owned
+    void *At_spare = nullptr;         // whichever of the two level-0 matrices is not L[0].A
     unsigned char *iso = nullptr;
     double *partial = nullptr;    // per-block partial sums
     double *scal = nullptr;       // device scalars
@@ -473,6 +476,14 @@ int assemble(nmg_ctx *c, const double *z, const double *U, double *R_out, double
     return NMG_OK;
 }
 
+// l1 norm of level 0's linear residual b - A x (synchronizes).
+int level0_residual_norm(nmg_ctx *c, double *out)
+{
+    Level &L0 = c->L[0];
+    HIPCHK(c, launch_lin_res_norm(c->dim, c->f32, L0.G, L0.A, L0.b, L0.x, c->partial, c->stream));
+    return reduce_to_host(c, nblocks(cells(L0.G)), out);
+}
+
 int count_pinned(nmg_ctx *c, const double *z, const double *U, int *n)
 {
     long N = cells(c->L[0].G);
@@ -566,6 +577,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
         delete c;
         return NMG_ENOMEM;
     }
+    c->pool = pool;
     size_t off = 0;
     for (int l = 0; l <= c->NL; ++l) {
         Level &Lv = c->L[l];
@@ -606,7 +618,8 @@ void nmg_destroy(nmg_ctx *c)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
-    if (c->L[0].A) (void)hipFree(c->L[0].A);
+    if (c->pool) (void)hipFree(c->pool);
+    if (c->At_alloc) (void)hipFree(c->At_alloc);
     if (c->iso) (void)hipFree(c->iso);
     if (c->partial) (void)hipFree(c->partial);
     if (c->scal) (void)hipFree(c->scal);
@@ -743,6 +756,56 @@ int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return status;
+}
+
+int nmg_adjoint_solve(nmg_ctx *c, const double *z, const double *U, const double *g,
+                      double *lambda, double tol, int max_cycles, int *cycles_host,
+                      double *rel_res_host)
+{
+    if (!c) return NMG_EINVAL;
+    if (!z || !U || !g || !lambda) return fail(c, NMG_EINVAL, "null z, U, g or lambda");
+    if (max_cycles < 0 || !(tol >= 0)) return fail(c, NMG_EINVAL, "bad tol or max_cycles");
+    Level &L0 = c->L[0];
+    const size_t mbytes = (size_t)2 * c->ne * L0.G.planeP * (c->f32 ? sizeof(float) : sizeof(double));
+    if (!c->At_alloc) {
+        if (hipMalloc(&c->At_alloc, mbytes) != hipSuccess) return fail(c, NMG_ENOMEM, "adjoint matrix");
+        c->At_spare = c->At_alloc;
+    }
+    HIPCHK(c, launch_isolated(c->P, z, U, c->iso, c->stream));
+    HIPCHK(c, launch_assemble(c->P, L0.G, z, U, c->iso, L0.A, L0.b, c->f32, nullptr, c->partial,
+                              c->stream));
+    HIPCHK(c, launch_transpose(c->dim, c->f32, L0.G, L0.A, c->At_spare, c->stream));
+    std::swap(L0.A, c->At_spare);
+    int rc = build_coarse(c);
+    if (rc) return rc;
+    HIPCHK(c, launch_vec_to_split(c->nc, c->f32, L0.G, g, L0.b, c->stream));
+    HIPCHK(c, launch_vec_to_split(c->nc, c->f32, L0.G, lambda, L0.x, c->stream));
+    L0.st[0] = L0.st[1] = ST_VALID;
+    L0.last = -1;
+    double r0 = 0.0, r = 0.0;
+    if ((rc = level0_residual_norm(c, &r0))) return rc;
+    r = r0;
+    int k = 0;
+    while (k < max_cycles && r > tol * r0) {
+        if ((rc = cycle(c, 0))) return rc;
+        if ((rc = materialize(c, 0))) return rc;
+        ++k;
+        if ((rc = level0_residual_norm(c, &r))) return rc;
+    }
+    HIPCHK(c, launch_vec_from_split(c->nc, c->f32, L0.G, L0.x, lambda, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (cycles_host) *cycles_host = k;
+    if (rel_res_host) *rel_res_host = r0 > 0.0 ? r / r0 : 0.0;
+    return NMG_OK;
+}
+
+int nmg_bed_vjp(nmg_ctx *c, const double *z, const double *U, const double *lambda, double *out)
+{
+    if (!c) return NMG_EINVAL;
+    if (!z || !U || !lambda || !out) return fail(c, NMG_EINVAL, "null z, U, lambda or out");
+    HIPCHK(c, launch_isolated(c->P, z, U, c->iso, c->stream));
+    HIPCHK(c, launch_bed_vjp(c->P, z, U, c->iso, lambda, out, c->stream));
+    return NMG_OK;
 }
 
 int nmg_timing_enable(nmg_ctx *c, int enable, int cap)

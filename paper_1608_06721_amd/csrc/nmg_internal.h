@@ -131,6 +131,16 @@ hipError_t launch_fix_color(int dim, bool f32, int op, const LevelGeom &G, void 
 hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
                                const LevelDev *lv, int l_lds, int nl, hipStream_t s);
 
+// Sensitivities: block transpose of a level matrix (A and At distinct), the
+// bed vector-Jacobian product (dR/dz)^T lam, and the l1 norm of a level's
+// linear residual as per-block partial sums (nblocks(nx * ny) of them).
+hipError_t launch_transpose(int dim, bool f32, const LevelGeom &G, const void *A, void *At,
+                            hipStream_t s);
+hipError_t launch_bed_vjp(const Phys &P, const double *z, const double *U,
+                          const unsigned char *iso, const double *lam, double *out, hipStream_t s);
+hipError_t launch_lin_res_norm(int dim, bool f32, const LevelGeom &G, const void *A,
+                               const void *b, const void *x, double *partial, hipStream_t s);
+
 // ---- batches of independent problems -------------------------------------
 // One instance of a batch at the Newton level.
 struct BatchInst {

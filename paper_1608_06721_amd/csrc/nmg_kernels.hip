@@ -1112,6 +1112,162 @@ __global__ void __launch_bounds__(kBlock) k_mat_from_tiled(int ne, LevelGeom G,
 
 
 // ---------------------------------------------------------------------------
+// Sensitivities of the steady state (the adjoint extension).
+
+// Face of the neighbour across face f that faces back.
+__device__ __forceinline__ int opposite(int f) { return f ^ 1; }   // W<->E, S<->N
+
+// Block transpose of a level matrix: At's block at slot t (colour c) towards
+// neighbour j is A's block at j towards this cell, transposed; the diagonal
+// block is transposed in place; blocks pointing out of the grid are zero.
+// One thread per slot of both colours.
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) k_transpose(LevelGeom G, const T *__restrict__ A,
+                                                      T *__restrict__ At)
+{
+    constexpr int NF = (NC == 2) ? 2 : 4;
+    constexpr int NN = NC * NC;
+    constexpr int NE = (NF + 1) * NN;
+    const long k = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= 2 * G.plane) return;
+    const int color = k >= G.plane ? 1 : 0;
+    const long t = k - color * G.plane;
+    const int j = (int)(t / G.W), kk = (int)(t % G.W);
+    const int i = 2 * kk + ((j + color) & 1);
+    if (i >= G.nx) return;
+    const T *Am = A + mat_off(G, NE, color, t);
+    T *Om = At + mat_off(G, NE, color, t);
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) Om[(r * NC + c) * kTile] = Am[(c * NC + r) * kTile];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        int ni = i, nj = j;
+        bool ok;
+        if (f == FW) { ni = i - 1; ok = i > 0; }
+        else if (f == FE) { ni = i + 1; ok = i + 1 < G.nx; }
+        else if (f == FS) { nj = j - 1; ok = j > 0; }
+        else { nj = j + 1; ok = j + 1 < G.ny; }
+        if (ok) {
+            const T *Nm = A + mat_off(G, NE, color ^ 1, (long)nj * G.W + (ni >> 1)) +
+                          (opposite(f) + 1) * NN * kTile;
+#pragma unroll
+            for (int r = 0; r < NC; ++r)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    Om[((f + 1) * NN + r * NC + c) * kTile] = Nm[(c * NC + r) * kTile];
+        } else {
+#pragma unroll
+            for (int e = 0; e < NN; ++e) Om[((f + 1) * NN + e) * kTile] = T(0);
+        }
+    }
+}
+
+// Row pins of the Newton matrix applied to one row's bed derivative d.
+template <int NC>
+__device__ __forceinline__ void pin_bed_row(const Phys &P, const unsigned char *iso,
+                                            const double *U, long idx, double *d)
+{
+    if (iso[idx]) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) d[r] = 0.0;
+    } else if (P.dry_pin && U[idx] == 0.0) {
+#pragma unroll
+        for (int r = 1; r < NC; ++r) d[r] = 0.0;
+    }
+}
+
+// out_j = (dR/dz)^T lam at cell j: the bed of j raised by eps = fd_eps,
+// dR_j/dz_j = sum over j's faces (W, E, S, N) of |e| (T(z_j + eps) - T) / eps
+// (a boundary face's ghost carries the raised bed), dR_i/dz_j = |e| (T(z_j +
+// eps) - T) / eps of each neighbour i's face towards j, rows pinned as in
+// the assembly; out_j = lam_j . dR_j/dz_j, then + lam_i . dR_i/dz_j for the
+// neighbours in W, E, S, N order, dot products in component order.
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_bed_vjp(Phys P, const double *__restrict__ z,
+                                                    const double *__restrict__ U,
+                                                    const unsigned char *__restrict__ iso,
+                                                    const double *__restrict__ lam,
+                                                    double *__restrict__ out)
+{
+    constexpr int NF = (NC == 2) ? 2 : 4;
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    const long idx = (long)xb * kBlock + threadIdx.x;
+    const long N = (long)P.nx * P.ny;
+    if (idx >= N) return;
+    const int i = (int)(idx % P.nx), j = (int)(idx / P.nx);
+    const double eps = P.eps;
+    double qo[NC];
+    load_state<NC>(P, U, idx, qo);
+    const Side own = cell_side<NC>(P, qo, z[idx]);
+    Side ownp = own;
+    ownp.z = z[idx] + eps;
+    double d[NC], T0[NC], Tp[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) d[r] = 0.0;
+    for (int f = 0; f < NF; ++f) {
+        const double e = P.elen[f];
+        int ni, nj;
+        if (neighbour(P, i, j, f, ni, nj)) {
+            const long nidx = (long)nj * P.nx + ni;
+            double qn[NC];
+            load_state<NC>(P, U, nidx, qn);
+            const Side oth = cell_side<NC>(P, qn, z[nidx]);
+            edge_term<NC>(P, f, own, oth, T0);
+            edge_term<NC>(P, f, ownp, oth, Tp);
+        } else {
+            edge_term<NC>(P, f, own, ghost(P, f, own), T0);
+            edge_term<NC>(P, f, ownp, ghost(P, f, ownp), Tp);
+        }
+#pragma unroll
+        for (int r = 0; r < NC; ++r) d[r] = d[r] + e * ((Tp[r] - T0[r]) / eps);
+    }
+    pin_bed_row<NC>(P, iso, U, idx, d);
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) acc = acc + lam[r * N + idx] * d[r];
+    for (int f = 0; f < NF; ++f) {
+        int ni, nj;
+        if (!neighbour(P, i, j, f, ni, nj)) continue;
+        const long nidx = (long)nj * P.nx + ni;
+        const int g = opposite(f);
+        const double e = P.elen[g];
+        double qn[NC];
+        load_state<NC>(P, U, nidx, qn);
+        const Side nb = cell_side<NC>(P, qn, z[nidx]);
+        edge_term<NC>(P, g, nb, own, T0);
+        edge_term<NC>(P, g, nb, ownp, Tp);
+#pragma unroll
+        for (int r = 0; r < NC; ++r) d[r] = e * ((Tp[r] - T0[r]) / eps);
+        pin_bed_row<NC>(P, iso, U, nidx, d);
+#pragma unroll
+        for (int r = 0; r < NC; ++r) acc = acc + lam[r * N + nidx] * d[r];
+    }
+    out[idx] = acc;
+}
+
+// l1 norm of the linear residual b - A x over a level's cells (block sums).
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) k_lin_res_norm(LevelGeom G, const T *__restrict__ A,
+                                                         const T *__restrict__ b,
+                                                         const T *__restrict__ x,
+                                                         double *__restrict__ partial)
+{
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    const long idx = (long)xb * kBlock + threadIdx.x;
+    double v = 0.0;
+    if (idx < (long)G.nx * G.ny) {
+        T r[NC];
+        lin_residual_cell<T, NC>(G, A, b, x, (int)(idx % G.nx), (int)(idx / G.nx), r);
+        v = dabs(double(r[0])) + dabs(double(r[1]));
+        if (NC == 3) v = v + dabs(double(r[2]));
+    }
+    double s = block_sum(v);
+    if (threadIdx.x == 0) partial[xb] = s;
+}
+
+// ---------------------------------------------------------------------------
 // Batched kernels: one block per work item (instance, tile), in XCD-aware
 // order; the per-cell work is the same function as in the single-problem
 // kernels, so every instance's results are those of its own solve.  Tiles of
@@ -1478,6 +1634,40 @@ hipError_t launch_coarse_cycle(int dim, bool f32, const CoarseOp *ops, int nops,
 #undef NMG_COARSE
 }
 
+
+// ---- sensitivities ----
+
+hipError_t launch_transpose(int dim, bool f32, const LevelGeom &G, const void *A, void *At,
+                            hipStream_t s)
+{
+    int g = nblocks(2 * G.plane);
+    if (f32) {
+        if (dim == 1) NMG_LAUNCH((k_transpose<float, 2>), g, G, (const float *)A, (float *)At);
+        NMG_LAUNCH((k_transpose<float, 3>), g, G, (const float *)A, (float *)At);
+    }
+    if (dim == 1) NMG_LAUNCH((k_transpose<double, 2>), g, G, (const double *)A, (double *)At);
+    NMG_LAUNCH((k_transpose<double, 3>), g, G, (const double *)A, (double *)At);
+}
+
+hipError_t launch_bed_vjp(const Phys &P, const double *z, const double *U,
+                          const unsigned char *iso, const double *lam, double *out, hipStream_t s)
+{
+    int g = nblocks((long)P.nx * P.ny);
+    if (P.dim == 1) NMG_LAUNCH(k_bed_vjp<2>, g, P, z, U, iso, lam, out);
+    NMG_LAUNCH(k_bed_vjp<3>, g, P, z, U, iso, lam, out);
+}
+
+hipError_t launch_lin_res_norm(int dim, bool f32, const LevelGeom &G, const void *A,
+                               const void *b, const void *x, double *partial, hipStream_t s)
+{
+    int g = nblocks((long)G.nx * G.ny);
+    if (f32) {
+        if (dim == 1) NMG_LAUNCH((k_lin_res_norm<float, 2>), g, G, (const float *)A, (const float *)b, (const float *)x, partial);
+        NMG_LAUNCH((k_lin_res_norm<float, 3>), g, G, (const float *)A, (const float *)b, (const float *)x, partial);
+    }
+    if (dim == 1) NMG_LAUNCH((k_lin_res_norm<double, 2>), g, G, (const double *)A, (const double *)b, (const double *)x, partial);
+    NMG_LAUNCH((k_lin_res_norm<double, 3>), g, G, (const double *)A, (const double *)b, (const double *)x, partial);
+}
 
 // ---- batched launchers ----
 

@@ -54,7 +54,8 @@ EXPORTS = ["nmg_create", "nmg_destroy", "nmg_last_error", "nmg_residual",
            "nmg_assemble_residual_jacobian", "nmg_mg_vcycle", "nmg_sgs", "nmg_blu_sweep",
            "nmg_newton_mg_solve", "nmg_load_system", "nmg_get_system", "nmg_timing_enable",
            "nmg_timing_read", "nmg_batch_create", "nmg_batch_destroy", "nmg_batch_last_error",
-           "nmg_batch_autotune", "nmg_batch_newton_mg_solve"]
+           "nmg_batch_autotune", "nmg_batch_newton_mg_solve", "nmg_adjoint_solve",
+           "nmg_bed_vjp"]
 
 
 def library_path() -> str:
@@ -86,6 +87,9 @@ def lib():
         L.nmg_timing_enable.argtypes = [vp, C.c_int, C.c_int]
         L.nmg_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                       C.POINTER(C.c_longlong)]
+        L.nmg_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int,
+                                        C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.nmg_bed_vjp.argtypes = [vp, vp, vp, vp, vp]
         L.nmg_batch_create.argtypes = [C.c_int, C.POINTER(nmg_grid), C.POINTER(nmg_bc),
                                        C.POINTER(nmg_params), vp, C.POINTER(vp)]
         L.nmg_batch_destroy.argtypes = [vp]
@@ -230,6 +234,25 @@ class Context:
         b = torch.empty((self.nc, ny, nx), dtype=torch.float64, device=dev) if want_b else None
         self._check(lib().nmg_get_system(self._h, int(level), _ptr(A, "A"), _ptr(b, "b")))
         return A, b
+
+    def adjoint_solve(self, z, U, g, lam=None, tol=1e-12, max_cycles=200):
+        """Solve (dR/dU)^T lam = g at (z, U) by multigrid (nmg_adjoint_solve);
+        returns (lam, cycles, relative residual)."""
+        if lam is None:
+            lam = torch.zeros_like(g)
+        cyc, rel = C.c_int(0), C.c_double(0.0)
+        self._check(lib().nmg_adjoint_solve(self._h, _ptr(z, "z"), _ptr(U, "U"), _ptr(g, "g"),
+                                            _ptr(lam, "lambda"), float(tol), int(max_cycles),
+                                            C.byref(cyc), C.byref(rel)))
+        return lam, cyc.value, rel.value
+
+    def bed_vjp(self, z, U, lam, out=None):
+        """(dR/dz)^T lam at (z, U) as a [ny][nx] tensor (nmg_bed_vjp)."""
+        if out is None:
+            out = torch.empty_like(z)
+        self._check(lib().nmg_bed_vjp(self._h, _ptr(z, "z"), _ptr(U, "U"), _ptr(lam, "lambda"),
+                                      _ptr(out, "out")))
+        return out
 
     def timing_enable(self, enable=True, cap=4096):
         self._check(lib().nmg_timing_enable(self._h, int(bool(enable)), int(cap)))
