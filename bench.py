@@ -146,6 +146,71 @@ def batched(args):
     }
 
 
+def adjoint_gradients(args):
+    """Bed gradients of a gauge misfit: for each of `args.adjoint`
+    topographies (512^2 channels), the steady state (FP64 W-cycle Newton
+    multigrid), the objective sum over 64 gauges of (h + z - target)^2 with
+    targets from the steady state over a perturbed bed (untimed), and its
+    gradient through the autograd Function (adjoint multigrid solve to 1e-12
+    relative, then the bed vector-Jacobian product).  Timed: forward solve +
+    objective + backward, per topography."""
+    import torch
+    from paper_1608_06721_amd import adjoint, nmg
+    from paper_1608_06721_amd import workloads as W
+    n = args.adjoint_size
+    levels = int(math.log2(n)) - 4
+    cases = W.gauge_cases(args.adjoint, size=n, n_levels=levels, gamma=2,
+                          max_newton=args.max_newton)
+    ctx = nmg.Context.from_problem(cases[0].prob)
+    times, fwd, adj, steps, skipped = [], [], [], [], []
+    for c in cases:
+        p = c.prob
+        Ut = torch.from_numpy(p.U0).cuda()
+        st = ctx.newton_mg_solve(torch.from_numpy(c.z_true).cuda(), Ut, args.tol)
+        if st["status"] != "OK":           # no steady state, no target: not a gradient case
+            skipped.append("%s (target solve %s)" % (p.name, st["status"]))
+            continue
+        g = torch.from_numpy(c.gauges).cuda()
+        target = (Ut[0] + torch.from_numpy(c.z_true).cuda()).reshape(-1)[g]
+        z = torch.from_numpy(p.z).cuda().requires_grad_(True)
+        U0 = torch.from_numpy(p.U0).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            U = adjoint.steady_state(ctx, z, U0, tol=args.tol, adj_tol=1e-12)
+        except nmg.NMGError as e:
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            skipped.append("%s (%s)" % (p.name, e))
+            continue
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J = adjoint.gauge_misfit(U, z, g, target)
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append(t2 - t0)
+        fwd.append(t1 - t0)
+        adj.append(t2 - t1)
+        steps.append(U.grad_fn.stats["newton_steps"])
+    ctx.close()
+    tot = sum(times)
+    ng = len(fwd)
+    print("[bench] adjoint: %d gradients in %.3f s (forward %.3f s), %d skipped"
+          % (ng, tot, sum(fwd), len(skipped)), file=sys.stderr, flush=True)
+    return {
+        "value": ng / tot if ng else None, "unit": "gradients/s", "topographies": len(cases),
+        "gradients": ng, "skipped": skipped,
+        "grid": "%dx%d" % (n, n), "ms_per_gradient": 1e3 * tot / max(ng, 1),
+        "ms_forward_mean": 1e3 * sum(fwd) / max(ng, 1),
+        "ms_adjoint_mean": 1e3 * sum(adj) / max(ng, 1),
+        "newton_steps_mean": float(sum(steps)) / max(len(steps), 1), "n_levels": levels,
+        "dtype": "f64", "gauges": 64, "adjoint_rel_tol": 1e-12,
+        "workload": "gauge misfit on %d channels %dx%d (seeds %d+b)" % (len(cases), n, n,
+                                                                      W.ADJOINT_SEED),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +234,9 @@ def main():
                     help="instances of the batched-solve workload (0: skip it)")
     ap.add_argument("--batch-levels", type=int, default=5)
     ap.add_argument("--batch-max-newton", type=int, default=150)
+    ap.add_argument("--adjoint", type=int, default=16,
+                    help="topographies of the gauge-misfit gradient workload (0: skip it)")
+    ap.add_argument("--adjoint-size", type=int, default=512)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--timing-cap", type=int, default=20000)
     ap.add_argument("--kernel-probe", action="store_true",
@@ -301,6 +369,8 @@ def main():
     ctx32.close()
     if args.batch > 0:
         out["batched"] = batched(args)
+    if args.adjoint > 0:
+        out["adjoint"] = adjoint_gradients(args)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, n_newton, args.cpu_budget)

@@ -184,14 +184,17 @@ int nmg_get_system(nmg_ctx *ctx, int level, double *A, double *b);
 /* Adjoint solve: assembles the Newton matrix at (z, U), transposes it block
  * by block (the transpose's block at cell i towards j is the transpose of
  * the block at j towards i), builds its Galerkin levels (which are the
- * transposes of the original's) and runs multigrid cycles of the context's
- * kind on A^T lambda = g from the given lambda (in/out, cell-vector layout)
- * until ||g - A^T lambda||_1 <= tol ||g - A^T lambda_in||_1 or max_cycles
- * cycles.  cycles_host and rel_res_host (nullable) receive the number of
- * cycles and the final relative residual.  The transposed system stays in
- * the context (nmg_get_system shows it).  Synchronizes the stream. */
+ * transposes of the original's) and solves A^T lambda = g from the given
+ * lambda (in/out, cell-vector layout) with multigrid cycles of the context's
+ * kind: krylov = 0 iterates the cycles until ||g - A^T lambda||_1 <=
+ * tol ||g - A^T lambda_in||_1; krylov = m > 0 (FP64 contexts, m <= 200)
+ * accelerates them with GMRES(m), one cycle from zero being the right
+ * preconditioner, until the 2-norm residual falls by tol.  At most
+ * max_cycles cycles.  cycles_host and rel_res_host (nullable) receive the
+ * number of cycles and the final l1 relative residual.  The transposed
+ * system stays in the context (nmg_get_system shows it).  Synchronizes. */
 int nmg_adjoint_solve(nmg_ctx *ctx, const double *z, const double *U, const double *g,
-                      double *lambda, double tol, int max_cycles, int *cycles_host,
+                      double *lambda, double tol, int max_cycles, int krylov, int *cycles_host,
                       double *rel_res_host);
 
 /* out[ny][nx] = (dR/dz)^T lambda at (z, U): forward differences of the edge

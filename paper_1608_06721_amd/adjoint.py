@@ -17,13 +17,13 @@ from . import nmg
 
 class SteadyState(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, z, U0, solver, tol, adj_tol, adj_cycles):
+    def forward(ctx, z, U0, solver, tol, adj_tol, adj_cycles, krylov):
         U = U0.detach().clone()
         st = solver.newton_mg_solve(z.detach(), U, tol)
         if st["status"] != "OK":
             raise nmg.NMGError(1, "steady solve did not converge: %s" % st["status"])
         ctx.save_for_backward(z.detach(), U)
-        ctx.solver, ctx.adj_tol, ctx.adj_cycles = solver, adj_tol, adj_cycles
+        ctx.solver, ctx.adj_tol, ctx.adj_cycles, ctx.krylov = solver, adj_tol, adj_cycles, krylov
         ctx.stats = st
         return U
 
@@ -31,18 +31,21 @@ class SteadyState(torch.autograd.Function):
     def backward(ctx, gU):
         z, U = ctx.saved_tensors
         lam, cycles, rel = ctx.solver.adjoint_solve(z, U, gU.contiguous(), tol=ctx.adj_tol,
-                                                    max_cycles=ctx.adj_cycles)
-        if rel > ctx.adj_tol:
+                                                    max_cycles=ctx.adj_cycles, krylov=ctx.krylov)
+        ctx.adjoint_cycles, ctx.adjoint_rel = cycles, rel
+        if cycles >= ctx.adj_cycles and rel > ctx.adj_tol:
             raise nmg.NMGError(1, "adjoint solve reached %d cycles at relative residual %.3e"
                                % (cycles, rel))
         gz = -ctx.solver.bed_vjp(z, U, lam)
-        return gz, None, None, None, None, None
+        return gz, None, None, None, None, None, None
 
 
-def steady_state(solver, z, U0, tol=1e-10, adj_tol=1e-12, adj_cycles=200):
+def steady_state(solver, z, U0, tol=1e-10, adj_tol=1e-12, adj_cycles=400, krylov=30):
     """U*(z) from U0 with `solver` (an nmg.Context for the grid and BC),
-    differentiable with respect to z."""
-    return SteadyState.apply(z, U0, solver, tol, adj_tol, adj_cycles)
+    differentiable with respect to z; the backward pass solves the adjoint to
+    a relative residual adj_tol with GMRES(krylov)-accelerated cycles
+    (krylov = 0: plain cycles) within adj_cycles cycles."""
+    return SteadyState.apply(z, U0, solver, tol, adj_tol, adj_cycles, krylov)
 
 
 def gauge_misfit(U, z, gauges, target):

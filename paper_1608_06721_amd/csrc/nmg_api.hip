@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -50,6 +51,10 @@ struct nmg_ctx {
     void *pool = nullptr;             // the hierarchy's allocation
     void *At_alloc = nullptr;         // second level-0 matrix (adjoint transpose), owned
     void *At_spare = nullptr;         // whichever of the two level-0 matrices is not L[0].A
+    // Krylov acceleration of the adjoint solve (allocated on first use)
+    int km = 0;                       // restart length the buffers were sized for
+    double *kV = nullptr, *kg = nullptr, *kx = nullptr, *kw = nullptr;
+    double *kpart = nullptr, *kdots = nullptr, *kcoef = nullptr, *h_k = nullptr;
     unsigned char *iso = nullptr;
     double *partial = nullptr;    // per-block partial sums
     double *scal = nullptr;       // device scalars
@@ -484,6 +489,151 @@ int level0_residual_norm(nmg_ctx *c, double *out)
     return reduce_to_host(c, nblocks(cells(L0.G)), out);
 }
 
+// ---- Krylov acceleration of the adjoint solve ------------------------------
+// Right-preconditioned GMRES(m) on level 0's system A x = b (the transposed
+// Newton matrix and the adjoint right-hand side), the preconditioner being
+// one multigrid cycle from zero.  Classical Gram-Schmidt with one
+// re-orthogonalization pass; Givens rotations on the host; the true residual
+// is recomputed at each restart.  Stops when ||b - A x||_2 <= tol ||b - A x0||_2
+// or after max_cycles preconditioner applications; x is left in L[0].x
+// (materialized) and b in L[0].b.
+
+int kbuffers(nmg_ctx *c, int m)
+{
+    if (c->km == m) return NMG_OK;
+    for (double **q : {&c->kV, &c->kg, &c->kx, &c->kw, &c->kpart, &c->kdots, &c->kcoef}) {
+        if (*q) (void)hipFree(*q);
+        *q = nullptr;
+    }
+    if (c->h_k) (void)hipHostFree(c->h_k);
+    c->h_k = nullptr;
+    c->km = 0;
+    const long n = 2L * c->nc * c->L[0].G.plane;
+    const size_t vb = sizeof(double) * (size_t)n;
+    bool ok = hipMalloc(&c->kV, vb * (m + 1)) == hipSuccess && hipMalloc(&c->kg, vb) == hipSuccess &&
+              hipMalloc(&c->kx, vb) == hipSuccess && hipMalloc(&c->kw, vb) == hipSuccess &&
+              hipMalloc(&c->kpart, sizeof(double) * (size_t)(m + 1) * nblocks(n)) == hipSuccess &&
+              hipMalloc(&c->kdots, sizeof(double) * (m + 1)) == hipSuccess &&
+              hipMalloc(&c->kcoef, sizeof(double) * (m + 1)) == hipSuccess &&
+              hipHostMalloc(&c->h_k, sizeof(double) * (m + 1), hipHostMallocDefault) == hipSuccess;
+    if (!ok) return fail(c, NMG_ENOMEM, "Krylov vectors");
+    c->km = m;
+    return NMG_OK;
+}
+
+// out[k] = <V_k, w>, k < nv, to the host (synchronizes).
+int kdots(nmg_ctx *c, long n, const double *V, int nv, const double *w, double *out)
+{
+    HIPCHK(c, launch_multidot(n, V, n, nv, w, c->kpart, c->kdots, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h_k, c->kdots, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int k = 0; k < nv; ++k) out[k] = c->h_k[k];
+    return NMG_OK;
+}
+
+// w = a w - sum_k coef[k] V_k.
+int kaxpy(nmg_ctx *c, long n, const double *V, int nv, const double *coef, double a, double *w)
+{
+    if (nv > 0) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));        // h_k is reused by the next transfer
+        for (int k = 0; k < nv; ++k) c->h_k[k] = coef[k];
+        HIPCHK(c, hipMemcpyAsync(c->kcoef, c->h_k, sizeof(double) * nv, hipMemcpyHostToDevice,
+                                 c->stream));
+    }
+    HIPCHK(c, launch_multi_axpy(n, V, n, nv, c->kcoef, a, w, c->stream));
+    return NMG_OK;
+}
+
+// x_out = M^-1 v: one multigrid cycle from zero on right-hand side v.
+int kprecond(nmg_ctx *c, const double *v, long n)
+{
+    Level &L0 = c->L[0];
+    HIPCHK(c, hipMemcpyAsync(L0.b, v, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    set_zero(c, 0);
+    int rc = cycle(c, 0);
+    if (!rc) rc = materialize(c, 0);
+    return rc;
+}
+
+int adjoint_gmres(nmg_ctx *c, int m, double tol, int max_cycles, int *cycles)
+{
+    int rc = kbuffers(c, m);
+    if (rc) return rc;
+    Level &L0 = c->L[0];
+    const long n = 2L * c->nc * L0.G.plane;
+    const size_t vb = sizeof(double) * (size_t)n;
+    double *V = c->kV;
+    HIPCHK(c, hipMemcpyAsync(c->kg, L0.b, vb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->kx, L0.x, vb, hipMemcpyDeviceToDevice, c->stream));
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), sv(m + 1), y(m), h(m + 1),
+        h2(m + 1);
+    auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    int k = 0;
+    double beta = 0.0, beta0 = -1.0;
+    for (;;) {
+        HIPCHK(c, launch_lin_res_vec(c->dim, L0.G, (const double *)L0.A, c->kg, c->kx, V, c->stream));
+        if ((rc = kdots(c, n, V, 1, V, &beta))) return rc;
+        beta = std::sqrt(beta);
+        if (beta0 < 0) beta0 = beta;
+        if (beta <= tol * beta0 || beta == 0.0 || k >= max_cycles) break;
+        if ((rc = kaxpy(c, n, V, 0, nullptr, 1.0 / beta, V))) return rc;
+        std::fill(sv.begin(), sv.end(), 0.0);
+        sv[0] = beta;
+        int j = 0;
+        bool done = false;
+        for (; j < m && k < max_cycles && !done; ++j) {
+            double *w = V + (long)(j + 1) * n;
+            if ((rc = kprecond(c, V + (long)j * n, n))) return rc;
+            ++k;
+            HIPCHK(c, launch_apply(c->dim, L0.G, (const double *)L0.A, (const double *)L0.x, w,
+                                   c->stream));
+            if ((rc = kdots(c, n, V, j + 1, w, h.data()))) return rc;
+            if ((rc = kaxpy(c, n, V, j + 1, h.data(), 1.0, w))) return rc;
+            if ((rc = kdots(c, n, V, j + 1, w, h2.data()))) return rc;
+            if ((rc = kaxpy(c, n, V, j + 1, h2.data(), 1.0, w))) return rc;
+            for (int i = 0; i <= j; ++i) Hij(i, j) = h[i] + h2[i];
+            double nrm = 0.0;
+            if ((rc = kdots(c, n, w, 1, w, &nrm))) return rc;
+            nrm = std::sqrt(nrm);
+            Hij(j + 1, j) = nrm;
+            for (int i = 0; i < j; ++i) {
+                const double a = Hij(i, j), bb = Hij(i + 1, j);
+                Hij(i, j) = cs[i] * a + sn[i] * bb;
+                Hij(i + 1, j) = -sn[i] * a + cs[i] * bb;
+            }
+            const double a = Hij(j, j), bb = Hij(j + 1, j);
+            const double d = std::hypot(a, bb);
+            cs[j] = d > 0.0 ? a / d : 1.0;
+            sn[j] = d > 0.0 ? bb / d : 0.0;
+            Hij(j, j) = d;
+            Hij(j + 1, j) = 0.0;
+            sv[j + 1] = -sn[j] * sv[j];
+            sv[j] = cs[j] * sv[j];
+            if (nrm == 0.0 || std::fabs(sv[j + 1]) <= tol * beta0) done = true;
+            else if ((rc = kaxpy(c, n, V, 0, nullptr, 1.0 / nrm, w))) return rc;
+        }
+        // y = H^-1 s on the j columns built, u = V y, x += M^-1 u
+        for (int i = j - 1; i >= 0; --i) {
+            double v = sv[i];
+            for (int q = i + 1; q < j; ++q) v -= Hij(i, q) * y[q];
+            y[i] = Hij(i, i) != 0.0 ? v / Hij(i, i) : 0.0;
+        }
+        for (int i = 0; i < j; ++i) y[i] = -y[i];
+        HIPCHK(c, hipMemsetAsync(c->kw, 0, vb, c->stream));
+        if ((rc = kaxpy(c, n, V, j, y.data(), 1.0, c->kw))) return rc;
+        if ((rc = kprecond(c, c->kw, n))) return rc;
+        ++k;
+        const double minus_one = -1.0;
+        if ((rc = kaxpy(c, n, (const double *)L0.x, 1, &minus_one, 1.0, c->kx))) return rc;
+    }
+    HIPCHK(c, hipMemcpyAsync(L0.x, c->kx, vb, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(L0.b, c->kg, vb, hipMemcpyDeviceToDevice, c->stream));
+    L0.st[0] = L0.st[1] = ST_VALID;
+    L0.last = -1;
+    *cycles = k;
+    return NMG_OK;
+}
+
 int count_pinned(nmg_ctx *c, const double *z, const double *U, int *n)
 {
     long N = cells(c->L[0].G);
@@ -620,6 +770,9 @@ void nmg_destroy(nmg_ctx *c)
     }
     if (c->pool) (void)hipFree(c->pool);
     if (c->At_alloc) (void)hipFree(c->At_alloc);
+    for (double *q : {c->kV, c->kg, c->kx, c->kw, c->kpart, c->kdots, c->kcoef})
+        if (q) (void)hipFree(q);
+    if (c->h_k) (void)hipHostFree(c->h_k);
     if (c->iso) (void)hipFree(c->iso);
     if (c->partial) (void)hipFree(c->partial);
     if (c->scal) (void)hipFree(c->scal);
@@ -759,12 +912,14 @@ int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_
 }
 
 int nmg_adjoint_solve(nmg_ctx *c, const double *z, const double *U, const double *g,
-                      double *lambda, double tol, int max_cycles, int *cycles_host,
+                      double *lambda, double tol, int max_cycles, int krylov, int *cycles_host,
                       double *rel_res_host)
 {
     if (!c) return NMG_EINVAL;
     if (!z || !U || !g || !lambda) return fail(c, NMG_EINVAL, "null z, U, g or lambda");
     if (max_cycles < 0 || !(tol >= 0)) return fail(c, NMG_EINVAL, "bad tol or max_cycles");
+    if (krylov < 0 || krylov > 200) return fail(c, NMG_EINVAL, "krylov restart out of range");
+    if (krylov > 0 && c->f32) return fail(c, NMG_EINVAL, "Krylov acceleration needs the FP64 hierarchy");
     Level &L0 = c->L[0];
     const size_t mbytes = (size_t)2 * c->ne * L0.G.planeP * (c->f32 ? sizeof(float) : sizeof(double));
     if (!c->At_alloc) {
@@ -786,10 +941,16 @@ int nmg_adjoint_solve(nmg_ctx *c, const double *z, const double *U, const double
     if ((rc = level0_residual_norm(c, &r0))) return rc;
     r = r0;
     int k = 0;
-    while (k < max_cycles && r > tol * r0) {
-        if ((rc = cycle(c, 0))) return rc;
-        if ((rc = materialize(c, 0))) return rc;
-        ++k;
+    if (krylov == 0) {
+        // stationary iteration: multigrid cycles on A^T lambda = g
+        while (k < max_cycles && r > tol * r0) {
+            if ((rc = cycle(c, 0))) return rc;
+            if ((rc = materialize(c, 0))) return rc;
+            ++k;
+            if ((rc = level0_residual_norm(c, &r))) return rc;
+        }
+    } else if (r0 > 0.0) {
+        if ((rc = adjoint_gmres(c, krylov, tol, max_cycles, &k))) return rc;
         if ((rc = level0_residual_norm(c, &r))) return rc;
     }
     HIPCHK(c, launch_vec_from_split(c->nc, c->f32, L0.G, L0.x, lambda, c->stream));

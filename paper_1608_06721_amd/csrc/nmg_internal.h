@@ -141,6 +141,18 @@ hipError_t launch_bed_vjp(const Phys &P, const double *z, const double *U,
 hipError_t launch_lin_res_norm(int dim, bool f32, const LevelGeom &G, const void *A,
                                const void *b, const void *x, double *partial, hipStream_t s);
 
+// Level-0 vector operations of the Krylov-accelerated adjoint solve (FP64):
+// y = A x; r = b - A x; out[k] = <V_k, w> for k < nv (V_k = V + k * ld,
+// partial holds nv * nblocks(n) doubles); w = a w - sum_k c[k] V_k.
+hipError_t launch_apply(int dim, const LevelGeom &G, const double *A, const double *x, double *y,
+                        hipStream_t s);
+hipError_t launch_lin_res_vec(int dim, const LevelGeom &G, const double *A, const double *b,
+                              const double *x, double *r, hipStream_t s);
+hipError_t launch_multidot(long n, const double *V, long ld, int nv, const double *w,
+                           double *partial, double *out, hipStream_t s);
+hipError_t launch_multi_axpy(long n, const double *V, long ld, int nv, const double *c, double a,
+                             double *w, hipStream_t s);
+
 // ---- batches of independent problems -------------------------------------
 // One instance of a batch at the Newton level.
 struct BatchInst {

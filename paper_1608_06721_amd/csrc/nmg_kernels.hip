@@ -1267,6 +1267,115 @@ __global__ void __launch_bounds__(kBlock) k_lin_res_norm(LevelGeom G, const T *_
     if (threadIdx.x == 0) partial[xb] = s;
 }
 
+// Level-0 vector kernels of the Krylov acceleration (FP64 hierarchy,
+// colour-split vectors of n = 2 * NC * plane entries).
+
+// y = A x on a level (the linear residual's product: D x_i, then the
+// neighbours in W, E, S, N order).
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_apply(LevelGeom G, const double *__restrict__ A,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ y)
+{
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    const long idx = (long)xb * kBlock + threadIdx.x;
+    if (idx >= (long)G.nx * G.ny) return;
+    const int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
+    double r[NC];
+    constexpr int NF = (NC == 2) ? 2 : 4;
+    constexpr int NE = (NF + 1) * NC * NC;
+    const int color = (i + j) & 1;
+    const long slot = (long)j * G.W + (i >> 1);
+    const double *Am = A + mat_off(G, NE, color, slot);
+    const double *xm = x + (long)color * NC * G.plane + slot;
+    const double *xo = x + (long)(color ^ 1) * NC * G.plane;
+    double xi[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xi[c] = xm[c * G.plane];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        r[q] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) r[q] = r[q] + Am[(q * NC + c) * kTile] * xi[c];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        int ni = i, nj = j;
+        bool ok;
+        if (f == FW) { ni = i - 1; ok = i > 0; }
+        else if (f == FE) { ni = i + 1; ok = i + 1 < G.nx; }
+        else if (f == FS) { nj = j - 1; ok = j > 0; }
+        else { nj = j + 1; ok = j + 1 < G.ny; }
+        if (!ok) continue;
+        const double *pp = xo + (long)nj * G.W + (ni >> 1);
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                r[q] = r[q] + Am[(((f + 1) * NC + q) * NC + c) * kTile] * pp[c * G.plane];
+    }
+    double *ym = y + (long)color * NC * G.plane + slot;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) ym[q * G.plane] = r[q];
+}
+
+// r = b - A x as a vector (lin_residual_cell per cell).
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_lin_res_vec(LevelGeom G, const double *__restrict__ A,
+                                                        const double *__restrict__ b,
+                                                        const double *__restrict__ x,
+                                                        double *__restrict__ r)
+{
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    const long idx = (long)xb * kBlock + threadIdx.x;
+    if (idx >= (long)G.nx * G.ny) return;
+    const int i = (int)(idx % G.nx), j = (int)(idx / G.nx);
+    double v[NC];
+    lin_residual_cell<double, NC>(G, A, b, x, i, j, v);
+    const int color = (i + j) & 1;
+    double *rm = r + (long)color * NC * G.plane + (long)j * G.W + (i >> 1);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) rm[q * G.plane] = v[q];
+}
+
+// partial[k * gridDim.x + block] = sum over the block's entries of
+// V_k[e] * w[e], k < nv (vectors V_k = V + k * ld).
+__global__ void __launch_bounds__(kBlock) k_multidot(long n, const double *__restrict__ V, long ld,
+                                                     int nv, const double *__restrict__ w,
+                                                     double *__restrict__ partial)
+{
+    const long e = (long)blockIdx.x * kBlock + threadIdx.x;
+    const double we = e < n ? w[e] : 0.0;
+    for (int k = 0; k < nv; ++k) {
+        const double v = e < n ? V[k * ld + e] * we : 0.0;
+        const double s = block_sum(v);
+        if (threadIdx.x == 0) partial[(long)k * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// out[k] = sum of partial[k * nparts .. (k + 1) * nparts), one block per k.
+__global__ void __launch_bounds__(kBlock) k_multi_reduce(const double *__restrict__ partial,
+                                                         int nparts, double *__restrict__ out)
+{
+    const double *p = partial + (long)blockIdx.x * nparts;
+    double v = 0.0;
+    for (int q = threadIdx.x; q < nparts; q += kBlock) v = v + p[q];
+    const double s = block_sum(v);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// w[e] = a * w[e] - sum over k < nv of c[k] V_k[e] (k in order).
+__global__ void __launch_bounds__(kBlock) k_multi_axpy(long n, const double *__restrict__ V, long ld,
+                                                       int nv, const double *__restrict__ c,
+                                                       double a, double *__restrict__ w)
+{
+    const long e = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n) return;
+    double v = a * w[e];
+    for (int k = 0; k < nv; ++k) v = v - c[k] * V[k * ld + e];
+    w[e] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Batched kernels: one block per work item (instance, tile), in XCD-aware
 // order; the per-cell work is the same function as in the single-problem
@@ -1667,6 +1776,40 @@ hipError_t launch_lin_res_norm(int dim, bool f32, const LevelGeom &G, const void
     }
     if (dim == 1) NMG_LAUNCH((k_lin_res_norm<double, 2>), g, G, (const double *)A, (const double *)b, (const double *)x, partial);
     NMG_LAUNCH((k_lin_res_norm<double, 3>), g, G, (const double *)A, (const double *)b, (const double *)x, partial);
+}
+
+hipError_t launch_apply(int dim, const LevelGeom &G, const double *A, const double *x, double *y,
+                        hipStream_t s)
+{
+    int g = nblocks((long)G.nx * G.ny);
+    if (dim == 1) NMG_LAUNCH(k_apply<2>, g, G, A, x, y);
+    NMG_LAUNCH(k_apply<3>, g, G, A, x, y);
+}
+
+hipError_t launch_lin_res_vec(int dim, const LevelGeom &G, const double *A, const double *b,
+                              const double *x, double *r, hipStream_t s)
+{
+    int g = nblocks((long)G.nx * G.ny);
+    if (dim == 1) NMG_LAUNCH(k_lin_res_vec<2>, g, G, A, b, x, r);
+    NMG_LAUNCH(k_lin_res_vec<3>, g, G, A, b, x, r);
+}
+
+hipError_t launch_multidot(long n, const double *V, long ld, int nv, const double *w,
+                           double *partial, double *out, hipStream_t s)
+{
+    if (nv <= 0) return hipSuccess;
+    const int g = nblocks(n);
+    hipLaunchKernelGGL(k_multidot, dim3(g), dim3(kBlock), 0, s, n, V, ld, nv, w, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_multi_reduce, dim3(nv), dim3(kBlock), 0, s, partial, g, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_axpy(long n, const double *V, long ld, int nv, const double *c, double a,
+                             double *w, hipStream_t s)
+{
+    NMG_LAUNCH(k_multi_axpy, nblocks(n), n, V, ld, nv, c, a, w);
 }
 
 // ---- batched launchers ----

@@ -87,7 +87,7 @@ def lib():
         L.nmg_timing_enable.argtypes = [vp, C.c_int, C.c_int]
         L.nmg_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                       C.POINTER(C.c_longlong)]
-        L.nmg_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int,
+        L.nmg_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int, C.c_int,
                                         C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.nmg_bed_vjp.argtypes = [vp, vp, vp, vp, vp]
         L.nmg_batch_create.argtypes = [C.c_int, C.POINTER(nmg_grid), C.POINTER(nmg_bc),
@@ -235,15 +235,16 @@ class Context:
         self._check(lib().nmg_get_system(self._h, int(level), _ptr(A, "A"), _ptr(b, "b")))
         return A, b
 
-    def adjoint_solve(self, z, U, g, lam=None, tol=1e-12, max_cycles=200):
-        """Solve (dR/dU)^T lam = g at (z, U) by multigrid (nmg_adjoint_solve);
-        returns (lam, cycles, relative residual)."""
+    def adjoint_solve(self, z, U, g, lam=None, tol=1e-12, max_cycles=200, krylov=0):
+        """Solve (dR/dU)^T lam = g at (z, U) by multigrid cycles, GMRES(krylov)
+        accelerated if krylov > 0 (nmg_adjoint_solve); returns (lam, cycles,
+        relative l1 residual)."""
         if lam is None:
             lam = torch.zeros_like(g)
         cyc, rel = C.c_int(0), C.c_double(0.0)
         self._check(lib().nmg_adjoint_solve(self._h, _ptr(z, "z"), _ptr(U, "U"), _ptr(g, "g"),
                                             _ptr(lam, "lambda"), float(tol), int(max_cycles),
-                                            C.byref(cyc), C.byref(rel)))
+                                            int(krylov), C.byref(cyc), C.byref(rel)))
         return lam, cyc.value, rel.value
 
     def bed_vjp(self, z, U, lam, out=None):

@@ -229,6 +229,39 @@ def batch_channels(n: int = 64, sizes=(128, 256, 384, 512), q_range=(0.5, 2.0),
     return probs
 
 
+ADJOINT_SEED = 160806821
+
+
+@dataclasses.dataclass
+class GaugeCase:
+    """One topography of the gauge-misfit gradient workload: the problem,
+    its gauge cells (flat indices) and the bed whose steady state defines the
+    gauge targets."""
+    prob: Problem
+    gauges: np.ndarray
+    z_true: np.ndarray
+
+
+def gauge_cases(n: int = 16, size: int = 512, n_gauges: int = 64, seed: int = ADJOINT_SEED,
+                bump_width=(0.2, 0.8), mound_amp: float = 0.8, **kw) -> list:
+    """Topography b < n: the steady channel of channel() at size x size with
+    bed seed `seed + b`; n_gauges gauge cells drawn without replacement among
+    the cells wet (h > 0.05) in the initial lake at rest; the target bed adds
+    0.02 exp(-r^2 / 0.3^2) around a seeded centre in [3, 7] x [0.5, 1.5]."""
+    out = []
+    for b in range(n):
+        p = channel(size, size, seed=seed + b, bump_width=bump_width, mound_amp=mound_amp, **kw)
+        rng = np.random.Generator(np.random.PCG64(seed + 1000 + b))
+        wet = np.flatnonzero(p.U0[0].ravel() > 0.05)
+        gauges = np.sort(rng.choice(wet, n_gauges, replace=False))
+        cx, cy = rng.uniform(3.0, 7.0), rng.uniform(0.5, 1.5)
+        X, Y = np.meshgrid(cell_centres(p.x0, p.x1, p.nx), cell_centres(p.y0, p.y1, p.ny))
+        z_true = p.z + 0.02 * np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / 0.3 ** 2)
+        p.name = "gauges%d_%dx%d" % (b, size, size)
+        out.append(GaugeCase(p, gauges, z_true))
+    return out
+
+
 def random_state(dim: int, nx: int, ny: int, seed: int, hmin=0.5, hmax=2.0, umax=0.5):
     """Smooth-ish random wet state (h in [hmin, hmax], |u|, |v| < umax) and
     bed in [0, 0.2], for unit tests of the discretization."""

@@ -114,12 +114,14 @@ def test_bed_vjp_bitwise(nmg, case):
     same(host(got), oracle.bed_vjp(prob, U, lam), "(dR/dz)^T lambda")
 
 
-def test_adjoint_solve_converges_to_the_dense_solution(nmg):
+@pytest.mark.parametrize("krylov", [0, 30])
+def test_adjoint_solve_converges_to_the_dense_solution(nmg, krylov):
     prob, U = wet(32, 16, 5, 2)
     ctx = nmg.Context.from_problem(prob, gamma=2)
     g = rng(5).uniform(-1, 1, U.shape)
-    lam, cyc, rel = ctx.adjoint_solve(dev(prob.z), dev(U), dev(g), tol=1e-13, max_cycles=200)
-    say("adjoint converged in", cyc, "cycles, rel", rel)
+    lam, cyc, rel = ctx.adjoint_solve(dev(prob.z), dev(U), dev(g), tol=1e-13, max_cycles=200,
+                                      krylov=krylov)
+    say("adjoint (krylov %d) converged in" % krylov, cyc, "cycles, rel", rel)
     assert rel <= 1e-13
     A, _, _ = oracle.assemble(prob, U)
     ref = unvec(np.linalg.solve(dense(oracle.transpose_blocks(A)), vec(g)), 3, 16, 32)
@@ -183,3 +185,45 @@ def test_autograd_gradient_matches_oracle_and_central_differences(nmg):
         g = grad.ravel()[k]
         say("  cell", k, "fd", fd, "adjoint", g)
         assert abs(fd - g) <= 1e-5 * max(abs(fd), 1e-2 * scale), (k, fd, g)
+
+
+def test_full_size_gradient_spot_check(nmg):
+    """One topography of the benchmark's gradient workload (512^2, 64 gauges,
+    FP64 W-cycle) in its launch configuration: the autograd gradient against
+    central differences (step 1e-6) through GPU Newton solves at the three
+    largest-gradient cells whose bed is smooth at that step."""
+    from paper_1608_06721_amd import adjoint
+    case = W.gauge_cases(1, size=512, n_levels=5, gamma=2)[0]
+    prob = case.prob
+    ctx = nmg.Context.from_problem(prob)
+    Ut = dev(prob.U0)
+    assert ctx.newton_mg_solve(dev(case.z_true), Ut, 1e-10)["status"] == "OK"
+    g = torch.from_numpy(case.gauges).cuda()
+    target = (Ut[0] + dev(case.z_true)).reshape(-1)[g]
+    z = dev(prob.z).requires_grad_(True)
+    U = adjoint.steady_state(ctx, z, dev(prob.U0), tol=1e-11)
+    J = adjoint.gauge_misfit(U, z, g, target)
+    J.backward()
+    grad = host(z.grad)
+    Us = host(U.detach())
+    scale = np.abs(grad).max()
+    d = 1e-6
+    cells = smooth_cells(prob.z, 100 * d, list(np.argsort(-np.abs(grad).ravel())[:200]))[:3]
+    say("full size: |grad| max", scale, "cells", cells)
+    assert len(cells) == 3
+    tg = host(target)
+
+    def Jof(zz):
+        Uz = dev(Us)
+        st = ctx.newton_mg_solve(dev(zz), Uz, 1e-11)
+        assert st["status"] == "OK", st
+        e = (host(Uz)[0] + zz).ravel()[case.gauges]
+        return float(((e - tg) ** 2).sum())
+
+    for k in cells:
+        zp = prob.z.copy().ravel(); zp[k] += d
+        zm = prob.z.copy().ravel(); zm[k] -= d
+        fd = (Jof(zp.reshape(prob.z.shape)) - Jof(zm.reshape(prob.z.shape))) / (2 * d)
+        gk = grad.ravel()[k]
+        say("  cell", k, "fd", fd, "adjoint", gk)
+        assert abs(fd - gk) <= 1e-5 * max(abs(fd), 1e-2 * scale), (k, fd, gk)
