@@ -37,13 +37,13 @@ class Params(C.Structure):
                 ("nu2", C.c_int), ("nu_coarse", C.c_int), ("n_mg", C.c_int),
                 ("blu_sweeps", C.c_int), ("max_newton", C.c_int), ("order", C.c_int),
                 ("dry_pin", C.c_int), ("pos_theta", C.c_double), ("inner_fp32", C.c_int),
-                ("gamma", C.c_int)]
+                ("gamma", C.c_int), ("eps_p", C.c_double), ("init_max_sweeps", C.c_int)]
 
 
 class Stats(C.Structure):
     _fields_ = [("newton_steps", C.c_int), ("status", C.c_int), ("n_pinned", C.c_int),
                 ("res_l1", C.c_double), ("res_hist", C.POINTER(C.c_double)),
-                ("hist_cap", C.c_int)]
+                ("hist_cap", C.c_int), ("init_sweeps", C.c_int)]
 
 
 def lib():
@@ -78,7 +78,8 @@ def params_struct(p: dict) -> Params:
                   p["eps_r"], int(p["n_levels"]), int(p["nu1"]), int(p["nu2"]),
                   int(p["nu_coarse"]), int(p["n_mg"]), int(p["blu_sweeps"]),
                   int(p["max_newton"]), int(p["order"]), int(p["dry_pin"]),
-                  float(p["pos_theta"]), int(p.get("inner_fp32", 0)), int(p.get("gamma", 1)))
+                  float(p["pos_theta"]), int(p.get("inner_fp32", 0)), int(p.get("gamma", 1)),
+                  float(p.get("eps_p", 0.0)), int(p.get("init_max_sweeps", 1000)))
 
 
 def _f64(a):
@@ -251,13 +252,24 @@ def newton_solve(prob, U0=None, tol=1e-10, params=None, hist_cap=10000):
     p = params_struct(params or prob.params)
     U = _f64(prob.U0 if U0 is None else U0).copy()
     hist = np.zeros(hist_cap)
-    st = Stats(0, 0, 0, 0.0, _dp(hist), hist_cap)
+    st = Stats(0, 0, 0, 0.0, _dp(hist), hist_cap, 0)
     rc = lib().orc_newton_solve(C.byref(_grid(prob)), _bc(prob), C.byref(p), _dp(_f64(prob.z)),
                                 _dp(U), C.c_double(tol), C.byref(st))
     n = st.newton_steps
     nh = min(n + 1, hist_cap) if st.status in (0, -4, -5) else min(n, hist_cap)
     return U, dict(status=STATUS.get(rc, rc), newton_steps=n, n_pinned=st.n_pinned,
-                   res_l1=st.res_l1, res_hist=hist[:nh].copy())
+                   res_l1=st.res_l1, res_hist=hist[:nh].copy(), init_sweeps=st.init_sweeps)
+
+
+def nested_init(prob, U0=None, params=None):
+    """Algorithm 1, Step 1 from U0 (default prob.U0): returns (Newton's initial
+    guess, BLU-SGS sweeps per level)."""
+    p = params_struct(params or prob.params)
+    U = _f64(prob.U0 if U0 is None else U0).copy()
+    sw = (C.c_int * 16)()
+    _check(lib().orc_nested_init(C.byref(_grid(prob)), _bc(prob), C.byref(p), _dp(_f64(prob.z)),
+                                 _dp(U), sw), "nested_init")
+    return U, [sw[l] for l in range(int(p.n_levels) + 1)]
 
 
 # --- sensitivities ---------------------------------------------------------------

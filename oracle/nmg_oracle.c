@@ -615,6 +615,90 @@ static void relaxed_update(const prob *P, double *U, const double *x)
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1, Step 1: the initial data averaged onto the coarsest mesh, then
+ * on each level l = N_L, ..., 1 symmetric BLU-SGS iterations until
+ * sum_i ||R_{i,l}||_1 < eps_p 2^-l, and the result injected into the children
+ * on level l - 1.  Coarse meshes cover the same domain with (nx, ny) >> l;
+ * their bed and initial state are averages of the children, taken level by
+ * level in the child order SW, SE, NW, NE as (((SW + SE) + NW) + NE) / 4
+ * (1D: (left + right) / 2).  The residual is tested before each sweep; at
+ * most init_max_sweeps sweeps per level. */
+
+static void average_children(int dim, int nxf, int nyf, int ncomp, const double *f, double *c)
+{
+    int nxc = nxf / 2, nyc = dim == 1 ? 1 : nyf / 2;
+    int Nf = nxf * nyf, Nc = nxc * nyc;
+    for (int k = 0; k < ncomp; ++k)
+        for (int J = 0; J < nyc; ++J)
+            for (int I = 0; I < nxc; ++I) {
+                const double *q = f + (size_t)k * Nf;
+                double v;
+                if (dim == 1) {
+                    v = (q[2 * I] + q[2 * I + 1]) * 0.5;
+                } else {
+                    int r0 = 2 * J * nxf, r1 = (2 * J + 1) * nxf;
+                    v = (((q[r0 + 2 * I] + q[r0 + 2 * I + 1]) + q[r1 + 2 * I]) + q[r1 + 2 * I + 1]) * 0.25;
+                }
+                c[(size_t)k * Nc + J * nxc + I] = v;
+            }
+}
+
+static void inject_children(int dim, int nxf, int nyf, int ncomp, const double *c, double *f)
+{
+    int nxc = nxf / 2, nyc = dim == 1 ? 1 : nyf / 2;
+    int Nf = nxf * nyf, Nc = nxc * nyc;
+    for (int k = 0; k < ncomp; ++k)
+        for (int j = 0; j < nyf; ++j)
+            for (int i = 0; i < nxf; ++i)
+                f[(size_t)k * Nf + j * nxf + i] = c[(size_t)k * Nc + (dim == 1 ? 0 : j / 2) * nxc + i / 2];
+}
+
+int orc_nested_init(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
+                    const double *z, double *U, int *sweeps)
+{
+    const int NL = p->n_levels, nc = gr->dim == 1 ? 2 : 3;
+    if (sweeps)
+        for (int l = 0; l <= NL; ++l) sweeps[l] = 0;
+    if (!(p->eps_p > 0.0) || NL < 1) return ORC_OK;
+    orc_grid G[16];
+    double *zl[16], *Ul[16];
+    G[0] = *gr;
+    zl[0] = (double *)z;
+    Ul[0] = U;
+    int rc = ORC_OK;
+    for (int l = 1; l <= NL; ++l) {
+        G[l] = G[l - 1];
+        G[l].nx = G[l - 1].nx / 2;
+        G[l].ny = gr->dim == 1 ? 1 : G[l - 1].ny / 2;
+        size_t N = (size_t)G[l].nx * G[l].ny;
+        zl[l] = (double *)malloc(sizeof(double) * N);
+        Ul[l] = (double *)malloc(sizeof(double) * N * nc);
+        if (!zl[l] || !Ul[l]) {
+            for (int q = 1; q <= l; ++q) { free(zl[q]); free(Ul[q]); }
+            return ORC_EINVAL;
+        }
+        average_children(gr->dim, G[l - 1].nx, G[l - 1].ny, 1, zl[l - 1], zl[l]);
+        average_children(gr->dim, G[l - 1].nx, G[l - 1].ny, nc, Ul[l - 1], Ul[l]);
+    }
+    for (int l = NL; l >= 1 && rc == ORC_OK; --l) {
+        const double thr = ldexp(p->eps_p, -l);
+        int cnt = 0;
+        for (;;) {
+            double res = 0.0;
+            rc = orc_residual(&G[l], bc, p, zl[l], Ul[l], NULL, &res);
+            if (rc || !(res >= thr) || cnt >= p->init_max_sweeps) break;
+            rc = orc_blu_sweep(&G[l], bc, p, zl[l], Ul[l]);
+            if (rc) break;
+            ++cnt;
+        }
+        if (sweeps) sweeps[l] = cnt;
+        inject_children(gr->dim, G[l - 1].nx, G[l - 1].ny, nc, Ul[l], Ul[l - 1]);
+    }
+    for (int l = 1; l <= NL; ++l) { free(zl[l]); free(Ul[l]); }
+    return rc;
+}
+
 /* Algorithm 1, Steps 2-3, started from the given U (Step 1 is not part of
  * this routine).  Each Newton step: optional BLU-SGS pre-smoothing, assembly
  * of R and A at the current U, stop test on sum_i ||R_i||_1, N_mg V-cycles
@@ -632,8 +716,14 @@ int orc_newton_solve(const orc_grid *gr, const orc_side bc[4], const orc_params 
     unsigned char *iso = (unsigned char *)malloc((size_t)P.N);
     int status = ORC_NOT_CONVERGED, n = 0;
     double res = 0.0, res0 = 0.0;
-    if (st) { st->newton_steps = 0; st->n_pinned = 0; st->res_l1 = 0.0; }
+    if (st) { st->newton_steps = 0; st->n_pinned = 0; st->res_l1 = 0.0; st->init_sweeps = 0; }
     orc_threshold(gr, p, U);
+    if (p->eps_p > 0.0 && p->n_levels >= 1) {      /* Step 1 */
+        int sw[16];
+        if (orc_nested_init(gr, bc, p, z, U, sw)) { free(A); free(b); free(Ulast); free(iso); return ORC_EINVAL; }
+        if (st)
+            for (int l = 1; l <= p->n_levels; ++l) st->init_sweeps += sw[l];
+    }
     for (n = 0; n < p->max_newton; ++n) {
         memcpy(Ulast, U, sizeof(double) * nv);
         for (int s = 0; s < p->blu_sweeps; ++s) orc_blu_sweep(gr, bc, p, z, U);

@@ -51,6 +51,8 @@ typedef struct {
     double pos_theta;               /* positivity limit of the per-cell relaxation (0 = off) */
     int inner_fp32;                 /* V-cycles in FP32 (Newton residual and update in FP64) */
     int gamma;                      /* cycle index: 1 = V-cycle, 2 = W-cycle */
+    double eps_p;                   /* Step 1 tolerance; <= 0: start Newton from U0 directly */
+    int init_max_sweeps;            /* Step 1: at most this many BLU-SGS sweeps per level */
 } orc_params;
 
 typedef struct {
@@ -58,6 +60,7 @@ typedef struct {
     double res_l1;
     double *res_hist;
     int hist_cap;
+    int init_sweeps;                /* Step 1 BLU-SGS sweeps over all levels */
 } orc_stats;
 
 /* --- pieces exposed for unit tests ------------------------------------ */
@@ -102,6 +105,12 @@ int orc_blu_sweep(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
 void orc_threshold(const orc_grid *gr, const orc_params *p, double *U);
 int orc_newton_solve(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
                      const double *z, double *U, double tol, orc_stats *st);
+
+/* Algorithm 1, Step 1: nested initial guess of U (in: the initial data on
+ * level 0, out: Newton's initial guess); sweeps[l] (nullable, n_levels + 1
+ * entries) receives the BLU-SGS sweeps done on level l. */
+int orc_nested_init(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
+                    const double *z, double *U, int *sweeps);
 
 /* --- sensitivities (adjoint of the steady state) ------------------------- */
 /* Exact block transpose: At's block at cell i towards neighbour j is A's

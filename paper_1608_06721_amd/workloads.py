@@ -32,11 +32,13 @@ def default_params(dim: int, **kw) -> dict:
     N_L=3; HLL in 1D, LLF in 2D.  dry_pin and pos_theta are the two
     wet/dry safeguards of this implementation (dry-cell momentum pin and the
     positivity-limited per-cell relaxation); dry_pin=0, pos_theta=0 gives
-    the method exactly as printed."""
+    the method exactly as printed.  eps_p > 0 turns on Step 1 of Algorithm 1
+    (nested BLU-SGS initial guess) with that tolerance."""
     p = dict(flux=HLL if dim == 1 else LLF, g=9.81, alpha=3.0, fd_eps=1e-8, tau=1.0,
              h_eps=1e-6, eps_r=0.03, n_levels=3, nu1=2, nu2=2, nu_coarse=10,
              n_mg=2 if dim == 1 else 3, blu_sweeps=1, max_newton=500, order=REDBLACK,
-             dry_pin=1, pos_theta=0.9 if dim == 2 else 0.0, inner_fp32=0, gamma=1)
+             dry_pin=1, pos_theta=0.9 if dim == 2 else 0.0, inner_fp32=0, gamma=1,
+             eps_p=0.0, init_max_sweeps=1000)
     for k, v in kw.items():
         if k not in p:
             raise KeyError(k)
