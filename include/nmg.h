@@ -95,7 +95,13 @@ typedef struct {
  * assembly arithmetic, the update, the threshold and the stop test stay FP64
  * (Newton then acts as iterative refinement).  gamma is the cycle index of
  * Algorithm 0 (1 = V-cycle, 2 = W-cycle); the finest level always makes a
- * single coarse-grid call. */
+ * single coarse-grid call.  eps_p > 0 turns on Step 1 of Algorithm 1 in
+ * nmg_newton_mg_solve: the initial data averaged onto the coarsest mesh
+ * (children averaged level by level in the order SW, SE, NW, NE), then on
+ * each level l = N_L..1 symmetric BLU-SGS sweeps while sum ||R_{i,l}||_1 >=
+ * eps_p 2^-l (at most init_max_sweeps sweeps), then injection into the
+ * children; eps_p = 0 starts Newton from U0 (the paper suggests about 1 %
+ * of the initial residual).  Batches require eps_p = 0. */
 typedef struct {
     int flux;
     double g, alpha, fd_eps, tau, h_eps, eps_r;
@@ -105,6 +111,8 @@ typedef struct {
     double pos_theta;
     int inner_fp32;
     int gamma;
+    double eps_p;
+    int init_max_sweeps;
 } nmg_params;
 
 /* Solve statistics (host memory).  res_hist (optional, host) receives the
@@ -116,6 +124,7 @@ typedef struct {
     double res_l1;           /* sum_i ||R_i||_1 of the returned state */
     double *res_hist;
     int hist_cap;
+    int init_sweeps;         /* Step 1 BLU-SGS sweeps over all coarse levels */
 } nmg_stats;
 
 /* Create a context for one grid / BC / parameter set on HIP stream `stream`

@@ -51,6 +51,9 @@ struct nmg_ctx {
     void *pool = nullptr;             // the hierarchy's allocation
     void *At_alloc = nullptr;         // second level-0 matrix (adjoint transpose), owned
     void *At_spare = nullptr;         // whichever of the two level-0 matrices is not L[0].A
+    // Algorithm 1, Step 1 (allocated on first use): coarse beds and states
+    double *init_pool = nullptr;
+    double *zl[kMaxLevels] = {}, *Ul[kMaxLevels] = {};
     // Krylov acceleration of the adjoint solve (allocated on first use)
     int km = 0;                       // restart length the buffers were sized for
     double *kV = nullptr, *kg = nullptr, *kx = nullptr, *kw = nullptr;
@@ -145,6 +148,7 @@ int check_params(const nmg_grid *g, const nmg_bc *bc, const nmg_params *p, std::
     }
     if (p->inner_fp32 != 0 && p->inner_fp32 != 1) { msg = "inner_fp32 must be 0 or 1"; return NMG_EINVAL; }
     if (p->gamma < 1 || p->gamma > 3) { msg = "gamma must be 1, 2 or 3"; return NMG_EINVAL; }
+    if (!(p->eps_p >= 0) || p->init_max_sweeps < 0) { msg = "bad eps_p or init_max_sweeps"; return NMG_EINVAL; }
     if (p->flux == NMG_FLUX_HLLC && g->dim != 2) { msg = "HLLC is a 2D flux"; return NMG_EINVAL; }
     if (p->nu1 < 0 || p->nu2 < 0 || p->nu_coarse < 0 || p->n_mg < 0 || p->blu_sweeps < 0 ||
         p->max_newton < 0) {
@@ -634,6 +638,70 @@ int adjoint_gmres(nmg_ctx *c, int m, double tol, int max_cycles, int *cycles)
     return NMG_OK;
 }
 
+// Physics of the coarse mesh of level l (same domain, (nx, ny) >> l).
+Phys level_phys(const nmg_ctx *c, int l)
+{
+    Phys P = c->P;
+    P.nx = c->grid.nx >> l;
+    P.ny = c->dim == 1 ? 1 : c->grid.ny >> l;
+    if (c->dim == 2) {
+        double dx = (c->grid.x1 - c->grid.x0) / P.nx, dy = (c->grid.y1 - c->grid.y0) / P.ny;
+        P.elen[0] = P.elen[1] = dy;
+        P.elen[2] = P.elen[3] = dx;
+    }
+    return P;
+}
+
+// Algorithm 1, Step 1 on U in place (see nmg_params); *sweeps = the BLU-SGS
+// sweeps done over all levels.
+int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps)
+{
+    const int NL = c->NL, nc = c->nc;
+    *sweeps = 0;
+    if (!(c->prm.eps_p > 0.0) || NL < 1) return NMG_OK;
+    if (!c->init_pool) {
+        size_t tot = 0;
+        for (int l = 1; l <= NL; ++l) tot += (size_t)(1 + nc) * cells(c->L[l].G);
+        if (hipMalloc(&c->init_pool, sizeof(double) * tot) != hipSuccess)
+            return fail(c, NMG_ENOMEM, "Step 1 levels");
+        size_t off = 0;
+        for (int l = 1; l <= NL; ++l) {
+            c->zl[l] = c->init_pool + off; off += cells(c->L[l].G);
+            c->Ul[l] = c->init_pool + off; off += (size_t)nc * cells(c->L[l].G);
+        }
+    }
+    const double *zp = z;
+    const double *Up = U;
+    for (int l = 1; l <= NL; ++l) {
+        const LevelGeom &Gf = c->L[l - 1].G;
+        HIPCHK(c, launch_average(c->dim, Gf.nx, Gf.ny, 1, zp, c->zl[l], c->stream));
+        HIPCHK(c, launch_average(c->dim, Gf.nx, Gf.ny, nc, Up, c->Ul[l], c->stream));
+        zp = c->zl[l];
+        Up = c->Ul[l];
+    }
+    const int order[4] = {0, 1, 1, 0};
+    for (int l = NL; l >= 1; --l) {
+        const Phys P = level_phys(c, l);
+        const double thr = std::ldexp(c->prm.eps_p, -l);
+        int cnt = 0;
+        for (;;) {
+            double res = 0.0;
+            HIPCHK(c, launch_residual(P, c->zl[l], c->Ul[l], nullptr, c->partial, c->stream));
+            int rc = reduce_to_host(c, nblocks(cells(c->L[l].G)), &res);
+            if (rc) return rc;
+            if (!(res >= thr) || cnt >= c->prm.init_max_sweeps) break;
+            for (int q = 0; q < 4; ++q)
+                HIPCHK(c, launch_blu_half(P, c->zl[l], c->Ul[l], order[q], c->stream));
+            ++cnt;
+        }
+        *sweeps += cnt;
+        const LevelGeom &Gf = c->L[l - 1].G;
+        HIPCHK(c, launch_inject(c->dim, Gf.nx, Gf.ny, nc, c->Ul[l], l == 1 ? U : c->Ul[l - 1],
+                                c->stream));
+    }
+    return NMG_OK;
+}
+
 int count_pinned(nmg_ctx *c, const double *z, const double *U, int *n)
 {
     long N = cells(c->L[0].G);
@@ -773,6 +841,7 @@ void nmg_destroy(nmg_ctx *c)
     for (double *q : {c->kV, c->kg, c->kx, c->kw, c->kpart, c->kdots, c->kcoef})
         if (q) (void)hipFree(q);
     if (c->h_k) (void)hipHostFree(c->h_k);
+    if (c->init_pool) (void)hipFree(c->init_pool);
     if (c->iso) (void)hipFree(c->iso);
     if (c->partial) (void)hipFree(c->partial);
     if (c->scal) (void)hipFree(c->scal);
@@ -875,6 +944,8 @@ int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_
     int status = NMG_NOT_CONVERGED, n = 0, rc;
     double res = 0.0, res0 = 0.0;
     HIPCHK(c, launch_threshold(c->P, U, c->stream));
+    int init_sweeps = 0;
+    if ((rc = nested_init(c, z, U, &init_sweeps))) return rc;     // Step 1 (eps_p > 0)
     for (n = 0; n < p.max_newton; ++n) {
         HIPCHK(c, hipMemcpyAsync(c->Ulast, U, vbytes, hipMemcpyDeviceToDevice, c->stream));
         for (int s = 0; s < p.blu_sweeps; ++s)
@@ -906,6 +977,7 @@ int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_
         st->newton_steps = n;
         st->status = status;
         st->res_l1 = res;
+        st->init_sweeps = init_sweeps;
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return status;
@@ -1085,6 +1157,7 @@ int nmg_batch_create(int n, const nmg_grid *grids, const nmg_bc *bcs, const nmg_
     if (!out) return NMG_EINVAL;
     *out = nullptr;
     if (n < 1 || n > 65536 || !grids || !bcs || !params) return NMG_EINVAL;
+    if (params->eps_p != 0.0) return NMG_EINVAL;        // Step 1 is not batched
     for (int k = 1; k < n; ++k)
         if (grids[k].dim != grids[0].dim) return NMG_EINVAL;
     nmg_batch *b = new (std::nothrow) nmg_batch();
@@ -1396,6 +1469,7 @@ int nmg_batch_newton_mg_solve(nmg_batch *b, const double *const *z, double *cons
             stats[k].newton_steps = steps[k];
             stats[k].status = status[k];
             stats[k].res_l1 = res[k];
+            stats[k].init_sweeps = 0;
         }
     }
     BHIPCHK(b, hipStreamSynchronize(b->stream));

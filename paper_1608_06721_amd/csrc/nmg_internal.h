@@ -153,6 +153,13 @@ hipError_t launch_multidot(long n, const double *V, long ld, int nv, const doubl
 hipError_t launch_multi_axpy(long n, const double *V, long ld, int nv, const double *c, double a,
                              double *w, hipStream_t s);
 
+// Algorithm 1, Step 1: child averages of ncomp planes of nxf x nyf fine cells
+// onto the coarser mesh, and injection of a coarse state into the children.
+hipError_t launch_average(int dim, int nxf, int nyf, int ncomp, const double *f, double *c,
+                          hipStream_t s);
+hipError_t launch_inject(int dim, int nxf, int nyf, int ncomp, const double *c, double *f,
+                         hipStream_t s);
+
 // ---- batches of independent problems -------------------------------------
 // One instance of a batch at the Newton level.
 struct BatchInst {

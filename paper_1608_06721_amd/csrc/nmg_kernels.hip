@@ -1377,6 +1377,47 @@ __global__ void __launch_bounds__(kBlock) k_multi_axpy(long n, const double *__r
 }
 
 // ---------------------------------------------------------------------------
+// Algorithm 1, Step 1 on the natural layout: child averages onto the next
+// coarser mesh, in the child order SW, SE, NW, NE as (((SW + SE) + NW) + NE)
+// / 4 (1D: (left + right) / 2), and injection of a coarse state into the
+// children.  ncomp component planes of nxf x nyf fine cells.
+
+__global__ void __launch_bounds__(kBlock) k_average(int dim, int nxf, int nyf, int ncomp,
+                                                    const double *__restrict__ f,
+                                                    double *__restrict__ c)
+{
+    const int nxc = nxf / 2, nyc = dim == 1 ? 1 : nyf / 2;
+    const long Nc = (long)nxc * nyc, Nf = (long)nxf * nyf;
+    const long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= Nc) return;
+    const int I = (int)(idx % nxc), J = (int)(idx / nxc);
+    for (int k = 0; k < ncomp; ++k) {
+        const double *q = f + k * Nf;
+        double v;
+        if (dim == 1) {
+            v = (q[2 * I] + q[2 * I + 1]) * 0.5;
+        } else {
+            const long r0 = (long)2 * J * nxf, r1 = (long)(2 * J + 1) * nxf;
+            v = (((q[r0 + 2 * I] + q[r0 + 2 * I + 1]) + q[r1 + 2 * I]) + q[r1 + 2 * I + 1]) * 0.25;
+        }
+        c[k * Nc + idx] = v;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_inject(int dim, int nxf, int nyf, int ncomp,
+                                                   const double *__restrict__ c,
+                                                   double *__restrict__ f)
+{
+    const int nxc = nxf / 2, nyc = dim == 1 ? 1 : nyf / 2;
+    const long Nc = (long)nxc * nyc, Nf = (long)nxf * nyf;
+    const long idx = (long)blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= Nf) return;
+    const int i = (int)(idx % nxf), j = (int)(idx / nxf);
+    const long src = (long)(dim == 1 ? 0 : j / 2) * nxc + i / 2;
+    for (int k = 0; k < ncomp; ++k) f[k * Nf + idx] = c[k * Nc + src];
+}
+
+// ---------------------------------------------------------------------------
 // Batched kernels: one block per work item (instance, tile), in XCD-aware
 // order; the per-cell work is the same function as in the single-problem
 // kernels, so every instance's results are those of its own solve.  Tiles of
@@ -1810,6 +1851,19 @@ hipError_t launch_multi_axpy(long n, const double *V, long ld, int nv, const dou
                              double *w, hipStream_t s)
 {
     NMG_LAUNCH(k_multi_axpy, nblocks(n), n, V, ld, nv, c, a, w);
+}
+
+hipError_t launch_average(int dim, int nxf, int nyf, int ncomp, const double *f, double *c,
+                          hipStream_t s)
+{
+    const long Nc = (long)(nxf / 2) * (dim == 1 ? 1 : nyf / 2);
+    NMG_LAUNCH(k_average, nblocks(Nc), dim, nxf, nyf, ncomp, f, c);
+}
+
+hipError_t launch_inject(int dim, int nxf, int nyf, int ncomp, const double *c, double *f,
+                         hipStream_t s)
+{
+    NMG_LAUNCH(k_inject, nblocks((long)nxf * nyf), dim, nxf, nyf, ncomp, c, f);
 }
 
 // ---- batched launchers ----

@@ -40,13 +40,14 @@ class nmg_params(C.Structure):
                 ("eps_r", C.c_double), ("n_levels", C.c_int), ("nu1", C.c_int),
                 ("nu2", C.c_int), ("nu_coarse", C.c_int), ("n_mg", C.c_int),
                 ("blu_sweeps", C.c_int), ("max_newton", C.c_int), ("dry_pin", C.c_int),
-                ("pos_theta", C.c_double), ("inner_fp32", C.c_int), ("gamma", C.c_int)]
+                ("pos_theta", C.c_double), ("inner_fp32", C.c_int), ("gamma", C.c_int),
+                ("eps_p", C.c_double), ("init_max_sweeps", C.c_int)]
 
 
 class nmg_stats(C.Structure):
     _fields_ = [("newton_steps", C.c_int), ("status", C.c_int), ("n_pinned", C.c_int),
                 ("res_l1", C.c_double), ("res_hist", C.POINTER(C.c_double)),
-                ("hist_cap", C.c_int)]
+                ("hist_cap", C.c_int), ("init_sweeps", C.c_int)]
 
 
 _lib = None
@@ -136,7 +137,8 @@ def _params(params):
                       int(params["n_mg"]), int(params["blu_sweeps"]),
                       int(params["max_newton"]), int(params["dry_pin"]),
                       float(params["pos_theta"]), int(params.get("inner_fp32", 0)),
-                      int(params.get("gamma", 1)))
+                      int(params.get("gamma", 1)), float(params.get("eps_p", 0.0)),
+                      int(params.get("init_max_sweeps", 1000)))
 
 
 class Context:
@@ -214,14 +216,15 @@ class Context:
 
     def newton_mg_solve(self, z, U, tol, hist_cap=10000):
         hist = (C.c_double * hist_cap)()
-        st = nmg_stats(0, 0, 0, 0.0, C.cast(hist, C.POINTER(C.c_double)), hist_cap)
+        st = nmg_stats(0, 0, 0, 0.0, C.cast(hist, C.POINTER(C.c_double)), hist_cap, 0)
         rc = lib().nmg_newton_mg_solve(self._h, _ptr(z, "z"), _ptr(U, "U"), float(tol),
                                        C.byref(st))
         self._check(rc, ok=(0, 1, -4, -5))
         n = st.newton_steps
         nh = min(n + 1 if rc in (0, -4, -5) else n, hist_cap)
         return dict(status=STATUS.get(rc, rc), newton_steps=n, n_pinned=st.n_pinned,
-                    res_l1=st.res_l1, res_hist=[hist[k] for k in range(nh)])
+                    res_l1=st.res_l1, res_hist=[hist[k] for k in range(nh)],
+                    init_sweeps=st.init_sweeps)
 
     def load_system(self, A0, b0):
         self._check(lib().nmg_load_system(self._h, _ptr(A0, "A0"), _ptr(b0, "b0")))
@@ -335,7 +338,7 @@ class Batch:
         for k in range(self.n):
             st[k] = nmg_stats(0, 0, 0, 0.0,
                               C.cast(hists[k], C.POINTER(C.c_double)) if hist_cap else None,
-                              int(hist_cap))
+                              int(hist_cap), 0)
         rc = lib().nmg_batch_newton_mg_solve(self._h, zp, up, float(tol), st)
         self._check(rc, ok=(0, 1))
         out = []

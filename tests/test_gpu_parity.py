@@ -321,3 +321,32 @@ def test_full_size_fp32_cycle(nmg):
     x = torch.zeros_like(U)
     ctx.mg_vcycle(x, 1)
     same(host(x), oracle.vcycles(Ao, bo, np.zeros_like(bo), prob.params, 1), "dU FP32 1024^2")
+
+
+STEP1 = [
+    (lambda: W.bump_1d(200, n_levels=3), 0.01),
+    (lambda: W.channel(64, 32, n_levels=3, mound_amp=0.3, gamma=2), 0.01),
+    (lambda: W.wetdry_1d(128, n_levels=5), 0.05),
+]
+
+
+@pytest.mark.parametrize("k", range(len(STEP1)))
+def test_newton_with_step1_bitwise(nmg, k):
+    """Algorithm 1 with Step 1 (nested BLU-SGS initial guess, eps_p a
+    fraction of the initial residual) against the oracle: same sweeps, same
+    Newton steps, same state bit for bit."""
+    mk, frac = STEP1[k]
+    prob = mk()
+    r0 = oracle.residual(prob, oracle.threshold(prob, prob.U0))[1]
+    prob = prob.with_params(eps_p=frac * r0)
+    say("step1", prob.name, prob.params["eps_p"])
+    ctx = nmg.Context.from_problem(prob)
+    U = dev(prob.U0)
+    st = ctx.newton_mg_solve(dev(prob.z), U, 1e-10)
+    Uo, so = oracle.newton_solve(prob, tol=1e-10)
+    say("  gpu", st["status"], st["newton_steps"], st["init_sweeps"], "oracle", so["status"],
+        so["newton_steps"], so["init_sweeps"])
+    assert (st["status"], st["newton_steps"], st["init_sweeps"]) == \
+        (so["status"], so["newton_steps"], so["init_sweeps"])
+    assert st["init_sweeps"] > 0
+    same(host(U), Uo, "U after Step 1 + Newton")
