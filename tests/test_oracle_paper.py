@@ -143,3 +143,36 @@ def test_dry_hill_2d_converges():
     # the hill top above every wet surface stays dry
     assert (U[0][prob.z > 0.25] == 0).all()
     assert ((U[0] + prob.z)[U[0] > 0] < 0.25).all()
+
+
+def test_interface_mass_fluxes_equal_at_steady_state():
+    """At a steady state of the 1D bump every interior interface carries the
+    same mass flux (R_i's mass component is the difference of its two face
+    fluxes), to within the stop tolerance.  The face fluxes are recomputed
+    here from the numerical flux on hydrostatically reconstructed states."""
+    prob = W.bump_1d(200)
+    U, st = oracle.newton_solve(prob, tol=1e-11)
+    assert st["status"] == "OK"
+    g, eps_r = prob.params["g"], prob.params["eps_r"]
+    h, q, z = U[0, 0], U[1, 0], prob.z[0]
+    fl = []
+    for i in range(prob.nx - 1):
+        zm = max(z[i], z[i + 1])
+        hl = max(0.0, h[i] + z[i] - zm)
+        hr = max(0.0, h[i + 1] + z[i + 1] - zm)
+        ul, ur = q[i] / h[i], q[i + 1] / h[i + 1]
+        fl.append(oracle.num_flux(prob.params["flux"], 2, 0, g, eps_r, hl, ul, 0.0, hr, ur, 0.0)[0])
+    fl = np.array(fl)
+    assert fl.max() - fl.min() < 2e-11
+    assert abs(fl.mean() - 4.42) < 1e-2
+
+
+def test_newton_steps_roughly_mesh_independent():
+    """The number of Newton steps on the 1D bump stays of the same size as the
+    mesh is refined (200, 400, 800 cells; N_L grows with N)."""
+    steps = []
+    for n, nl in ((200, 3), (400, 4), (800, 5)):
+        _, st = oracle.newton_solve(W.bump_1d(n, n_levels=nl), tol=1e-10)
+        assert st["status"] == "OK"
+        steps.append(st["newton_steps"])
+    assert max(steps) <= 2 * min(steps), steps
