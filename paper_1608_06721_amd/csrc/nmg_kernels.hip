@@ -944,9 +944,14 @@ __device__ __forceinline__ void coarse_run(const CoarseOp &op, const LevelGeom &
                 gs_update<T, NC, true, true>(a, inv, bv, v, ok, xi);
             } else {
 #pragma unroll
-                for (int f = 0; f < NF; ++f)
+                for (int f = 0; f < NF; ++f) {
+                    const int q = ok[f] ? nb[f] : t;      // a valid slot; its value is dropped
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) v[f][c] = ok[f] ? xo[c * plane + nb[f]] : T(0);
+                    for (int c = 0; c < NC; ++c) {
+                        const T val = xo[c * plane + q];
+                        v[f][c] = ok[f] ? val : T(0);
+                    }
+                }
                 gs_update<T, NC, false, true>(a, inv, bv, v, ok, xi);
             }
 #pragma unroll

@@ -140,26 +140,34 @@ __device__ __forceinline__ void read_other(const LevelGeom &G, const T *xo, int 
 }
 
 // The arithmetic of one block Gauss-Seidel cell update: acc = sum over the
-// existing neighbours (W, E, S, N order) and components of A_f x_f, then
+// neighbours (W, E, S, N order) and components of A_f x_f, then
 // x_i = D_i^-1 (b_i - acc) by solve_block (a holds D) or solve_inv (inv).
-// ZERO: every neighbour value is zero, so acc = 0.
+// ZERO: every neighbour value is zero, so acc = 0.  A face without a
+// neighbour has a zero block and a zero value here, so its terms are +0 and
+// leave acc unchanged (acc starts at +0 and can never become -0): it is
+// summed like the others, without a branch.  Each row's sum runs in face,
+// then component order; the rows are interleaved.
 template <class T, int NC, bool ZERO, bool INV>
 __device__ __forceinline__ void gs_update(const T *a, const T *inv, const T *bv,
                                           const T (*v)[NC], const bool *ok, T *xi)
 {
     constexpr int NF = (NC == 2) ? 2 : 4;
+    (void)ok;
     T acc[NC];
 #pragma unroll
     for (int r = 0; r < NC; ++r) acc[r] = T(0);
     if (!ZERO) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            if (!ok[f]) continue;
+            T p[NC][NC];
 #pragma unroll
             for (int r = 0; r < NC; ++r)
 #pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    acc[r] = acc[r] + a[((f + 1) * NC + r) * NC + c] * v[f][c];
+                for (int c = 0; c < NC; ++c) p[r][c] = a[((f + 1) * NC + r) * NC + c] * v[f][c];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int r = 0; r < NC; ++r) acc[r] = acc[r] + p[r][c];
         }
     }
     T rhs[NC];
