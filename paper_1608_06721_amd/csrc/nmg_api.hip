@@ -97,7 +97,8 @@ struct nmg_batch {
     WorkItem *d_work = nullptr;
     WorkRange w_cells0{nullptr, 0};       // 256-cell tiles of level 0
     WorkRange w_plane[kMaxLevels][kNumTiles];   // colour-plane tiles per tile length
-    WorkRange w_ccells[kMaxLevels];       // 256-cell tiles of level l (restriction into l, Galerkin)
+    WorkRange w_ccells[kMaxLevels];       // 256-cell tiles of level l (Galerkin into l)
+    WorkRange w_rchild[kMaxLevels];       // tiles of 256 children of level l's cells (restriction into l)
     int tile[kMaxLevels];                 // tile length of the half sweeps per level
     int *d_active = nullptr, *h_active = nullptr;   // instances still iterating
     int *d_mask = nullptr, *h_mask = nullptr;       // a second instance mask
@@ -303,7 +304,7 @@ int cycle(nmg_ctx *c, int l)
             c->rec.push_back(CoarseOp{COP_RESTRICT, l, 0, 0});
         else if (c->batch)
             HIPCHK(c, launch_b_restrict(c->dim, c->f32, c->batch->d_lv + (long)l * c->batch->n,
-                                        c->batch->w_ccells[l + 1], c->batch->d_active, c->stream));
+                                        c->batch->w_rchild[l + 1], c->batch->d_active, c->stream));
         else
             HIPCHK(c, launch_restrict(c->dim, c->f32, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b, c->stream));
         set_zero(c, l + 1);
@@ -1244,6 +1245,8 @@ int nmg_batch_create(int n, const nmg_grid *grids, const nmg_bc *bcs, const nmg_
         if (l >= 1) {
             for (int k = 0; k < n; ++k) u[k] = cells(geom(k, l));
             rb.add(&b->w_ccells[l], u, kBlock);
+            for (int k = 0; k < n; ++k) u[k] = cells(geom(k, l)) * (b->dim == 1 ? 2 : 4);
+            rb.add(&b->w_rchild[l], u, kBlock);
         }
     }
     std::vector<BatchLevel> blv((size_t)(NL + 1) * n);

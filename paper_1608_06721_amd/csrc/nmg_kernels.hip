@@ -732,6 +732,50 @@ __device__ __forceinline__ void restrict_cell(const LevelGeom &G, const T *__res
     for (int q = 0; q < NC; ++q) bm[q * Gc.plane] = acc[q];
 }
 
+// Restriction with one thread per child: a block of kBlock threads covers
+// CB = kBlock / nch consecutive coarse cells (nch = 4 children in 2D, 2 in
+// 1D); thread u of the block handles child u / CB of cell u % CB, so each
+// wave reads one child position of consecutive cells (coalesced), and the
+// block's first CB threads sum the children's residuals, exchanged through
+// LDS, in the order of restrict_cell.  base: index of the block's first
+// coarse cell.  Every thread of the block reaches the barrier.
+template <class T, int NC>
+__device__ __forceinline__ void restrict_block(const LevelGeom &G, const T *__restrict__ A,
+                                               const T *__restrict__ b,
+                                               const T *__restrict__ x, const LevelGeom &Gc,
+                                               T *__restrict__ bc, long base)
+{
+    constexpr int nch = (NC == 2) ? 2 : 4;
+    constexpr int CB = kBlock / nch;
+    __shared__ T rs[nch][NC][CB];
+    const int ch = (int)threadIdx.x / CB, k = (int)threadIdx.x % CB;
+    const long t = base + k;
+    const bool valid = t < (long)Gc.nx * Gc.ny;
+    const int I = valid ? (int)(t % Gc.nx) : 0, J = valid ? (int)(t / Gc.nx) : 0;
+    if (valid) {
+        T r[NC];
+        const int i = 2 * I + (ch & 1);
+        const int j = (NC == 2) ? 0 : 2 * J + (ch >> 1);
+        lin_residual_cell<T, NC>(G, A, b, x, i, j, r);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) rs[ch][q][k] = r[q];
+    }
+    __syncthreads();
+    if (valid && ch == 0) {
+        T acc[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[q] = T(0);
+#pragma unroll
+        for (int c = 0; c < nch; ++c)
+#pragma unroll
+            for (int q = 0; q < NC; ++q) acc[q] = acc[q] + rs[c][q][k];
+        const int cc = (I + J) & 1;
+        T *bm = bc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) bm[q * Gc.plane] = acc[q];
+    }
+}
+
 template <class T, int NC>
 __global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const T *__restrict__ A,
                                                      const T *__restrict__ b,
@@ -739,9 +783,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const T *__res
                                                      T *__restrict__ bc)
 {
     const int xb = xcd_block(blockIdx.x, gridDim.x);
-    long t = (long)xb * kBlock + threadIdx.x;
-    if (t >= (long)Gc.nx * Gc.ny) return;
-    restrict_cell<T, NC>(G, A, b, x, Gc, bc, t);
+    restrict_block<T, NC>(G, A, b, x, Gc, bc, (long)xb * (kBlock / ((NC == 2) ? 2 : 4)));
 }
 
 // Galerkin coarse blocks (eq:ProjectAR, left) with the child-pair order of
@@ -1594,9 +1636,9 @@ __global__ void __launch_bounds__(kBlock) kb_restrict(const BatchLevel *__restri
     const WorkItem it = work_item(w, pos);
     if (!active[it.inst]) return;
     const BatchLevel &L = lv[it.inst];
-    const long t = (long)it.tile * kBlock + threadIdx.x;
-    if (t < (long)L.Gc.nx * L.Gc.ny)
-        restrict_cell<T, NC>(L.G, (const T *)L.A, (const T *)L.b, (const T *)L.x, L.Gc, (T *)L.bc, t);
+    // tiles of kBlock children = kBlock / nch coarse cells
+    restrict_block<T, NC>(L.G, (const T *)L.A, (const T *)L.b, (const T *)L.x, L.Gc, (T *)L.bc,
+                          (long)it.tile * (kBlock / ((NC == 2) ? 2 : 4)));
 }
 
 template <class T, int NC>
@@ -1738,7 +1780,7 @@ hipError_t launch_sgs_half(int dim, bool f32, int mode, const LevelGeom &G, cons
 hipError_t launch_restrict(int dim, bool f32, const LevelGeom &G, const void *A, const void *b,
                            const void *x, const LevelGeom &Gc, void *bc, hipStream_t s)
 {
-    int g = nblocks((long)Gc.nx * Gc.ny);
+    int g = nblocks((long)Gc.nx * Gc.ny * (dim == 1 ? 2 : 4));
     if (f32) {
         if (dim == 1) NMG_LAUNCH((k_restrict<float, 2>), g, G, (const float *)A, (const float *)b, (const float *)x, Gc, (float *)bc);
         NMG_LAUNCH((k_restrict<float, 3>), g, G, (const float *)A, (const float *)b, (const float *)x, Gc, (float *)bc);
