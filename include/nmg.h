@@ -217,13 +217,14 @@ int nmg_bed_vjp(nmg_ctx *ctx, const double *z, const double *U, const double *la
                 double *out);
 
 /* Measurement hooks.  With enable = 1 the library records a pair of
- * hipEvents on its stream around each full finest-level block SGS half
- * sweep (one that reads every neighbour block), for at most `cap`
- * (<= 2^20) launches; the events are created here, so recording adds no
- * allocation to the solve, and enabling again drops earlier records.
- * enable = 0 stops recording.  nmg_timing_read synchronizes the stream and
- * returns, over the recorded launches, the summed kernel milliseconds, the
- * number of launches and the number of cell updates they performed. */
+ * hipEvents on its stream around each run of full finest-level block SGS
+ * half sweeps (ones that read every neighbour block) launched back to back
+ * within one smoothing call, for at most `cap` (<= 2^20) runs; the events
+ * are created here, so recording adds no allocation to the solve, and
+ * enabling again drops earlier records.  enable = 0 stops recording.
+ * nmg_timing_read synchronizes the stream and returns, over the recorded
+ * runs, the summed milliseconds, the number of launches and the number of
+ * cell updates they performed. */
 int nmg_timing_enable(nmg_ctx *ctx, int enable, int cap);
 int nmg_timing_read(nmg_ctx *ctx, double *sgs_ms_host, int *sgs_launches_host,
                     long long *sgs_cells_host);

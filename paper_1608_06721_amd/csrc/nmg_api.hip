@@ -66,9 +66,11 @@ struct nmg_ctx {
     std::string err;
     // measurement hooks
     bool timing = false;
-    int nrec = 0;                 // events of ev[] in use
+    int nrec = 0;                 // event pairs of ev[] in use
+    int tgroup = -1;              // pair of the open run of back-to-back timed launches, or -1
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<long long> ev_cells;
+    std::vector<int> ev_launches;
     // coarse part of the V-cycle in one workgroup (levels lc..NL), recorded
     // once from the same state machine that drives the per-level launches
     int lc = -1;
@@ -202,19 +204,28 @@ int halfsweep(nmg_ctx *c, int l, int color)
         Lv.last = color;
         return NMG_OK;
     }
-    // Measurement hook: only full half sweeps (all neighbour blocks read)
-    // of the finest level are recorded.
-    const int k = c->nrec;
-    const bool rec = c->timing && l == 0 && mode == MODE_NORMAL && k < (int)c->ev.size();
-    if (rec) HIPCHK(c, hipEventRecord(c->ev[k].first, c->stream));
+    // Measurement hook: full half sweeps (all neighbour blocks read) of the
+    // finest level.  A run of them launched back to back (within one
+    // smoothing call) shares one pair of events around the whole run.
+    const bool want = c->timing && l == 0 && mode == MODE_NORMAL;
+    const bool open = want && c->tgroup >= 0;
+    const int k = open ? c->tgroup : c->nrec;
+    const bool rec = want && k < (int)c->ev.size();
+    if (rec && !open) HIPCHK(c, hipEventRecord(c->ev[k].first, c->stream));
     HIPCHK(c, launch_sgs_half(c->dim, c->f32, mode, Lv.G, Lv.A, Lv.b, Lv.x, color, Lc.G, Lc.x,
                               c->stream));
     if (rec) {
         HIPCHK(c, hipEventRecord(c->ev[k].second, c->stream));
         long n = 0;
         for (int j = 0; j < Lv.G.ny; ++j) n += (Lv.G.nx - ((j + color) & 1) + 1) / 2;
-        c->ev_cells[k] = n;
-        c->nrec = k + 1;
+        c->ev_cells[k] += n;
+        c->ev_launches[k] += 1;
+        if (!open) {
+            c->nrec = k + 1;
+            c->tgroup = k;
+        }
+    } else {
+        c->tgroup = -1;
     }
     Lv.st[color] = ST_VALID;
     Lv.last = color;
@@ -223,12 +234,14 @@ int halfsweep(nmg_ctx *c, int l, int color)
 
 int smooth(nmg_ctx *c, int l, int iters)
 {
+    c->tgroup = -1;               // timed runs never span other launches
     for (int it = 0; it < iters; ++it) {
         int rc;
         if ((rc = halfsweep(c, l, 0)) || (rc = halfsweep(c, l, 1)) || (rc = halfsweep(c, l, 1)) ||
             (rc = halfsweep(c, l, 0)))
             return rc;
     }
+    c->tgroup = -1;
     return NMG_OK;
 }
 
@@ -1058,7 +1071,9 @@ int nmg_timing_enable(nmg_ctx *c, int enable, int cap)
             c->ev.emplace_back(a, b);
         }
         c->ev_cells.assign(c->ev.size(), 0);
+        c->ev_launches.assign(c->ev.size(), 0);
         c->nrec = 0;
+        c->tgroup = -1;
     }
     c->timing = enable != 0;
     return NMG_OK;
@@ -1070,14 +1085,16 @@ int nmg_timing_read(nmg_ctx *c, double *ms_host, int *launches_host, long long *
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double tot = 0.0;
     long long cl = 0;
+    int nl = 0;
     for (int k = 0; k < c->nrec; ++k) {
         float ms = 0.0f;
         HIPCHK(c, hipEventElapsedTime(&ms, c->ev[k].first, c->ev[k].second));
         tot += ms;
         cl += c->ev_cells[k];
+        nl += c->ev_launches[k];
     }
     if (ms_host) *ms_host = tot;
-    if (launches_host) *launches_host = c->nrec;
+    if (launches_host) *launches_host = nl;
     if (cells_host) *cells_host = cl;
     return NMG_OK;
 }

@@ -350,3 +350,23 @@ def test_newton_with_step1_bitwise(nmg, k):
         (so["status"], so["newton_steps"], so["init_sweeps"])
     assert st["init_sweeps"] > 0
     same(host(U), Uo, "U after Step 1 + Newton")
+
+
+def test_timing_hook_counts_full_finest_sweeps(nmg):
+    """The measurement hook: every recorded launch is a full finest-level half
+    sweep (half the cells each), and the recorded time is positive and not
+    above the solve's own wall time."""
+    import time
+    prob = W.channel(64, 64, n_levels=3, gamma=2)
+    ctx = nmg.Context.from_problem(prob)
+    ctx.timing_enable(True, 1000)
+    U = dev(prob.U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.newton_mg_solve(dev(prob.z), U, 1e-10)
+    wall = time.perf_counter() - t0
+    tm = ctx.timing_read()
+    say("timing", st["newton_steps"], tm)
+    assert tm["launches"] > 0
+    assert tm["cells"] == tm["launches"] * (64 * 64 // 2)
+    assert 0 < tm["ms"] <= 1e3 * wall
