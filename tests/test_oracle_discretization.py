@@ -184,3 +184,80 @@ def test_dry_momentum_pin():
     assert A[0, 1, 0, 0, 3] == 0 and b[1, 0, 3] == 0 and (A[1:, 1, :, 0, 3] == 0).all()
     A2, b2, _ = oracle.assemble(prob, U, dict(prob.params, dry_pin=0))
     assert A2[0, 1, 1, 0, 3] != A2[0, 0, 0, 0, 3]
+
+
+def blu_replay(prob, U0, redblack=False):
+    """One lexicographic BLU-SGS sweep (Algorithm 1, Step 2.1) from its
+    definition: for each cell, forward then backward, U_i -= (alpha ||R_i||_1 I
+    + dR_i/dU_i)^-1 R_i with R and the diagonal block recomputed at the
+    latest state (brute-force forward differences of the whole residual),
+    the dry-cell pin, and the dry threshold after the update."""
+    p = prob.params
+    nc, nx, ny = prob.nc, prob.nx, prob.ny
+    U = U0.copy()
+    order = [(j, i) for j in range(ny) for i in range(nx)]
+    if redblack:        # red, black, then black, red (cells of one colour are independent)
+        red = [c for c in order if (c[0] + c[1]) % 2 == 0]
+        black = [c for c in order if (c[0] + c[1]) % 2 == 1]
+        seq = red + black + black + red
+    else:
+        seq = order + order[::-1]
+    for j, i in seq:
+        R, _ = oracle.residual(prob, U)
+        Ri = R[:, j, i].copy()
+        D = np.zeros((nc, nc))
+        for k in range(nc):
+            Up = U.copy()
+            Up[k, j, i] += p["fd_eps"]
+            Rp, _ = oracle.residual(prob, Up)
+            D[:, k] = (Rp[:, j, i] - Ri) / p["fd_eps"]
+        D += p["alpha"] * np.abs(Ri).sum() * np.eye(nc)
+        if p["dry_pin"] and U[0, j, i] == 0.0:
+            D[1:, :] = 0.0
+            for r in range(1, nc):
+                D[r, r] = D[0, 0]
+            Ri[1:] = 0.0
+        U[:, j, i] -= np.linalg.solve(D, Ri)
+        if U[0, j, i] < p["h_eps"]:
+            U[:, j, i] = 0.0
+    return U
+
+
+@pytest.mark.parametrize("order", [W.LEX, W.REDBLACK])
+@pytest.mark.parametrize("mk", [lambda: W.bump_1d(16), lambda: W.channel(6, 4, n_levels=1, mound_amp=0.3)])
+def test_blu_sweep_is_the_block_lu_sgs_definition(mk, order):
+    prob = mk().with_params(order=order)
+    U0 = prob.U0.copy()
+    U0[0] *= 1.05                        # away from the initial data's symmetries
+    got = oracle.blu_sweep(prob, U0)
+    ref = blu_replay(prob, U0, redblack=order == W.REDBLACK)
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-9)
+    assert np.abs(got - U0).max() > 1e-4  # the sweep moved the state
+
+
+def test_positivity_relaxation():
+    """Per-cell relaxation of the Newton update U_i += tau_i dU_i (pos_theta):
+    with the same linear solve, a cell whose full step would remove more than
+    the fraction theta of its depth keeps exactly (1 - theta) h_i, its
+    momentum moves by the same fraction of the full step, and every other
+    cell takes the full step.  A thin film on the dry hill's dry cells and a
+    small alpha give cells where the limit acts."""
+    prob = W.dry_hill(32, 16)
+    th = 0.9
+    U = prob.U0.copy()
+    U[0][U[0] == 0] = 1e-2
+    U[0] *= np.random.default_rng(1).uniform(0.5, 1.5, U[0].shape)
+    base = dict(prob.params, max_newton=1, blu_sweeps=0, alpha=0.1, tau=1.0)
+    Ua, _ = oracle.newton_solve(prob, U0=U, params=dict(base, pos_theta=0.0))
+    Ub, _ = oracle.newton_solve(prob, U0=U, params=dict(base, pos_theta=th))
+    h0 = U[0]
+    lim = Ua[0] < (1 - th) * h0
+    assert lim.sum() > 50
+    np.testing.assert_array_equal(Ua[:, ~lim], Ub[:, ~lim])
+    np.testing.assert_allclose(Ub[0][lim], (1 - th) * h0[lim], rtol=1e-12)
+    full = lim & (Ua[0] > 0)                  # full step not cut by the dry threshold
+    assert full.sum() > 5
+    t = (Ub[0] - h0)[full] / (Ua[0] - h0)[full]
+    assert (t > 0).all() and (t < 1).all()
+    for k in range(1, prob.nc):
+        np.testing.assert_allclose((Ub[k] - U[k])[full], t * (Ua[k] - U[k])[full], rtol=1e-9, atol=1e-15)
