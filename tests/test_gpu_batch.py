@@ -95,6 +95,11 @@ CASES = {
     # every level launched on its own (no coarse kernel)
     "launched": (lambda: W.batch_channels(3, sizes=(32, 64), seed=13, n_levels=3, gamma=2,
                                           max_newton=40), 1e-10, "0"),
+    # 1D: two bed families, uneven lengths, the coarse kernel on the 8..25-cell levels
+    "one_d": (lambda: [W.bump_1d(64, n_levels=3, max_newton=80),
+                       W.smooth_1d(96, n_levels=3, max_newton=80),
+                       W.bump_1d(128, n_levels=3, max_newton=80),
+                       W.smooth_1d(200, n_levels=3, max_newton=80)], 1e-10, "1024"),
     # a step limit that stops some instances before others converge
     "step_limit": (lambda: W.batch_channels(4, sizes=(32, 64), seed=14, n_levels=3,
                                             max_newton=9), 1e-10, "1024"),
