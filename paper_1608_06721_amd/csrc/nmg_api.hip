@@ -213,7 +213,7 @@ int halfsweep(nmg_ctx *c, int l, int color)
     const bool rec = want && k < (int)c->ev.size();
     if (rec && !open) HIPCHK(c, hipEventRecord(c->ev[k].first, c->stream));
     HIPCHK(c, launch_sgs_half(c->dim, c->f32, mode, Lv.G, Lv.A, Lv.b, Lv.x, color, Lc.G, Lc.x,
-                              c->stream));
+                              stream_level(cells(Lv.G), c->nc, c->f32 ? 4 : 8), c->stream));
     if (rec) {
         HIPCHK(c, hipEventRecord(c->ev[k].second, c->stream));
         long n = 0;
@@ -319,7 +319,9 @@ int cycle(nmg_ctx *c, int l)
             HIPCHK(c, launch_b_restrict(c->dim, c->f32, c->batch->d_lv + (long)l * c->batch->n,
                                         c->batch->w_rchild[l + 1], c->batch->d_active, c->stream));
         else
-            HIPCHK(c, launch_restrict(c->dim, c->f32, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b, c->stream));
+            HIPCHK(c, launch_restrict(c->dim, c->f32, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b,
+                                      stream_level(cells(Lv.G), c->nc, c->f32 ? 4 : 8),
+                                      c->stream));
         set_zero(c, l + 1);
         // gamma coarse cycles (gamma = 1: V, 2: W), one when leaving the
         // finest level (Algorithm 0)

@@ -98,6 +98,17 @@ struct CoarseOp {
 
 inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
 
+// A level whose block matrix is larger than this cannot stay in the chip's
+// 256 MB last-level cache between two visits of the level in a cycle, so its
+// launches fetch the matrix as read-once data (non-temporal hint); smaller
+// levels are left to the cache, which serves their repeated visits.
+constexpr long kStreamBytes = 128L << 20;
+inline bool stream_level(long cells, int nc, long elem_bytes)
+{
+    const long ne = (nc == 2 ? 3 : 5) * (long)nc * nc;
+    return cells * ne * elem_bytes > kStreamBytes;
+}
+
 // ---- launchers (return hipError_t of the launch) ----
 hipError_t launch_isolated(const Phys &P, const double *z, const double *U, unsigned char *iso,
                            hipStream_t s);
@@ -114,11 +125,13 @@ hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool 
 hipError_t launch_threshold(const Phys &P, double *U, hipStream_t s);
 
 // Linear multigrid launchers; f32 selects the float hierarchy.
+// stream: the level's matrix is fetched as read-once data (stream_level).
 hipError_t launch_sgs_half(int dim, bool f32, int mode, const LevelGeom &G, const void *A,
                            const void *b, void *x, int color, const LevelGeom &Gc, const void *xc,
-                           hipStream_t s);
+                           bool stream, hipStream_t s);
 hipError_t launch_restrict(int dim, bool f32, const LevelGeom &G, const void *A, const void *b,
-                           const void *x, const LevelGeom &Gc, void *bc, hipStream_t s);
+                           const void *x, const LevelGeom &Gc, void *bc, bool stream,
+                           hipStream_t s);
 hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *Af,
                            const LevelGeom &Gc, void *Ac, hipStream_t s);
 // Materialize one colour of x: op 0 = set zero, 1 = add the parent's

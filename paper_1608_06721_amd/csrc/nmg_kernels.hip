@@ -659,7 +659,8 @@ __global__ void __launch_bounds__(kBlock) k_threshold(Phys P, double *__restrict
 // Linear multigrid kernels on the colour-split layout.
 
 // Linear residual of fine cell (i, j): b - (D x_i + sum_nbr A x_nbr).
-template <class T, int NC>
+// STREAM: off-diagonal blocks loaded through ld_once (read once per launch).
+template <class T, int NC, bool STREAM = false>
 __device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const T *A,
                                                   const T *b, const T *x, int i, int j,
                                                   T *r)
@@ -698,7 +699,7 @@ __device__ __forceinline__ void lin_residual_cell(const LevelGeom &G, const T *A
         for (int q = 0; q < NC; ++q)
 #pragma unroll
             for (int c = 0; c < NC; ++c)
-                acc[q] = acc[q] + Am[(((f + 1) * NC + q) * NC + c) * kTile] * v[c];
+                acc[q] = acc[q] + ld_once<T, STREAM>(&Am[(((f + 1) * NC + q) * NC + c) * kTile]) * v[c];
     }
 #pragma unroll
     for (int q = 0; q < NC; ++q) r[q] = bm[q * G.plane] - acc[q];
@@ -739,7 +740,7 @@ __device__ __forceinline__ void restrict_cell(const LevelGeom &G, const T *__res
 // block's first CB threads sum the children's residuals, exchanged through
 // LDS, in the order of restrict_cell.  base: index of the block's first
 // coarse cell.  Every thread of the block reaches the barrier.
-template <class T, int NC>
+template <class T, int NC, bool STREAM = false>
 __device__ __forceinline__ void restrict_block(const LevelGeom &G, const T *__restrict__ A,
                                                const T *__restrict__ b,
                                                const T *__restrict__ x, const LevelGeom &Gc,
@@ -756,7 +757,7 @@ __device__ __forceinline__ void restrict_block(const LevelGeom &G, const T *__re
         T r[NC];
         const int i = 2 * I + (ch & 1);
         const int j = (NC == 2) ? 0 : 2 * J + (ch >> 1);
-        lin_residual_cell<T, NC>(G, A, b, x, i, j, r);
+        lin_residual_cell<T, NC, STREAM>(G, A, b, x, i, j, r);
 #pragma unroll
         for (int q = 0; q < NC; ++q) rs[ch][q][k] = r[q];
     }
@@ -776,14 +777,14 @@ __device__ __forceinline__ void restrict_block(const LevelGeom &G, const T *__re
     }
 }
 
-template <class T, int NC>
+template <class T, int NC, bool STREAM>
 __global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const T *__restrict__ A,
                                                      const T *__restrict__ b,
                                                      const T *__restrict__ x, LevelGeom Gc,
                                                      T *__restrict__ bc)
 {
     const int xb = xcd_block(blockIdx.x, gridDim.x);
-    restrict_block<T, NC>(G, A, b, x, Gc, bc, (long)xb * (kBlock / ((NC == 2) ? 2 : 4)));
+    restrict_block<T, NC, STREAM>(G, A, b, x, Gc, bc, (long)xb * (kBlock / ((NC == 2) ? 2 : 4)));
 }
 
 // Galerkin coarse blocks (eq:ProjectAR, left) with the child-pair order of
@@ -1746,47 +1747,65 @@ hipError_t launch_threshold(const Phys &P, double *U, hipStream_t s)
     NMG_LAUNCH(k_threshold<3>, g, P, U);
 }
 
-template <class T, int NC>
+template <class T, int NC, bool ST>
 static hipError_t sgs_dispatch(int mode, const LevelGeom &G, const T *A, const T *b, T *x,
                                int color, const LevelGeom &Gc, const T *xc, hipStream_t s)
 {
     int g = nblocks(G.plane);
     switch (mode) {
-    case MODE_NORMAL: NMG_LAUNCH((k_sgs_half<T, NC, MODE_NORMAL>), g, G, A, b, x, color, Gc, xc);
-    case MODE_ZERO: NMG_LAUNCH((k_sgs_half<T, NC, MODE_ZERO>), g, G, A, b, x, color, Gc, xc);
-    case MODE_PROLONG: NMG_LAUNCH((k_sgs_half<T, NC, MODE_PROLONG>), g, G, A, b, x, color, Gc, xc);
-    default: NMG_LAUNCH((k_sgs_half<T, NC, MODE_PROLONG_ZERO>), g, G, A, b, x, color, Gc, xc);
+    case MODE_NORMAL: NMG_LAUNCH((k_sgs_half<T, NC, MODE_NORMAL, ST>), g, G, A, b, x, color, Gc, xc);
+    case MODE_ZERO: NMG_LAUNCH((k_sgs_half<T, NC, MODE_ZERO, ST>), g, G, A, b, x, color, Gc, xc);
+    case MODE_PROLONG: NMG_LAUNCH((k_sgs_half<T, NC, MODE_PROLONG, ST>), g, G, A, b, x, color, Gc, xc);
+    default: NMG_LAUNCH((k_sgs_half<T, NC, MODE_PROLONG_ZERO, ST>), g, G, A, b, x, color, Gc, xc);
     }
+}
+
+template <class T, int NC>
+static hipError_t sgs_stream(bool stream, int mode, const LevelGeom &G, const void *A,
+                             const void *b, void *x, int color, const LevelGeom &Gc,
+                             const void *xc, hipStream_t s)
+{
+    if (stream)
+        return sgs_dispatch<T, NC, true>(mode, G, (const T *)A, (const T *)b, (T *)x, color, Gc,
+                                         (const T *)xc, s);
+    return sgs_dispatch<T, NC, false>(mode, G, (const T *)A, (const T *)b, (T *)x, color, Gc,
+                                      (const T *)xc, s);
 }
 
 hipError_t launch_sgs_half(int dim, bool f32, int mode, const LevelGeom &G, const void *A,
                            const void *b, void *x, int color, const LevelGeom &Gc, const void *xc,
-                           hipStream_t s)
+                           bool stream, hipStream_t s)
 {
     if (f32) {
-        if (dim == 1)
-            return sgs_dispatch<float, 2>(mode, G, (const float *)A, (const float *)b, (float *)x,
-                                          color, Gc, (const float *)xc, s);
-        return sgs_dispatch<float, 3>(mode, G, (const float *)A, (const float *)b, (float *)x,
-                                      color, Gc, (const float *)xc, s);
+        if (dim == 1) return sgs_stream<float, 2>(stream, mode, G, A, b, x, color, Gc, xc, s);
+        return sgs_stream<float, 3>(stream, mode, G, A, b, x, color, Gc, xc, s);
     }
-    if (dim == 1)
-        return sgs_dispatch<double, 2>(mode, G, (const double *)A, (const double *)b, (double *)x,
-                                       color, Gc, (const double *)xc, s);
-    return sgs_dispatch<double, 3>(mode, G, (const double *)A, (const double *)b, (double *)x,
-                                   color, Gc, (const double *)xc, s);
+    if (dim == 1) return sgs_stream<double, 2>(stream, mode, G, A, b, x, color, Gc, xc, s);
+    return sgs_stream<double, 3>(stream, mode, G, A, b, x, color, Gc, xc, s);
+}
+
+template <class T, int NC>
+static hipError_t restrict_stream(bool stream, const LevelGeom &G, const void *A, const void *b,
+                                  const void *x, const LevelGeom &Gc, void *bc, hipStream_t s)
+{
+    int g = nblocks((long)Gc.nx * Gc.ny * (NC == 2 ? 2 : 4));
+    if (stream)
+        NMG_LAUNCH((k_restrict<T, NC, true>), g, G, (const T *)A, (const T *)b, (const T *)x, Gc,
+                   (T *)bc);
+    NMG_LAUNCH((k_restrict<T, NC, false>), g, G, (const T *)A, (const T *)b, (const T *)x, Gc,
+               (T *)bc);
 }
 
 hipError_t launch_restrict(int dim, bool f32, const LevelGeom &G, const void *A, const void *b,
-                           const void *x, const LevelGeom &Gc, void *bc, hipStream_t s)
+                           const void *x, const LevelGeom &Gc, void *bc, bool stream,
+                           hipStream_t s)
 {
-    int g = nblocks((long)Gc.nx * Gc.ny * (dim == 1 ? 2 : 4));
     if (f32) {
-        if (dim == 1) NMG_LAUNCH((k_restrict<float, 2>), g, G, (const float *)A, (const float *)b, (const float *)x, Gc, (float *)bc);
-        NMG_LAUNCH((k_restrict<float, 3>), g, G, (const float *)A, (const float *)b, (const float *)x, Gc, (float *)bc);
+        if (dim == 1) return restrict_stream<float, 2>(stream, G, A, b, x, Gc, bc, s);
+        return restrict_stream<float, 3>(stream, G, A, b, x, Gc, bc, s);
     }
-    if (dim == 1) NMG_LAUNCH((k_restrict<double, 2>), g, G, (const double *)A, (const double *)b, (const double *)x, Gc, (double *)bc);
-    NMG_LAUNCH((k_restrict<double, 3>), g, G, (const double *)A, (const double *)b, (const double *)x, Gc, (double *)bc);
+    if (dim == 1) return restrict_stream<double, 2>(stream, G, A, b, x, Gc, bc, s);
+    return restrict_stream<double, 3>(stream, G, A, b, x, Gc, bc, s);
 }
 
 hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *Af,
