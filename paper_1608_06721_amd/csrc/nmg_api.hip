@@ -389,6 +389,78 @@ void merge_runs(nmg_ctx *c, bool fits)
     }
 }
 
+// Replace each maximal sequence of alternating half sweeps on the first
+// coarse level lc (the first in any mode, the rest normal), with the
+// restriction from lc when it follows, by one COP_REGRUN whose residual
+// exchange area starts at LDS byte rs_off.  ok: lc lives in global memory,
+// has at most one slot per colour and thread, and the exchange area fits.
+void merge_reg_runs(nmg_ctx *c, bool ok, long rs_off)
+{
+    if (!ok) return;
+    if (const char *e = std::getenv("NMG_COARSE_REG"))
+        if (std::atoi(e) == 0) return;
+    const int lc = c->lc;
+    std::vector<CoarseOp> out;
+    int off[2], len[2];
+    for (int prog = 0; prog < 2; ++prog) {
+        off[prog] = (int)out.size();
+        const CoarseOp *r = c->rec.data() + c->prog_off[prog];
+        const int n = c->prog_len[prog];
+        for (int q = 0; q < n;) {
+            CoarseOp o = r[q];
+            if (o.kind == COP_SGS && o.level == lc) {
+                int e = q + 1;
+                while (e < n && r[e].kind == COP_SGS && r[e].level == lc &&
+                       r[e].mode == MODE_NORMAL && r[e].color == (r[e - 1].color ^ 1))
+                    ++e;
+                o.kind = COP_REGRUN;
+                o.count = e - q;
+                o.aux = 0;
+                o.lds_off = (int)rs_off;
+                if (e < n && r[e].kind == COP_RESTRICT && r[e].level == lc) {
+                    o.aux = 1;
+                    ++e;
+                }
+                q = e;
+            } else {
+                ++q;
+            }
+            out.push_back(o);
+        }
+        len[prog] = (int)out.size() - off[prog];
+    }
+    c->rec.swap(out);
+    for (int prog = 0; prog < 2; ++prog) {
+        c->prog_off[prog] = off[prog];
+        c->prog_len[prog] = len[prog];
+    }
+}
+
+// LDS bytes of the coarse-cycle kernel's level copies (levels l_lds..NL).
+long lds_levels_bytes(const nmg_ctx *c, int l_lds)
+{
+    long tot = 0;
+    if (l_lds >= 0)
+        for (int l = l_lds; l <= c->NL; ++l)
+            tot += lds_level_bytes(c->L[l].G, c->ne, c->nc, c->f32 ? 4 : 8);
+    return tot;
+}
+
+// Bytes of the residual exchange area of a register-resident run on level l.
+long reg_exchange_bytes(const nmg_ctx *c, int l)
+{
+    return 2L * c->nc * c->L[l].G.plane * (c->f32 ? 4 : 8);
+}
+
+// Whether level lc of context c can run as COP_REGRUN with its exchange area
+// at LDS byte rs_off.
+bool reg_run_fits(const nmg_ctx *c, int lc, int l_lds, long rs_off)
+{
+    if (l_lds >= 0 && lc >= l_lds) return false;
+    if (c->L[lc].G.plane > kCoarseBlock) return false;
+    return rs_off + reg_exchange_bytes(c, lc) <= kCoarseLdsBytes;
+}
+
 long coarse_cells_limit()
 {
     long maxcells = 1024;
@@ -435,8 +507,9 @@ void coarse_level_table(const nmg_ctx *c, int l_lds, LevelDev *lv)
 
 // Record the two coarse programs of context c from level c->lc (with the
 // LDS plan c->l_lds) and upload the operation list.  fits: the coarsest level
-// has a thread per cell (merged runs allowed).
-int record_coarse(nmg_ctx *c, bool fits)
+// has a thread per cell (merged runs allowed); reg_ok: level lc's half sweeps
+// may run register-resident with the exchange area at LDS byte rs_off.
+int record_coarse(nmg_ctx *c, bool fits, bool reg_ok, long rs_off)
 {
     Level saved[16];
     for (int l = 0; l <= c->NL; ++l) saved[l] = c->L[l];
@@ -460,6 +533,7 @@ int record_coarse(nmg_ctx *c, bool fits)
         return NMG_OK;
     }
     merge_runs(c, fits);
+    merge_reg_runs(c, reg_ok, rs_off);
     size_t ob = sizeof(CoarseOp) * c->rec.size();
     if (hipMalloc(&c->d_ops, ob) != hipSuccess) return fail(c, NMG_ENOMEM, "coarse-cycle program");
     HIPCHK(c, hipMemcpy(c->d_ops, c->rec.data(), ob, hipMemcpyHostToDevice));
@@ -471,7 +545,9 @@ int plan_coarse(nmg_ctx *c)
     c->lc = first_coarse_level(c);
     if (c->lc < 0) return NMG_OK;
     c->l_lds = lds_first_level(c, c->lc);
-    int rc = record_coarse(c, 2 * c->L[c->NL].G.plane <= kCoarseBlock);
+    const long rs_off = (lds_levels_bytes(c, c->l_lds) + 15) / 16 * 16;
+    int rc = record_coarse(c, 2 * c->L[c->NL].G.plane <= kCoarseBlock,
+                           reg_run_fits(c, c->lc, c->l_lds, rs_off), rs_off);
     if (rc || c->lc < 0) return rc;
     LevelDev lv[kMaxLevels];
     coarse_level_table(c, c->l_lds, lv);
@@ -1223,7 +1299,14 @@ int nmg_batch_create(int n, const nmg_grid *grids, const nmg_bc *bcs, const nmg_
         }
         for (int k = 0; k < n; ++k) fits = fits && 2 * geom(k, NL).plane <= kCoarseBlock;
         t->l_lds = l_lds < 0 ? -1 : l_lds;
-        int rc = record_coarse(t, fits);
+        long rs_off = 0;
+        for (int k = 0; k < n; ++k) {
+            const long used = (lds_levels_bytes(b->inst[k], t->l_lds) + 15) / 16 * 16;
+            rs_off = used > rs_off ? used : rs_off;
+        }
+        bool reg_ok = true;
+        for (int k = 0; k < n; ++k) reg_ok = reg_ok && reg_run_fits(b->inst[k], t->lc, t->l_lds, rs_off);
+        int rc = record_coarse(t, fits, reg_ok, rs_off);
         if (rc) {
             b->err = t->err;
             nmg_batch_destroy(b);

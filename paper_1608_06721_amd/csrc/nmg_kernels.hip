@@ -1004,6 +1004,183 @@ __device__ __forceinline__ void coarse_run(const CoarseOp &op, const LevelGeom &
     }
 }
 
+// One cell of a register-resident run: the cell of colour `color` at slot
+// threadIdx.x of a level in global memory (if it exists) and its block row,
+// loaded once for the whole run.  Its neighbours and right-hand side are
+// recomputed and reloaded where used, which keeps two block rows per thread
+// within the register file.
+template <class T, int NC>
+struct RegCell {
+    static constexpr int NF = (NC == 2) ? 2 : 4;
+    static constexpr int NE = (NF + 1) * NC * NC;
+    bool mine;
+    T a[NE];
+
+    __device__ __forceinline__ static void where(const LevelGeom &G, int color, int t, int &i,
+                                                 int &j)
+    {
+        j = t / G.W;
+        i = 2 * (t - j * G.W) + ((j + color) & 1);
+    }
+    __device__ __forceinline__ static void face(const LevelGeom &G, int i, int j, int f, int &ni,
+                                                int &nj, bool &ok)
+    {
+        ni = i;
+        nj = j;
+        if (f == FW) { ni = i - 1; ok = i > 0; }
+        else if (f == FE) { ni = i + 1; ok = i + 1 < G.nx; }
+        else if (f == FS) { nj = j - 1; ok = j > 0; }
+        else { nj = j + 1; ok = j + 1 < G.ny; }
+    }
+
+    __device__ __forceinline__ void load(const LevelGeom &G, const T *A, int color, int t)
+    {
+        int i, j;
+        where(G, color, t, i, j);
+        mine = t < G.plane && i < G.nx;
+        if (mine) {
+            const T *Am = A + mat_off(G, NE, color, t);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) a[e] = Am[e * kTile];
+        }
+    }
+
+    // Half sweep update of this cell: the arithmetic of sgs_cell.
+    template <int MODE>
+    __device__ __forceinline__ void update(const LevelGeom &G, const T *b, T *x, int color,
+                                           const LevelGeom &Gc, const T *xc, int t) const
+    {
+        if (!mine) return;
+        int i, j;
+        where(G, color, t, i, j);
+        const T *xo = x + (long)(color ^ 1) * NC * G.plane;
+        T v[NF][NC], xi[NC], bv[NC];
+        bool ok[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            int ni, nj;
+            face(G, i, j, f, ni, nj, ok[f]);
+            if (MODE != MODE_ZERO) {
+                if (ok[f]) {
+                    read_other<T, NC, MODE>(G, xo, ni, nj, Gc, xc, v[f]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) v[f][c] = T(0);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NC; ++r) bv[r] = b[((long)color * NC + r) * G.plane + t];
+        gs_update<T, NC, MODE == MODE_ZERO, false>(a, nullptr, bv, v, ok, xi);
+        T *xm = x + (long)color * NC * G.plane + t;
+#pragma unroll
+        for (int r = 0; r < NC; ++r) xm[r * G.plane] = xi[r];
+    }
+
+    __device__ __forceinline__ void first(int mode, const LevelGeom &G, const T *b, T *x,
+                                          int color, const LevelGeom &Gc, const T *xc,
+                                          int t) const
+    {
+        switch (mode) {
+        case MODE_NORMAL: update<MODE_NORMAL>(G, b, x, color, Gc, xc, t); break;
+        case MODE_ZERO: update<MODE_ZERO>(G, b, x, color, Gc, xc, t); break;
+        case MODE_PROLONG: update<MODE_PROLONG>(G, b, x, color, Gc, xc, t); break;
+        default: update<MODE_PROLONG_ZERO>(G, b, x, color, Gc, xc, t); break;
+        }
+    }
+
+    // Linear residual of this cell into rs (colour-split like x): the
+    // arithmetic of lin_residual_cell.
+    __device__ __forceinline__ void residual(const LevelGeom &G, const T *b, const T *x,
+                                             int color, int t, T *rs) const
+    {
+        if (!mine) return;
+        int i, j;
+        where(G, color, t, i, j);
+        const T *xm = x + (long)color * NC * G.plane + t;
+        const T *xo = x + (long)(color ^ 1) * NC * G.plane;
+        T xi[NC], acc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xi[c] = xm[c * G.plane];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            acc[q] = T(0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[q] = acc[q] + a[q * NC + c] * xi[c];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            int ni, nj;
+            bool ok;
+            face(G, i, j, f, ni, nj, ok);
+            if (!ok) continue;
+            const T *p = xo + (long)nj * G.W + (ni >> 1);
+            T v[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[c] = p[c * G.plane];
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[q] = acc[q] + a[((f + 1) * NC + q) * NC + c] * v[c];
+        }
+#pragma unroll
+        for (int q = 0; q < NC; ++q)
+            rs[((long)color * NC + q) * G.plane + t] = b[((long)color * NC + q) * G.plane + t] - acc[q];
+    }
+};
+
+// COP_REGRUN: op.count alternating half sweeps on a level in global memory
+// with at most one slot per colour and thread (the first in op.mode, the
+// rest normal), each thread holding the block rows of its red and its black
+// cell in registers, so the level's blocks are read once per run instead of
+// once per half sweep; then, if op.aux, the restriction to the next level
+// (restrict_cell's sums in its child order, the children's residuals
+// exchanged through rs in LDS).  x and b stay in global memory; the caller's
+// barrier follows.
+template <class T, int NC>
+__device__ __forceinline__ void coarse_reg_run(const CoarseOp &op, const LevelGeom &G,
+                                               const T *A, const T *b, T *x, const LevelGeom &Gc,
+                                               T *bc, const T *xc, T *rs)
+{
+    const int t = (int)threadIdx.x;
+    RegCell<T, NC> red, black;
+    red.load(G, A, 0, t);
+    black.load(G, A, 1, t);
+    if (op.color == 0) red.first(op.mode, G, b, x, 0, Gc, xc, t);
+    else black.first(op.mode, G, b, x, 1, Gc, xc, t);
+    __syncthreads();
+    for (int s = 1; s < op.count; ++s) {
+        if ((op.color ^ (s & 1)) == 0) red.template update<MODE_NORMAL>(G, b, x, 0, Gc, xc, t);
+        else black.template update<MODE_NORMAL>(G, b, x, 1, Gc, xc, t);
+        __syncthreads();
+    }
+    if (!op.aux) return;
+    red.residual(G, b, x, 0, t, rs);
+    black.residual(G, b, x, 1, t, rs);
+    __syncthreads();
+    const int nch = (NC == 2) ? 2 : 4;
+    for (int u = t; u < Gc.nx * Gc.ny; u += kCoarseBlock) {
+        const int I = u % Gc.nx, J = u / Gc.nx;
+        T acc[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) acc[q] = T(0);
+#pragma unroll
+        for (int ch = 0; ch < nch; ++ch) {
+            const int i = 2 * I + (ch & 1);
+            const int j = (NC == 2) ? 0 : 2 * J + (ch >> 1);
+            const int col = (i + j) & 1;
+            const long slot = (long)j * G.W + (i >> 1);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) acc[q] = acc[q] + rs[((long)col * NC + q) * G.plane + slot];
+        }
+        const int cc = (I + J) & 1;
+        T *bm = bc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) bm[q * Gc.plane] = acc[q];
+    }
+}
+
 // Pointers into a level's LDS copy (layout of LevelDev::lds_off).
 template <class T, int NC>
 struct LdsLevel {
@@ -1076,6 +1253,18 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
         if (op.kind == COP_RUN) {
             const LdsLevel<T, NC> F(lds, Ld);
             coarse_run<T, NC>(op, Ld.G, F.A, F.Ai, F.b, F.x);
+        } else if (op.kind == COP_REGRUN) {
+            T *rs = (T *)(lds + op.lds_off);
+            if (Lc.lds_off >= 0) {
+                const LdsLevel<T, NC> Cl(lds, Lc);
+                coarse_reg_run<T, NC>(op, Ld.G, in_global((const T *)Ld.A),
+                                      in_global((const T *)Ld.b), in_global((T *)Ld.x), Lc.G,
+                                      Cl.b, Cl.x, rs);
+            } else {
+                coarse_reg_run<T, NC>(op, Ld.G, in_global((const T *)Ld.A),
+                                      in_global((const T *)Ld.b), in_global((T *)Ld.x), Lc.G,
+                                      in_global((T *)Lc.b), in_global((const T *)Lc.x), rs);
+            }
         } else if (Ld.lds_off >= 0) {
             const LdsLevel<T, NC> F(lds, Ld), Cl(lds, Lc);
             coarse_op<T, NC, true>(op, Ld.G, Lc.G, F.A, F.Ai, F.b, F.x, Cl.b, Cl.x);

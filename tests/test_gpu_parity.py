@@ -164,6 +164,34 @@ def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, gamma, monkeypatch
     same(host(x), oracle.vcycles(A, b, x0, p, cycles), "x after V-cycles")
 
 
+# Cycles whose first coarse-kernel level (32x32, 32x24; 1024 cells in 1D)
+# lives in global memory with at most one slot per colour and thread: its
+# runs of half sweeps, and the restriction that follows them, execute with
+# the level's block rows in registers (COP_REGRUN); NMG_COARSE_REG=0 runs the
+# same operations one by one.  nu1 = 0 leaves a restriction with no run
+# before it, nu2 = 0 a level whose correction is fixed up at the end.
+REG = [(2, 64, 64, 5, 2), (2, 64, 48, 6, 3), (1, 2048, 1, 7, 2)]
+
+
+@pytest.mark.parametrize("case", REG)
+@pytest.mark.parametrize("nus", [(2, 2, 10), (1, 0, 3), (0, 1, 2)])
+@pytest.mark.parametrize("gamma", [1, 2])
+@pytest.mark.parametrize("reg", ["1", "0"])
+@pytest.mark.parametrize("fp32", [0, 1])
+def test_vcycle_register_runs_bitwise(nmg, case, nus, gamma, reg, fp32, monkeypatch):
+    prob, A, b, x0 = random_case(*case)
+    say("vcycle register runs", case, nus, gamma, reg, fp32)
+    monkeypatch.setenv("NMG_COARSE_CELLS", "1024")
+    monkeypatch.setenv("NMG_COARSE_REG", reg)
+    p = dict(prob.params, nu1=nus[0], nu2=nus[1], nu_coarse=nus[2], gamma=gamma,
+             inner_fp32=fp32)
+    ctx = nmg.Context.from_problem(prob, **p)
+    ctx.load_system(dev(A), dev(b))
+    x = dev(x0)
+    ctx.mg_vcycle(x, 2)
+    same(host(x), oracle.vcycles(A, b, x0, p, 2), "x after cycles")
+
+
 @pytest.mark.parametrize("k", [0, 1, 3, 7, 8, 9])
 def test_blu_sweep_bitwise(nmg, k):
     prob = PROBS[k]
