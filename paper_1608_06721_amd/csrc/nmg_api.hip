@@ -391,8 +391,8 @@ void merge_runs(nmg_ctx *c, bool fits)
 
 // Replace each maximal sequence of alternating half sweeps on the first
 // coarse level lc (the first in any mode, the rest normal), with the
-// restriction from lc when it follows, by one COP_REGRUN whose residual
-// exchange area starts at LDS byte rs_off.  ok: lc lives in global memory,
+// restriction from lc when it follows, by one COP_REGRUN whose x and
+// residual exchange area starts at LDS byte rs_off.  ok: lc lives in global memory,
 // has at most one slot per colour and thread, and the exchange area fits.
 void merge_reg_runs(nmg_ctx *c, bool ok, long rs_off)
 {
@@ -446,7 +446,8 @@ long lds_levels_bytes(const nmg_ctx *c, int l_lds)
     return tot;
 }
 
-// Bytes of the residual exchange area of a register-resident run on level l.
+// Bytes of the LDS area (x, then the residual exchange) of a register-resident
+// run on level l.
 long reg_exchange_bytes(const nmg_ctx *c, int l)
 {
     return 2L * c->nc * c->L[l].G.plane * (c->f32 ? 4 : 8);

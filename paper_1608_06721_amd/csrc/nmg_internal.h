@@ -88,9 +88,10 @@ struct LevelDev {
 // with a thread per cell, the first of them in `mode` (any start mode for
 // COP_REGRUN, normal or zero start for COP_RUN) and the rest normal.
 // COP_REGRUN is the same on a level in global memory with at most one slot
-// per colour and thread, whose block rows stay in registers for the run;
-// aux = 1 appends the restriction to the next level, whose residuals are
-// exchanged through the LDS bytes at lds_off.
+// per colour and thread, whose block rows stay in registers and whose x
+// moves to the LDS bytes at lds_off for the run; aux = 1 appends the
+// restriction to the next level, whose residuals are exchanged through the
+// same LDS bytes.
 enum CoarseOpKind { COP_SGS = 0, COP_RESTRICT = 1, COP_FIX = 2, COP_RUN = 3, COP_REGRUN = 4 };
 struct CoarseOp {
     int kind;               // CoarseOpKind
@@ -99,7 +100,7 @@ struct CoarseOp {
     int mode;               // SGS / RUN / REGRUN: SweepMode; FIX: 0 zero, 1 add parent, 2 set parent
     int count;              // RUN, REGRUN: number of half sweeps
     int aux;                // REGRUN: 1 if the restriction follows
-    int lds_off;            // REGRUN: byte offset of the residual exchange area in LDS
+    int lds_off;            // REGRUN: byte offset of the run's x / exchange area in LDS
 };
 
 inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }

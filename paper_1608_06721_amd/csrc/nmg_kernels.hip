@@ -1005,16 +1005,20 @@ __device__ __forceinline__ void coarse_run(const CoarseOp &op, const LevelGeom &
 }
 
 // One cell of a register-resident run: the cell of colour `color` at slot
-// threadIdx.x of a level in global memory (if it exists) and its block row,
-// loaded once for the whole run.  Its neighbours and right-hand side are
-// recomputed and reloaded where used, which keeps two block rows per thread
-// within the register file.
+// threadIdx.x of a level in global memory (if it exists), its off-diagonal
+// blocks and the inverse data of its diagonal block (block_inverse), loaded
+// once for the whole run.  Its neighbours, right-hand side and (for the
+// residual) diagonal block are recomputed or reloaded where used, which
+// keeps two cells per thread within the register file.
 template <class T, int NC>
 struct RegCell {
     static constexpr int NF = (NC == 2) ? 2 : 4;
-    static constexpr int NE = (NF + 1) * NC * NC;
+    static constexpr int NN = NC * NC;
+    static constexpr int NE = (NF + 1) * NN;
+    static constexpr int NI = inv_entries(NC);
     bool mine;
-    T a[NE];
+    T a[NE];          // a[0, NN) unused; a[NN, NE) the off-diagonal blocks
+    T inv[NI];
 
     __device__ __forceinline__ static void where(const LevelGeom &G, int color, int t, int &i,
                                                  int &j)
@@ -1040,12 +1044,17 @@ struct RegCell {
         mine = t < G.plane && i < G.nx;
         if (mine) {
             const T *Am = A + mat_off(G, NE, color, t);
+            T D[NN];
 #pragma unroll
-            for (int e = 0; e < NE; ++e) a[e] = Am[e * kTile];
+            for (int e = 0; e < NN; ++e) D[e] = Am[e * kTile];
+#pragma unroll
+            for (int e = NN; e < NE; ++e) a[e] = Am[e * kTile];
+            block_inverse<T, NC>(D, inv);
         }
     }
 
-    // Half sweep update of this cell: the arithmetic of sgs_cell.
+    // Half sweep update of this cell: the arithmetic of sgs_cell (solve_inv
+    // with block_inverse's data is solve_block bit for bit).
     template <int MODE>
     __device__ __forceinline__ void update(const LevelGeom &G, const T *b, T *x, int color,
                                            const LevelGeom &Gc, const T *xc, int t) const
@@ -1071,7 +1080,7 @@ struct RegCell {
         }
 #pragma unroll
         for (int r = 0; r < NC; ++r) bv[r] = b[((long)color * NC + r) * G.plane + t];
-        gs_update<T, NC, MODE == MODE_ZERO, false>(a, nullptr, bv, v, ok, xi);
+        gs_update<T, NC, MODE == MODE_ZERO, true>(a, inv, bv, v, ok, xi);
         T *xm = x + (long)color * NC * G.plane + t;
 #pragma unroll
         for (int r = 0; r < NC; ++r) xm[r * G.plane] = xi[r];
@@ -1089,14 +1098,14 @@ struct RegCell {
         }
     }
 
-    // Linear residual of this cell into rs (colour-split like x): the
-    // arithmetic of lin_residual_cell.
-    __device__ __forceinline__ void residual(const LevelGeom &G, const T *b, const T *x,
-                                             int color, int t, T *rs) const
+    // Linear residual r of this cell: the arithmetic of lin_residual_cell,
+    // with the diagonal block reloaded from A.
+    __device__ __forceinline__ void residual(const LevelGeom &G, const T *A, const T *b,
+                                             const T *x, int color, int t, T *r) const
     {
-        if (!mine) return;
         int i, j;
         where(G, color, t, i, j);
+        const T *Am = A + mat_off(G, NE, color, t);
         const T *xm = x + (long)color * NC * G.plane + t;
         const T *xo = x + (long)(color ^ 1) * NC * G.plane;
         T xi[NC], acc[NC];
@@ -1106,7 +1115,7 @@ struct RegCell {
         for (int q = 0; q < NC; ++q) {
             acc[q] = T(0);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[q] = acc[q] + a[q * NC + c] * xi[c];
+            for (int c = 0; c < NC; ++c) acc[q] = acc[q] + Am[(q * NC + c) * kTile] * xi[c];
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -1125,8 +1134,7 @@ struct RegCell {
                     acc[q] = acc[q] + a[((f + 1) * NC + q) * NC + c] * v[c];
         }
 #pragma unroll
-        for (int q = 0; q < NC; ++q)
-            rs[((long)color * NC + q) * G.plane + t] = b[((long)color * NC + q) * G.plane + t] - acc[q];
+        for (int q = 0; q < NC; ++q) r[q] = b[((long)color * NC + q) * G.plane + t] - acc[q];
     }
 };
 
@@ -1134,30 +1142,45 @@ struct RegCell {
 // with at most one slot per colour and thread (the first in op.mode, the
 // rest normal), each thread holding the block rows of its red and its black
 // cell in registers, so the level's blocks are read once per run instead of
-// once per half sweep; then, if op.aux, the restriction to the next level
-// (restrict_cell's sums in its child order, the children's residuals
-// exchanged through rs in LDS).  x and b stay in global memory; the caller's
-// barrier follows.
+// once per half sweep.  x moves to the LDS area xl (2 NC plane values) for
+// the run and back afterwards.  Then, if op.aux, the restriction to the next
+// level: restrict_cell's sums in its child order, the children's residuals
+// exchanged through the same LDS area.  The caller's barrier follows.
 template <class T, int NC>
 __device__ __forceinline__ void coarse_reg_run(const CoarseOp &op, const LevelGeom &G,
                                                const T *A, const T *b, T *x, const LevelGeom &Gc,
-                                               T *bc, const T *xc, T *rs)
+                                               T *bc, const T *xc, T *xl)
 {
     const int t = (int)threadIdx.x;
+    const int nv = 2 * NC * (int)G.plane;
+    for (int k = t; k < nv; k += kCoarseBlock) xl[k] = x[k];
     RegCell<T, NC> red, black;
     red.load(G, A, 0, t);
     black.load(G, A, 1, t);
-    if (op.color == 0) red.first(op.mode, G, b, x, 0, Gc, xc, t);
-    else black.first(op.mode, G, b, x, 1, Gc, xc, t);
+    __syncthreads();
+    if (op.color == 0) red.first(op.mode, G, b, xl, 0, Gc, xc, t);
+    else black.first(op.mode, G, b, xl, 1, Gc, xc, t);
     __syncthreads();
     for (int s = 1; s < op.count; ++s) {
-        if ((op.color ^ (s & 1)) == 0) red.template update<MODE_NORMAL>(G, b, x, 0, Gc, xc, t);
-        else black.template update<MODE_NORMAL>(G, b, x, 1, Gc, xc, t);
+        if ((op.color ^ (s & 1)) == 0) red.template update<MODE_NORMAL>(G, b, xl, 0, Gc, xc, t);
+        else black.template update<MODE_NORMAL>(G, b, xl, 1, Gc, xc, t);
         __syncthreads();
     }
+    T rr[NC], rb[NC];
+    if (op.aux) {
+        if (red.mine) red.residual(G, A, b, xl, 0, t, rr);
+        if (black.mine) black.residual(G, A, b, xl, 1, t, rb);
+    }
+    for (int k = t; k < nv; k += kCoarseBlock) x[k] = xl[k];
     if (!op.aux) return;
-    red.residual(G, b, x, 0, t, rs);
-    black.residual(G, b, x, 1, t, rs);
+    __syncthreads();
+    T *rs = xl;
+    const int plane = (int)G.plane;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        if (red.mine) rs[q * plane + t] = rr[q];
+        if (black.mine) rs[(NC + q) * plane + t] = rb[q];
+    }
     __syncthreads();
     const int nch = (NC == 2) ? 2 : 4;
     for (int u = t; u < Gc.nx * Gc.ny; u += kCoarseBlock) {
@@ -1170,9 +1193,9 @@ __device__ __forceinline__ void coarse_reg_run(const CoarseOp &op, const LevelGe
             const int i = 2 * I + (ch & 1);
             const int j = (NC == 2) ? 0 : 2 * J + (ch >> 1);
             const int col = (i + j) & 1;
-            const long slot = (long)j * G.W + (i >> 1);
+            const int slot = j * G.W + (i >> 1);
 #pragma unroll
-            for (int q = 0; q < NC; ++q) acc[q] = acc[q] + rs[((long)col * NC + q) * G.plane + slot];
+            for (int q = 0; q < NC; ++q) acc[q] = acc[q] + rs[(col * NC + q) * plane + slot];
         }
         const int cc = (I + J) & 1;
         T *bm = bc + (long)cc * NC * Gc.plane + (long)J * Gc.W + (I >> 1);
@@ -1254,16 +1277,16 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
             const LdsLevel<T, NC> F(lds, Ld);
             coarse_run<T, NC>(op, Ld.G, F.A, F.Ai, F.b, F.x);
         } else if (op.kind == COP_REGRUN) {
-            T *rs = (T *)(lds + op.lds_off);
+            T *xl = (T *)(lds + op.lds_off);
             if (Lc.lds_off >= 0) {
                 const LdsLevel<T, NC> Cl(lds, Lc);
                 coarse_reg_run<T, NC>(op, Ld.G, in_global((const T *)Ld.A),
                                       in_global((const T *)Ld.b), in_global((T *)Ld.x), Lc.G,
-                                      Cl.b, Cl.x, rs);
+                                      Cl.b, Cl.x, xl);
             } else {
                 coarse_reg_run<T, NC>(op, Ld.G, in_global((const T *)Ld.A),
                                       in_global((const T *)Ld.b), in_global((T *)Ld.x), Lc.G,
-                                      in_global((T *)Lc.b), in_global((const T *)Lc.x), rs);
+                                      in_global((T *)Lc.b), in_global((const T *)Lc.x), xl);
             }
         } else if (Ld.lds_off >= 0) {
             const LdsLevel<T, NC> F(lds, Ld), Cl(lds, Lc);
