@@ -31,6 +31,7 @@ enum ColorState {
 struct Level {
     LevelGeom G;
     void *A = nullptr, *b = nullptr, *x = nullptr;   // double, or float (FP32 inner)
+    void *xt = nullptr;     // one colour's planes: the other buffer of fused half-sweep pairs
     int st[2] = {ST_ZERO, ST_ZERO};
     int last = -1;      // colour of the last half sweep if nothing changed since, else -1
 };
@@ -47,6 +48,7 @@ struct nmg_ctx {
     Phys P;
     int dim = 0, nc = 0, nb = 0, ne = 0, NL = 0;
     bool f32 = false;                 // FP32 inner V-cycle
+    bool pairs = true;                // fused half-sweep pairs on launched coarse levels
     Level L[16];
     void *pool = nullptr;             // the hierarchy's allocation
     void *At_alloc = nullptr;         // second level-0 matrix (adjoint transpose), owned
@@ -232,7 +234,77 @@ int halfsweep(nmg_ctx *c, int l, int color)
     return NMG_OK;
 }
 
+int smooth_single(nmg_ctx *c, int l, int iters);
+
+// Whether the half sweeps of level l are launched as fused pairs: 2D levels
+// below the finest that are launched level by level (the finest level is
+// bandwidth-bound and keeps its timed single half sweeps).
+bool fuse_pairs(const nmg_ctx *c, int l)
+{
+    if (c->recording || c->batch || c->dim != 2 || l == 0) return false;
+    if (c->lc >= 0 && l >= c->lc) return false;
+    return c->pairs;
+}
+
+int sweep_mode(int st_other)
+{
+    switch (st_other) {
+    case ST_VALID: return MODE_NORMAL;
+    case ST_ZERO: return MODE_ZERO;
+    case ST_VALID_PP: return MODE_PROLONG;
+    default: return MODE_PROLONG_ZERO;
+    }
+}
+
+// The half sweeps of `iters` symmetric iterations on level l (colour order
+// 0, 1, 1, 0, a repeat of the last colour elided) with consecutive pairs
+// fused into one launch each.  An even number of pairs is fused, so that the
+// second colour, which alternates between x and the level's xt, ends in x;
+// the remaining half sweeps are launched one by one.
+int smooth_pairs(nmg_ctx *c, int l, int iters)
+{
+    Level &Lv = c->L[l];
+    const Level &Lc = c->L[l + 1 <= c->NL ? l + 1 : l];
+    int col[64], mode[64], k = 0;
+    int st[2] = {Lv.st[0], Lv.st[1]}, last = Lv.last;
+    const int order[4] = {0, 1, 1, 0};
+    for (int it = 0; it < iters; ++it)
+        for (int q = 0; q < 4; ++q) {
+            const int cl = order[q];
+            if (cl == last) continue;
+            if (k == 64) return smooth_single(c, l, iters);
+            col[k] = cl;
+            mode[k] = sweep_mode(st[cl ^ 1]);
+            st[cl] = ST_VALID;
+            last = cl;
+            ++k;
+        }
+    const int npairs = 2 * (k / 4);
+    const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
+    for (int p = 0; p < npairs; ++p) {
+        const int c1 = col[2 * p], c2 = c1 ^ 1;
+        char *xc2 = (char *)Lv.x + (size_t)c2 * c->nc * Lv.G.plane * esz;
+        const void *xin = (p & 1) ? Lv.xt : xc2;
+        void *xout = (p & 1) ? (void *)xc2 : Lv.xt;
+        HIPCHK(c, launch_sgs_pair(c->f32, mode[2 * p], Lv.G, Lv.A, Lv.b, Lv.x, xin, xout, c1,
+                                  Lc.G, Lc.x, c->stream));
+        Lv.st[c1] = Lv.st[c2] = ST_VALID;
+        Lv.last = c2;
+    }
+    for (int q = 2 * npairs; q < k; ++q) {
+        int rc = halfsweep(c, l, col[q]);
+        if (rc) return rc;
+    }
+    return NMG_OK;
+}
+
 int smooth(nmg_ctx *c, int l, int iters)
+{
+    if (fuse_pairs(c, l)) return smooth_pairs(c, l, iters);
+    return smooth_single(c, l, iters);
+}
+
+int smooth_single(nmg_ctx *c, int l, int iters)
 {
     c->tgroup = -1;               // timed runs never span other launches
     for (int it = 0; it < iters; ++it) {
@@ -876,12 +948,14 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     }
 
     c->f32 = params->inner_fp32 != 0;
+    if (const char *e = std::getenv("NMG_PAIRS")) c->pairs = std::atoi(e) != 0;
     const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
     size_t total = 0;   // elements
     for (int l = 0; l <= c->NL; ++l) {
         int nx = grid->nx >> l, ny = grid->dim == 1 ? 1 : grid->ny >> l;
         c->L[l].G = make_geom(nx, ny);
-        total += (size_t)2 * c->ne * c->L[l].G.planeP + (size_t)2 * 2 * c->nc * c->L[l].G.plane;
+        total += (size_t)2 * c->ne * c->L[l].G.planeP + (size_t)2 * 2 * c->nc * c->L[l].G.plane +
+                 (size_t)c->nc * c->L[l].G.plane;
     }
     char *pool = nullptr;
     if (hipMalloc(&pool, total * esz) != hipSuccess) {
@@ -895,6 +969,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
         Lv.A = pool + off * esz; off += (size_t)2 * c->ne * Lv.G.planeP;
         Lv.b = pool + off * esz; off += (size_t)2 * c->nc * Lv.G.plane;
         Lv.x = pool + off * esz; off += (size_t)2 * c->nc * Lv.G.plane;
+        Lv.xt = pool + off * esz; off += (size_t)c->nc * Lv.G.plane;
     }
     long N = cells(c->L[0].G);
     int nparts = nblocks(N);

@@ -139,6 +139,12 @@ hipError_t launch_sgs_half(int dim, bool f32, int mode, const LevelGeom &G, cons
 hipError_t launch_restrict(int dim, bool f32, const LevelGeom &G, const void *A, const void *b,
                            const void *x, const LevelGeom &Gc, void *bc, bool stream,
                            hipStream_t s);
+// Two consecutive half sweeps (colour `color` in `mode`, then the other colour
+// in normal mode) in one launch, 2D only: colour `color` is updated in x, the
+// other colour is read from xin (NC planes) and written to xout (NC planes).
+hipError_t launch_sgs_pair(bool f32, int mode, const LevelGeom &G, const void *A, const void *b,
+                           void *x, const void *xin, void *xout, int color, const LevelGeom &Gc,
+                           const void *xc, hipStream_t s);
 hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *Af,
                            const LevelGeom &Gc, void *Ac, hipStream_t s);
 // Materialize one colour of x: op 0 = set zero, 1 = add the parent's

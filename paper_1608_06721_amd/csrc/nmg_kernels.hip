@@ -1313,6 +1313,129 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
     }
 }
 
+// Two consecutive half sweeps of the red-black block Gauss-Seidel smoother
+// in one launch, on tiles of kPairTX x kPairTY cells.  Phase 1: colour c in
+// MODE for the tile's colour-c cells (one per thread of the first
+// kPairCells) and, redundantly, for the kPairRing colour-c cells that border
+// the tile (the neighbours of its colour-c^1 cells; one per further thread),
+// all kept in LDS; the tile's own go to x.  Phase 2: colour c^1 (normal
+// mode) for the tile's cells, reading colour c from LDS; each thread's block
+// row is loaded before phase 1 so both phases' loads are in flight together.
+// Colour c^1's old values come from xin and its new values go to xout (two
+// different buffers: other tiles may still read the old values).  Every
+// cell update is sgs_cell's arithmetic on the same inputs, so the result is
+// bit for bit that of the two half sweeps launched one by one.
+constexpr int kPairTX = 32, kPairTY = 16;
+constexpr int kPairCells = kPairTX / 2 * kPairTY;        // cells of one colour per tile
+constexpr int kPairRing = kPairTX + kPairTY;             // colour-c cells bordering a tile
+constexpr int kPairThreads = (kPairCells + kPairRing + 63) / 64 * 64;
+
+template <class T, int NC, int MODE>
+__global__ void __launch_bounds__(kPairThreads) k_sgs_pair(LevelGeom G, const T *__restrict__ A,
+                                                           const T *__restrict__ b,
+                                                           T *__restrict__ x,
+                                                           const T *__restrict__ xin,
+                                                           T *__restrict__ xout, int color,
+                                                           LevelGeom Gc, const T *__restrict__ xc,
+                                                           int ntx)
+{
+    constexpr int NF = 4;
+    constexpr int NN = NC * NC;
+    constexpr int NE = (NF + 1) * NN;
+    constexpr int LX = kPairTX + 2, LY = kPairTY + 2;
+    __shared__ T lx[NC][LY][LX];
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int i0 = (tile % ntx) * kPairTX, j0 = (tile / ntx) * kPairTY;   // both even
+    const int tid = (int)threadIdx.x;
+    const int c1 = color, c2 = color ^ 1;
+
+    // phase 2 cell of this thread and its block row, loaded first
+    const bool tile_thread = tid < kPairCells;
+    const int j2 = j0 + tid / (kPairTX / 2);
+    const int i2 = i0 + 2 * (tid % (kPairTX / 2)) + ((j2 + c2) & 1);
+    const bool own2 = tile_thread && i2 < G.nx && j2 < G.ny;
+    const long t2 = (long)j2 * G.W + (i2 >> 1);
+    T a2[NE], bv2[NC];
+    if (own2) {
+        const T *Am = A + mat_off(G, NE, c2, t2);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) a2[e] = Am[e * kTile];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) bv2[r] = b[((long)c2 * NC + r) * G.plane + t2];
+    }
+
+    // phase 1 cell of this thread: a tile cell of colour c, or a bordering one
+    int i, j;
+    if (tile_thread) {
+        j = j0 + tid / (kPairTX / 2);
+        i = i0 + 2 * (tid % (kPairTX / 2)) + ((j + c1) & 1);
+    } else {
+        const int v = tid - kPairCells, h = kPairTY / 2;
+        if (v < h) { i = i0 - 1; j = j0 + 2 * v + (c1 ^ 1); }                 // left
+        else if (v < 2 * h) { i = i0 + kPairTX; j = j0 + 2 * (v - h) + c1; }  // right
+        else if (v < 2 * h + kPairTX / 2) { i = i0 + 2 * (v - 2 * h) + (c1 ^ 1); j = j0 - 1; }
+        else { i = i0 + 2 * (v - 2 * h - kPairTX / 2) + c1; j = j0 + kPairTY; }  // top
+    }
+    const bool own1 = tid < kPairCells + kPairRing && i >= 0 && i < G.nx && j >= 0 && j < G.ny;
+    if (own1) {
+        const long t = (long)j * G.W + (i >> 1);
+        const T *Am = A + mat_off(G, NE, c1, t);
+        T a[NE], bv[NC], v[NF][NC], xi[NC];
+        bool ok[NF];
+#pragma unroll
+        for (int e = 0; e < (MODE == MODE_ZERO ? NN : NE); ++e) a[e] = Am[e * kTile];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) bv[r] = b[((long)c1 * NC + r) * G.plane + t];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            int ni = i, nj = j;
+            if (f == FW) { ni = i - 1; ok[f] = i > 0; }
+            else if (f == FE) { ni = i + 1; ok[f] = i + 1 < G.nx; }
+            else if (f == FS) { nj = j - 1; ok[f] = j > 0; }
+            else { nj = j + 1; ok[f] = j + 1 < G.ny; }
+            if (MODE != MODE_ZERO) {
+                if (ok[f]) {
+                    read_other<T, NC, MODE>(G, xin, ni, nj, Gc, xc, v[f]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NC; ++q) v[f][q] = T(0);
+                }
+            }
+        }
+        gs_update<T, NC, MODE == MODE_ZERO, false>(a, nullptr, bv, v, ok, xi);
+#pragma unroll
+        for (int r = 0; r < NC; ++r) lx[r][j - j0 + 1][i - i0 + 1] = xi[r];
+        if (tile_thread) {
+            T *xm = x + (long)c1 * NC * G.plane + t;
+#pragma unroll
+            for (int r = 0; r < NC; ++r) xm[r * G.plane] = xi[r];
+        }
+    }
+    __syncthreads();
+
+    // phase 2: the tile's colour-c^1 cells, colour c from LDS
+    if (!own2) return;
+    T v[NF][NC], xi[NC];
+    bool ok[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        int ni = i2, nj = j2;
+        if (f == FW) { ni = i2 - 1; ok[f] = i2 > 0; }
+        else if (f == FE) { ni = i2 + 1; ok[f] = i2 + 1 < G.nx; }
+        else if (f == FS) { nj = j2 - 1; ok[f] = j2 > 0; }
+        else { nj = j2 + 1; ok[f] = j2 + 1 < G.ny; }
+        const int li = ok[f] ? ni - i0 + 1 : 1, lj = ok[f] ? nj - j0 + 1 : 1;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const T val = lx[q][lj][li];
+            v[f][q] = ok[f] ? val : T(0);
+        }
+    }
+    gs_update<T, NC, false, false>(a2, nullptr, bv2, v, ok, xi);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) xout[r * G.plane + t2] = xi[r];
+}
+
 // Layout conversions between the public FP64 layouts and the hierarchy's
 // colour-split storage of precision T.
 template <class T>
@@ -1994,6 +2117,41 @@ hipError_t launch_sgs_half(int dim, bool f32, int mode, const LevelGeom &G, cons
     }
     if (dim == 1) return sgs_stream<double, 2>(stream, mode, G, A, b, x, color, Gc, xc, s);
     return sgs_stream<double, 3>(stream, mode, G, A, b, x, color, Gc, xc, s);
+}
+
+template <class T>
+static hipError_t pair_dispatch(int mode, const LevelGeom &G, const T *A, const T *b, T *x,
+                                const T *xin, T *xout, int color, const LevelGeom &Gc, const T *xc,
+                                hipStream_t s)
+{
+    const int ntx = (G.nx + kPairTX - 1) / kPairTX, nty = (G.ny + kPairTY - 1) / kPairTY;
+    const int g = ntx * nty;
+#define NMG_PAIR(M)                                                                           \
+    do {                                                                                      \
+        hipLaunchKernelGGL((k_sgs_pair<T, 3, M>), dim3(g), dim3(kPairThreads), 0, s, G, A, b, \
+                           x, xin, xout, color, Gc, xc, ntx);                                 \
+        return hipGetLastError();                                                             \
+    } while (0)
+    switch (mode) {
+    case MODE_NORMAL: NMG_PAIR(MODE_NORMAL);
+    case MODE_ZERO: NMG_PAIR(MODE_ZERO);
+    case MODE_PROLONG: NMG_PAIR(MODE_PROLONG);
+    default: NMG_PAIR(MODE_PROLONG_ZERO);
+    }
+#undef NMG_PAIR
+}
+
+hipError_t launch_sgs_pair(bool f32, int mode, const LevelGeom &G, const void *A, const void *b,
+                           void *x, const void *xin, void *xout, int color, const LevelGeom &Gc,
+                           const void *xc, hipStream_t s)
+{
+    if (f32)
+        return pair_dispatch<float>(mode, G, (const float *)A, (const float *)b, (float *)x,
+                                    (const float *)xin, (float *)xout, color, Gc,
+                                    (const float *)xc, s);
+    return pair_dispatch<double>(mode, G, (const double *)A, (const double *)b, (double *)x,
+                                 (const double *)xin, (double *)xout, color, Gc,
+                                 (const double *)xc, s);
 }
 
 template <class T, int NC>

@@ -130,6 +130,9 @@ def random_case(dim, nx, ny, seed, nl):
 
 
 LIN = [(1, 32, 1, 1, 3), (2, 16, 12, 2, 2), (2, 24, 16, 3, 3), (2, 8, 8, 4, 1)]
+# levels spanning several 32x16 tiles of the fused half-sweep pairs, ragged in
+# both directions, with odd coarse dimensions
+TILED = [(2, 160, 72, 8, 2), (2, 96, 40, 9, 3)]
 
 
 @pytest.mark.parametrize("case", LIN)
@@ -144,18 +147,21 @@ def test_sgs_bitwise(nmg, case, iters):
     same(host(x), oracle.sgs(A, b, x0, iters, order=W.REDBLACK), "x after SGS")
 
 
-@pytest.mark.parametrize("case", LIN)
+@pytest.mark.parametrize("case", LIN + TILED)
 @pytest.mark.parametrize("nus", [(2, 2, 10), (1, 0, 3), (0, 1, 2), (0, 0, 1), (3, 1, 0)])
 @pytest.mark.parametrize("cycles", [1, 3])
 @pytest.mark.parametrize("coarse_cells", ["4096", "0"])
 @pytest.mark.parametrize("gamma", [1, 2])
-def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, gamma, monkeypatch):
+@pytest.mark.parametrize("pairs", ["1", "0"])
+def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, gamma, pairs, monkeypatch):
     """coarse_cells: levels up to this many cells run in the single-workgroup
     coarse-cycle kernel ("0": every level launched on its own); gamma = 2 is
-    the W-cycle."""
+    the W-cycle; pairs = "0" launches every half sweep on its own instead of
+    fusing consecutive pairs on the launched coarse levels."""
     prob, A, b, x0 = random_case(*case)
-    say("vcycle", case, nus, cycles, coarse_cells, gamma)
+    say("vcycle", case, nus, cycles, coarse_cells, gamma, pairs)
     monkeypatch.setenv("NMG_COARSE_CELLS", coarse_cells)
+    monkeypatch.setenv("NMG_PAIRS", pairs)
     p = dict(prob.params, nu1=nus[0], nu2=nus[1], nu_coarse=nus[2], gamma=gamma)
     ctx = nmg.Context.from_problem(prob, **p)
     ctx.load_system(dev(A), dev(b))
@@ -302,7 +308,7 @@ def test_full_size_assembly_and_cycle(nmg):
 
 # --- FP32 inner V-cycle (hierarchy and smoother in FP32, Newton in FP64) ---
 
-@pytest.mark.parametrize("case", LIN)
+@pytest.mark.parametrize("case", LIN + TILED)
 @pytest.mark.parametrize("nus", [(2, 2, 10), (1, 0, 3)])
 @pytest.mark.parametrize("coarse_cells", ["256", "0"])
 def test_vcycle_fp32_bitwise(nmg, case, nus, coarse_cells, monkeypatch):
