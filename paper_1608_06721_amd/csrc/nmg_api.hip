@@ -958,7 +958,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
         int nx = grid->nx >> l, ny = grid->dim == 1 ? 1 : grid->ny >> l;
         c->L[l].G = make_geom(nx, ny);
         total += (size_t)2 * c->ne * c->L[l].G.planeP + (size_t)2 * 2 * c->nc * c->L[l].G.plane +
-                 (size_t)c->nc * c->L[l].G.plane;
+                 (l > 0 ? (size_t)c->nc * c->L[l].G.plane : 0);
     }
     char *pool = nullptr;
     if (hipMalloc(&pool, total * esz) != hipSuccess) {
@@ -972,7 +972,10 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
         Lv.A = pool + off * esz; off += (size_t)2 * c->ne * Lv.G.planeP;
         Lv.b = pool + off * esz; off += (size_t)2 * c->nc * Lv.G.plane;
         Lv.x = pool + off * esz; off += (size_t)2 * c->nc * Lv.G.plane;
-        Lv.xt = pool + off * esz; off += (size_t)c->nc * Lv.G.plane;
+        if (l > 0) {      // fused pairs never run on the finest level
+            Lv.xt = pool + off * esz;
+            off += (size_t)c->nc * Lv.G.plane;
+        }
     }
     long N = cells(c->L[0].G);
     int nparts = nblocks(N);
