@@ -78,7 +78,7 @@ struct nmg_ctx {
     int lc = -1;
     bool recording = false;
     std::vector<CoarseOp> rec;
-    int prog_off[2] = {0, 0}, prog_len[2] = {0, 0};   // [0]: zero start, [1]: valid start
+    int prog_off[2] = {0, 0}, prog_len[2] = {0, 0};   // [0]: the coarse program, [1]: unused
     int l_lds = -1;                   // levels l_lds..NL run from LDS in the coarse kernel
     CoarseOp *d_ops = nullptr;
     LevelDev *d_lv = nullptr;
@@ -359,28 +359,6 @@ int cycle(nmg_ctx *c, int l)
 {
     const nmg_params &p = c->prm;
     int rc;
-    if (l == c->lc && !c->recording) {
-        // The whole sub-cycle from level lc down runs in one workgroup and
-        // leaves level lc's correction materialized.  Program 0 starts from a
-        // zero correction, program 1 from stored values (the later calls of a
-        // W-cycle).
-        int st0 = c->L[l].st[0], st1 = c->L[l].st[1];
-        int prog = (st0 == ST_ZERO && st1 == ST_ZERO) ? 0
-                   : (st0 == ST_VALID && st1 == ST_VALID) ? 1 : -1;
-        if (prog >= 0 && c->prog_len[prog] > 0) {
-            if (c->batch)
-                HIPCHK(c, launch_b_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[prog],
-                                                c->prog_len[prog], c->batch->d_clv, c->batch->n,
-                                                c->batch->d_active, c->l_lds, c->NL, c->stream));
-            else
-                HIPCHK(c, launch_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[prog],
-                                              c->prog_len[prog], c->d_lv, c->l_lds, c->NL,
-                                              c->stream));
-            c->L[l].st[0] = c->L[l].st[1] = ST_VALID;
-            c->L[l].last = -1;
-            return NMG_OK;
-        }
-    }
     if ((rc = smooth(c, l, p.nu1))) return rc;
     if (l == c->NL) {
         if ((rc = smooth(c, l, p.nu_coarse))) return rc;
@@ -398,12 +376,28 @@ int cycle(nmg_ctx *c, int l)
                                       stream_level(cells(Lv.G), c->nc, c->f32 ? 4 : 8),
                                       c->stream));
         set_zero(c, l + 1);
-        // gamma coarse cycles (gamma = 1: V, 2: W), one when leaving the
-        // finest level (Algorithm 0)
-        const int calls = (l == 0) ? 1 : p.gamma;
-        for (int g = 0; g < calls; ++g)
-            if ((rc = cycle(c, l + 1))) return rc;
-        if ((rc = materialize(c, l + 1))) return rc;
+        if (l + 1 == c->lc && !c->recording && c->prog_len[0] > 0) {
+            // The coarse calls below, from level lc down, run in one
+            // workgroup (the program recorded by record_coarse) and leave
+            // level lc's correction materialized.
+            if (c->batch)
+                HIPCHK(c, launch_b_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[0],
+                                                c->prog_len[0], c->batch->d_clv, c->batch->n,
+                                                c->batch->d_active, c->l_lds, c->NL, c->stream));
+            else
+                HIPCHK(c, launch_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[0],
+                                              c->prog_len[0], c->d_lv, c->l_lds, c->NL,
+                                              c->stream));
+            Lc.st[0] = Lc.st[1] = ST_VALID;
+            Lc.last = -1;
+        } else {
+            // gamma coarse cycles (gamma = 1: V, 2: W), one when leaving the
+            // finest level (Algorithm 0)
+            const int calls = (l == 0) ? 1 : p.gamma;
+            for (int g = 0; g < calls; ++g)
+                if ((rc = cycle(c, l + 1))) return rc;
+            if ((rc = materialize(c, l + 1))) return rc;
+        }
         for (int color = 0; color < 2; ++color)
             Lv.st[color] = (Lv.st[color] == ST_ZERO) ? ST_ZERO_PP : ST_VALID_PP;
         Lv.last = -1;
@@ -591,16 +585,21 @@ int record_coarse(nmg_ctx *c, bool fits, bool reg_ok, long rs_off)
     for (int l = 0; l <= c->NL; ++l) saved[l] = c->L[l];
     c->rec.clear();
     int rc = NMG_OK;
-    for (int prog = 0; prog < 2 && !rc; ++prog) {
-        c->prog_off[prog] = (int)c->rec.size();
-        c->recording = true;
-        set_zero(c, c->lc);
-        if (prog == 1) c->L[c->lc].st[0] = c->L[c->lc].st[1] = ST_VALID;
-        rc = cycle(c, c->lc);
-        if (!rc) rc = materialize(c, c->lc);
-        c->recording = false;
-        c->prog_len[prog] = (int)c->rec.size() - c->prog_off[prog];
-    }
+    // The program: all consecutive calls of cycle(lc) that cycle(lc - 1)
+    // makes (gamma of them, one when lc - 1 is the finest level), from a
+    // zero correction, then level lc's correction materialized.  Runs of half
+    // sweeps continue across the calls (the repeated colour at the junction
+    // is elided as in the level-by-level launches).
+    c->prog_off[0] = 0;
+    c->recording = true;
+    set_zero(c, c->lc);
+    const int calls = (c->lc == 1) ? 1 : c->prm.gamma;
+    for (int g = 0; g < calls && !rc; ++g) rc = cycle(c, c->lc);
+    if (!rc) rc = materialize(c, c->lc);
+    c->recording = false;
+    c->prog_len[0] = (int)c->rec.size();
+    c->prog_off[1] = c->prog_len[0];
+    c->prog_len[1] = 0;
     for (int l = 0; l <= c->NL; ++l) c->L[l] = saved[l];
     if (rc) return rc;
     if (c->prog_len[0] > kMaxCoarseOps || c->prog_len[1] > kMaxCoarseOps) {
