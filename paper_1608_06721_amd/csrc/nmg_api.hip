@@ -48,7 +48,7 @@ struct nmg_ctx {
     Phys P;
     int dim = 0, nc = 0, nb = 0, ne = 0, NL = 0;
     bool f32 = false;                 // FP32 inner V-cycle
-    bool pairs = true;                // fused half-sweep pairs on launched coarse levels
+    int fuse = 3;                     // most half sweeps per launch on launched coarse levels
     Level L[16];
     void *pool = nullptr;             // the hierarchy's allocation
     void *At_alloc = nullptr;         // second level-0 matrix (adjoint transpose), owned
@@ -241,12 +241,16 @@ int smooth_single(nmg_ctx *c, int l, int iters);
 // than bandwidth (measured: a pair takes 6.7-8.0 us against 2 x 4.6-4.8 us
 // up to 256x256, 21.5 us against 2 x 10.3 us at 512x512).
 constexpr long kPairMaxCells = 1L << 17;
+// Triples replace a pair and a single launch only on the smallest launched
+// levels (measured: 9.4 us against 6.5 + 4.5 us at 64x64, 11.8 against
+// 7.0 + 4.7 us at 128x128, 13.5 against 8.0 + 4.8 us at 256x256).
+constexpr long kTripleMaxCells = 1L << 12;
 bool fuse_pairs(const nmg_ctx *c, int l)
 {
     if (c->recording || c->batch || c->dim != 2 || l == 0) return false;
     if (c->lc >= 0 && l >= c->lc) return false;
     if (cells(c->L[l].G) > kPairMaxCells) return false;
-    return c->pairs;
+    return c->fuse >= 2;
 }
 
 int sweep_mode(int st_other)
@@ -260,43 +264,66 @@ int sweep_mode(int st_other)
 }
 
 // The half sweeps of `iters` symmetric iterations on level l (colour order
-// 0, 1, 1, 0, a repeat of the last colour elided) with consecutive pairs
-// fused into one launch each.  An even number of pairs is fused, so that the
-// second colour, which alternates between x and the level's xt, ends in x;
-// the remaining half sweeps are launched one by one.
+// 0, 1, 1, 0, a repeat of the last colour elided), fused into launches of two
+// or three consecutive half sweeps.  Fused launches come in groups of two
+// (pair + pair or pair + triple) that start on the same colour: the first
+// reads the second colour from x and writes it to the level's xt, the second
+// reads it from xt and writes it back to x, so the values end in x.  The
+// rest are launched one by one; the plan uses the fewest launches.
 int smooth_pairs(nmg_ctx *c, int l, int iters)
 {
     Level &Lv = c->L[l];
     const Level &Lc = c->L[l + 1 <= c->NL ? l + 1 : l];
-    int col[64], mode[64], k = 0;
+    constexpr int kMax = 64;
+    int col[kMax], mode[kMax], k = 0;
     int st[2] = {Lv.st[0], Lv.st[1]}, last = Lv.last;
     const int order[4] = {0, 1, 1, 0};
     for (int it = 0; it < iters; ++it)
         for (int q = 0; q < 4; ++q) {
             const int cl = order[q];
             if (cl == last) continue;
-            if (k == 64) return smooth_single(c, l, iters);
+            if (k == kMax) return smooth_single(c, l, iters);
             col[k] = cl;
             mode[k] = sweep_mode(st[cl ^ 1]);
             st[cl] = ST_VALID;
             last = cl;
             ++k;
         }
-    const int npairs = 2 * (k / 4);
-    const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
-    for (int p = 0; p < npairs; ++p) {
-        const int c1 = col[2 * p], c2 = c1 ^ 1;
-        char *xc2 = (char *)Lv.x + (size_t)c2 * c->nc * Lv.G.plane * esz;
-        const void *xin = (p & 1) ? Lv.xt : xc2;
-        void *xout = (p & 1) ? (void *)xc2 : Lv.xt;
-        HIPCHK(c, launch_sgs_pair(c->f32, mode[2 * p], Lv.G, Lv.A, Lv.b, Lv.x, xin, xout, c1,
-                                  Lc.G, Lc.x, c->stream));
-        Lv.st[c1] = Lv.st[c2] = ST_VALID;
-        Lv.last = c2;
+    // best[q]: fewest launches for half sweeps q..k-1; step[q]: 1 (single),
+    // 4 (pair + pair) or 5 (pair + triple)
+    int best[kMax + 1], step[kMax + 1];
+    const bool triples = c->fuse >= 3 && cells(Lv.G) <= kTripleMaxCells;
+    best[k] = 0;
+    for (int q = k - 1; q >= 0; --q) {
+        best[q] = 1 + best[q + 1];
+        step[q] = 1;
+        if (q + 4 <= k && 2 + best[q + 4] < best[q]) { best[q] = 2 + best[q + 4]; step[q] = 4; }
+        if (triples && q + 5 <= k && 2 + best[q + 5] < best[q]) {
+            best[q] = 2 + best[q + 5];
+            step[q] = 5;
+        }
     }
-    for (int q = 2 * npairs; q < k; ++q) {
-        int rc = halfsweep(c, l, col[q]);
-        if (rc) return rc;
+    const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
+    for (int q = 0; q < k;) {
+        if (step[q] == 1) {
+            int rc = halfsweep(c, l, col[q]);
+            if (rc) return rc;
+            ++q;
+            continue;
+        }
+        const int c1 = col[q], c2 = c1 ^ 1;
+        void *xc2 = (char *)Lv.x + (size_t)c2 * c->nc * Lv.G.plane * esz;
+        HIPCHK(c, launch_sgs_pair(c->f32, mode[q], Lv.G, Lv.A, Lv.b, Lv.x, xc2, Lv.xt, c1,
+                                  Lc.G, Lc.x, c->stream));
+        if (step[q] == 4)
+            HIPCHK(c, launch_sgs_pair(c->f32, MODE_NORMAL, Lv.G, Lv.A, Lv.b, Lv.x, Lv.xt, xc2,
+                                      c1, Lc.G, Lc.x, c->stream));
+        else
+            HIPCHK(c, launch_sgs_triple(c->f32, MODE_NORMAL, Lv.G, Lv.A, Lv.b, Lv.x, Lv.xt, xc2,
+                                        c1, Lc.G, Lc.x, c->stream));
+        Lv.st[0] = Lv.st[1] = ST_VALID;
+        Lv.last = step[q] == 4 ? c2 : c1;
+        q += step[q];
     }
     return NMG_OK;
 }
@@ -950,7 +977,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     }
 
     c->f32 = params->inner_fp32 != 0;
-    if (const char *e = std::getenv("NMG_PAIRS")) c->pairs = std::atoi(e) != 0;
+    if (const char *e = std::getenv("NMG_FUSE")) c->fuse = std::atoi(e);
     const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
     size_t total = 0;   // elements
     for (int l = 0; l <= c->NL; ++l) {

@@ -145,6 +145,11 @@ hipError_t launch_restrict(int dim, bool f32, const LevelGeom &G, const void *A,
 hipError_t launch_sgs_pair(bool f32, int mode, const LevelGeom &G, const void *A, const void *b,
                            void *x, const void *xin, void *xout, int color, const LevelGeom &Gc,
                            const void *xc, hipStream_t s);
+// Three consecutive half sweeps (colours color, other, color; the first in
+// `mode`) in one launch, 2D only, with the buffers of launch_sgs_pair.
+hipError_t launch_sgs_triple(bool f32, int mode, const LevelGeom &G, const void *A,
+                             const void *b, void *x, const void *xin, void *xout, int color,
+                             const LevelGeom &Gc, const void *xc, hipStream_t s);
 hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *Af,
                            const LevelGeom &Gc, void *Ac, hipStream_t s);
 // Materialize one colour of x: op 0 = set zero, 1 = add the parent's

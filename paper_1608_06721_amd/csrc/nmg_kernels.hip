@@ -1436,6 +1436,161 @@ __global__ void __launch_bounds__(kPairThreads) k_sgs_pair(LevelGeom G, const T 
     for (int r = 0; r < NC; ++r) xout[r * G.plane + t2] = xi[r];
 }
 
+// Three consecutive half sweeps (colours c, c^1, c; the first in MODE) in one
+// launch, on the tiles of k_sgs_pair: phase 0 updates colour c on the tile
+// extended by two cells (neighbours from xin), phase 1 colour c^1 on the tile
+// extended by one cell, phase 2 colour c on the tile (neighbours from LDS in
+// phases 1 and 2).  Every cell that a later phase reads was computed by the
+// previous phase, so each update is sgs_cell's arithmetic on the values the
+// separate launches would have produced.  Outputs: colour c^1 of the tile to
+// xout (xin is still read by other tiles), colour c to x.  The phase-2 block
+// rows are loaded before phase 0.
+constexpr int kTripleThreads = ((kPairTX + 4) / 2 * (kPairTY + 4) + 63) / 64 * 64;
+
+template <class T, int NC>
+__device__ __forceinline__ void multi_faces(const LevelGeom &G, int i, int j, int *ni, int *nj,
+                                            bool *ok)
+{
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        ni[f] = i;
+        nj[f] = j;
+        if (f == FW) { ni[f] = i - 1; ok[f] = i > 0; }
+        else if (f == FE) { ni[f] = i + 1; ok[f] = i + 1 < G.nx; }
+        else if (f == FS) { nj[f] = j - 1; ok[f] = j > 0; }
+        else { nj[f] = j + 1; ok[f] = j + 1 < G.ny; }
+    }
+}
+
+template <class T, int NC, int MODE>
+__global__ void __launch_bounds__(kTripleThreads) k_sgs_triple(LevelGeom G,
+                                                               const T *__restrict__ A,
+                                                               const T *__restrict__ b,
+                                                               T *__restrict__ x,
+                                                               const T *__restrict__ xin,
+                                                               T *__restrict__ xout, int color,
+                                                               LevelGeom Gc,
+                                                               const T *__restrict__ xc, int ntx)
+{
+    constexpr int NF = 4;
+    constexpr int NN = NC * NC;
+    constexpr int NE = (NF + 1) * NN;
+    constexpr int H = 2;
+    constexpr int LW = kPairTX + 2 * H, LH = kPairTY + 2 * H;
+    __shared__ T lx[NC][LH][LW];
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int i0 = (tile % ntx) * kPairTX, j0 = (tile / ntx) * kPairTY;   // both even
+    const int tid = (int)threadIdx.x;
+    const int c0 = color, c1 = color ^ 1;
+
+    // phase 2 cell (the tile's colour-c cell of this thread), loaded first
+    const int j2 = j0 + tid / (kPairTX / 2);
+    const int i2 = i0 + 2 * (tid % (kPairTX / 2)) + ((j2 + c0) & 1);
+    const bool own2 = tid < kPairCells && i2 < G.nx && j2 < G.ny;
+    const long t2 = (long)j2 * G.W + (i2 >> 1);
+    T a2[NE], bv2[NC];
+    if (own2) {
+        const T *Am = A + mat_off(G, NE, c0, t2);
+#pragma unroll
+        for (int e = 0; e < NE; ++e) a2[e] = Am[e * kTile];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) bv2[r] = b[((long)c0 * NC + r) * G.plane + t2];
+    }
+
+    // phase 0: colour c on the tile extended by 2 (one cell per thread)
+    {
+        constexpr int WH = (kPairTX + 2 * H) / 2;
+        const int jj = j0 - H + tid / WH;
+        const int ib = i0 - H;
+        const int ii = ib + 2 * (tid % WH) + ((ib + jj + c0) & 1);
+        if (tid < WH * (kPairTY + 2 * H) && ii >= 0 && ii < G.nx && jj >= 0 && jj < G.ny) {
+            const long t = (long)jj * G.W + (ii >> 1);
+            const T *Am = A + mat_off(G, NE, c0, t);
+            T a[NE], bv[NC], v[NF][NC], xi[NC];
+            int ni[NF], nj[NF];
+            bool ok[NF];
+            multi_faces<T, NC>(G, ii, jj, ni, nj, ok);
+#pragma unroll
+            for (int e = 0; e < (MODE == MODE_ZERO ? NN : NE); ++e) a[e] = Am[e * kTile];
+#pragma unroll
+            for (int r = 0; r < NC; ++r) bv[r] = b[((long)c0 * NC + r) * G.plane + t];
+            if (MODE != MODE_ZERO) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    if (ok[f]) {
+                        read_other<T, NC, MODE>(G, xin, ni[f], nj[f], Gc, xc, v[f]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < NC; ++q) v[f][q] = T(0);
+                    }
+                }
+            }
+            gs_update<T, NC, MODE == MODE_ZERO, false>(a, nullptr, bv, v, ok, xi);
+#pragma unroll
+            for (int r = 0; r < NC; ++r) lx[r][jj - j0 + H][ii - i0 + H] = xi[r];
+        }
+    }
+    __syncthreads();
+
+    // phase 1: colour c^1 on the tile extended by 1, neighbours from LDS
+    {
+        constexpr int WH = (kPairTX + 2) / 2;
+        const int jj = j0 - 1 + tid / WH;
+        const int ib = i0 - 1;
+        const int ii = ib + 2 * (tid % WH) + ((ib + jj + c1) & 1);
+        if (tid < WH * (kPairTY + 2) && ii >= 0 && ii < G.nx && jj >= 0 && jj < G.ny) {
+            const long t = (long)jj * G.W + (ii >> 1);
+            const T *Am = A + mat_off(G, NE, c1, t);
+            T a[NE], bv[NC], v[NF][NC], xi[NC];
+            int ni[NF], nj[NF];
+            bool ok[NF];
+            multi_faces<T, NC>(G, ii, jj, ni, nj, ok);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) a[e] = Am[e * kTile];
+#pragma unroll
+            for (int r = 0; r < NC; ++r) bv[r] = b[((long)c1 * NC + r) * G.plane + t];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const int li = ok[f] ? ni[f] - i0 + H : H, lj = ok[f] ? nj[f] - j0 + H : H;
+#pragma unroll
+                for (int q = 0; q < NC; ++q) {
+                    const T val = lx[q][lj][li];
+                    v[f][q] = ok[f] ? val : T(0);
+                }
+            }
+            gs_update<T, NC, false, false>(a, nullptr, bv, v, ok, xi);
+            // colour c^1 slots: no thread reads them in this phase
+#pragma unroll
+            for (int r = 0; r < NC; ++r) lx[r][jj - j0 + H][ii - i0 + H] = xi[r];
+            if (ii >= i0 && ii < i0 + kPairTX && jj >= j0 && jj < j0 + kPairTY) {
+#pragma unroll
+                for (int r = 0; r < NC; ++r) xout[r * G.plane + t] = xi[r];
+            }
+        }
+    }
+    __syncthreads();
+
+    // phase 2: the tile's colour-c cells, neighbours from LDS
+    if (!own2) return;
+    T v[NF][NC], xi[NC];
+    int ni[NF], nj[NF];
+    bool ok[NF];
+    multi_faces<T, NC>(G, i2, j2, ni, nj, ok);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const int li = ok[f] ? ni[f] - i0 + H : H, lj = ok[f] ? nj[f] - j0 + H : H;
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            const T val = lx[q][lj][li];
+            v[f][q] = ok[f] ? val : T(0);
+        }
+    }
+    gs_update<T, NC, false, false>(a2, nullptr, bv2, v, ok, xi);
+    T *xm = x + (long)c0 * NC * G.plane + t2;
+#pragma unroll
+    for (int r = 0; r < NC; ++r) xm[r * G.plane] = xi[r];
+}
+
 // Layout conversions between the public FP64 layouts and the hierarchy's
 // colour-split storage of precision T.
 template <class T>
@@ -2152,6 +2307,41 @@ hipError_t launch_sgs_pair(bool f32, int mode, const LevelGeom &G, const void *A
     return pair_dispatch<double>(mode, G, (const double *)A, (const double *)b, (double *)x,
                                  (const double *)xin, (double *)xout, color, Gc,
                                  (const double *)xc, s);
+}
+
+template <class T>
+static hipError_t triple_dispatch(int mode, const LevelGeom &G, const T *A, const T *b, T *x,
+                                  const T *xin, T *xout, int color, const LevelGeom &Gc,
+                                  const T *xc, hipStream_t s)
+{
+    const int ntx = (G.nx + kPairTX - 1) / kPairTX, nty = (G.ny + kPairTY - 1) / kPairTY;
+    const int g = ntx * nty;
+#define NMG_TRIPLE(M)                                                                         \
+    do {                                                                                      \
+        hipLaunchKernelGGL((k_sgs_triple<T, 3, M>), dim3(g), dim3(kTripleThreads), 0, s, G,   \
+                           A, b, x, xin, xout, color, Gc, xc, ntx);                           \
+        return hipGetLastError();                                                             \
+    } while (0)
+    switch (mode) {
+    case MODE_NORMAL: NMG_TRIPLE(MODE_NORMAL);
+    case MODE_ZERO: NMG_TRIPLE(MODE_ZERO);
+    case MODE_PROLONG: NMG_TRIPLE(MODE_PROLONG);
+    default: NMG_TRIPLE(MODE_PROLONG_ZERO);
+    }
+#undef NMG_TRIPLE
+}
+
+hipError_t launch_sgs_triple(bool f32, int mode, const LevelGeom &G, const void *A,
+                             const void *b, void *x, const void *xin, void *xout, int color,
+                             const LevelGeom &Gc, const void *xc, hipStream_t s)
+{
+    if (f32)
+        return triple_dispatch<float>(mode, G, (const float *)A, (const float *)b, (float *)x,
+                                      (const float *)xin, (float *)xout, color, Gc,
+                                      (const float *)xc, s);
+    return triple_dispatch<double>(mode, G, (const double *)A, (const double *)b, (double *)x,
+                                   (const double *)xin, (double *)xout, color, Gc,
+                                   (const double *)xc, s);
 }
 
 template <class T, int NC>

@@ -152,16 +152,16 @@ def test_sgs_bitwise(nmg, case, iters):
 @pytest.mark.parametrize("cycles", [1, 3])
 @pytest.mark.parametrize("coarse_cells", ["4096", "0"])
 @pytest.mark.parametrize("gamma", [1, 2])
-@pytest.mark.parametrize("pairs", ["1", "0"])
-def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, gamma, pairs, monkeypatch):
+@pytest.mark.parametrize("fuse", ["3", "2", "1"])
+def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, gamma, fuse, monkeypatch):
     """coarse_cells: levels up to this many cells run in the single-workgroup
     coarse-cycle kernel ("0": every level launched on its own); gamma = 2 is
-    the W-cycle; pairs = "0" launches every half sweep on its own instead of
-    fusing consecutive pairs on the launched coarse levels."""
+    the W-cycle; fuse: most half sweeps per launch on the launched coarse
+    levels (3: pairs and triples, 2: pairs, 1: every half sweep on its own)."""
     prob, A, b, x0 = random_case(*case)
-    say("vcycle", case, nus, cycles, coarse_cells, gamma, pairs)
+    say("vcycle", case, nus, cycles, coarse_cells, gamma, fuse)
     monkeypatch.setenv("NMG_COARSE_CELLS", coarse_cells)
-    monkeypatch.setenv("NMG_PAIRS", pairs)
+    monkeypatch.setenv("NMG_FUSE", fuse)
     p = dict(prob.params, nu1=nus[0], nu2=nus[1], nu_coarse=nus[2], gamma=gamma)
     ctx = nmg.Context.from_problem(prob, **p)
     ctx.load_system(dev(A), dev(b))
