@@ -105,11 +105,13 @@ struct CoarseOp {
 
 inline int nblocks(long n) { return (int)((n + kBlock - 1) / kBlock); }
 
-// A level whose block matrix is larger than this cannot stay in the chip's
-// 256 MB last-level cache between two visits of the level in a cycle, so its
-// launches fetch the matrix as read-once data (non-temporal hint); smaller
-// levels are left to the cache, which serves their repeated visits.
-constexpr long kStreamBytes = 128L << 20;
+// A level whose block matrix is larger than this is fetched as read-once data
+// (non-temporal hint) by its launched half sweeps and restriction; smaller
+// levels are left to the caches, which serve their repeated visits in a
+// cycle.  Measured on the 1024x1024 solve: streaming the finest level (377
+// MB) gained 13% on its half sweep, adding the 512x512 level (94 MB) 1% on
+// the solve, going down to 16 MB nothing more; streaming every level lost.
+constexpr long kStreamBytes = 64L << 20;
 inline bool stream_level(long cells, int nc, long elem_bytes)
 {
     const long ne = (nc == 2 ? 3 : 5) * (long)nc * nc;

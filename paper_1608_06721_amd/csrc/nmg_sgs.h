@@ -33,9 +33,8 @@ __device__ __forceinline__ int xcd_block(int b, int n)
     return (k / kXcdChunk) * G + x * kXcdChunk + k % kXcdChunk;
 }
 
-// Load of matrix data that one launch reads exactly once and that is too
-// large to stay in the last-level cache until the next visit of its level
-// (the host decides per level, see stream_level).  In FP64 the off-diagonal
+// Load of matrix data that one launch reads exactly once, on a level large
+// enough that the host streams it (stream_level).  In FP64 the off-diagonal
 // blocks are then fetched with the non-temporal hint (measured: the
 // 1024x1024 half sweep runs 13% faster; in FP32, and for the diagonal block
 // and b, the hint is slower or neutral).
