@@ -170,13 +170,14 @@ def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, gamma, fuse, monke
     same(host(x), oracle.vcycles(A, b, x0, p, cycles), "x after V-cycles")
 
 
-# Cycles whose first coarse-kernel level (32x32, 32x24; 1024 cells in 1D)
+# Cycles whose first coarse-kernel level (32x32, 32x24, 30x20 over an odd
+# 15x10; 1024 cells in 1D)
 # lives in global memory with at most one slot per colour and thread: its
 # runs of half sweeps, and the restriction that follows them, execute with
 # the level's block rows in registers (COP_REGRUN); NMG_COARSE_REG=0 runs the
 # same operations one by one.  nu1 = 0 leaves a restriction with no run
 # before it, nu2 = 0 a level whose correction is fixed up at the end.
-REG = [(2, 64, 64, 5, 2), (2, 64, 48, 6, 3), (1, 2048, 1, 7, 2)]
+REG = [(2, 64, 64, 5, 2), (2, 64, 48, 6, 3), (1, 2048, 1, 7, 2), (2, 120, 80, 10, 3)]
 
 
 @pytest.mark.parametrize("case", REG)
