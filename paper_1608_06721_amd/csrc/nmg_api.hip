@@ -103,6 +103,8 @@ struct nmg_batch {
     WorkRange w_plane[kMaxLevels][kNumTiles];   // colour-plane tiles per tile length
     WorkRange w_ccells[kMaxLevels];       // 256-cell tiles of level l (Galerkin into l)
     WorkRange w_rchild[kMaxLevels];       // tiles of 256 children of level l's cells (restriction into l)
+    WorkRange w_tile2d[kMaxLevels];       // 32x16 cell tiles of level l (fused half-sweep pairs)
+    long cells_l[kMaxLevels] = {};        // cells of level l summed over the instances
     int tile[kMaxLevels];                 // tile length of the half sweeps per level
     int *d_active = nullptr, *h_active = nullptr;   // instances still iterating
     int *d_mask = nullptr, *h_mask = nullptr;       // a second instance mask
@@ -245,11 +247,14 @@ constexpr long kPairMaxCells = 1L << 17;
 // levels (measured: 9.4 us against 6.5 + 4.5 us at 64x64, 11.8 against
 // 7.0 + 4.7 us at 128x128, 13.5 against 8.0 + 4.8 us at 256x256).
 constexpr long kTripleMaxCells = 1L << 12;
+long batch_cells(const nmg_ctx *c, int l) { return c->batch->cells_l[l]; }
+
 bool fuse_pairs(const nmg_ctx *c, int l)
 {
-    if (c->recording || c->batch || c->dim != 2 || l == 0) return false;
+    if (c->recording || c->dim != 2 || l == 0) return false;
     if (c->lc >= 0 && l >= c->lc) return false;
-    if (cells(c->L[l].G) > kPairMaxCells) return false;
+    const long n = c->batch ? batch_cells(c, l) : cells(c->L[l].G);
+    if (n > kPairMaxCells) return false;
     return c->fuse >= 2;
 }
 
@@ -292,7 +297,7 @@ int smooth_pairs(nmg_ctx *c, int l, int iters)
     // best[q]: fewest launches for half sweeps q..k-1; step[q]: 1 (single),
     // 4 (pair + pair) or 5 (pair + triple)
     int best[kMax + 1], step[kMax + 1];
-    const bool triples = c->fuse >= 3 && cells(Lv.G) <= kTripleMaxCells;
+    const bool triples = !c->batch && c->fuse >= 3 && cells(Lv.G) <= kTripleMaxCells;
     best[k] = 0;
     for (int q = k - 1; q >= 0; --q) {
         best[q] = 1 + best[q + 1];
@@ -312,6 +317,18 @@ int smooth_pairs(nmg_ctx *c, int l, int iters)
             continue;
         }
         const int c1 = col[q], c2 = c1 ^ 1;
+        if (c->batch) {
+            const nmg_batch *B = c->batch;
+            const BatchLevel *blv = B->d_lv + (long)l * B->n;
+            HIPCHK(c, launch_b_sgs_pair(c->f32, mode[q], blv, B->w_tile2d[l], B->d_active, c1, 0,
+                                        c->stream));
+            HIPCHK(c, launch_b_sgs_pair(c->f32, MODE_NORMAL, blv, B->w_tile2d[l], B->d_active, c1,
+                                        1, c->stream));
+            Lv.st[0] = Lv.st[1] = ST_VALID;
+            Lv.last = c2;
+            q += 4;
+            continue;
+        }
         void *xc2 = (char *)Lv.x + (size_t)c2 * c->nc * Lv.G.plane * esz;
         HIPCHK(c, launch_sgs_pair(c->f32, mode[q], Lv.G, Lv.A, Lv.b, Lv.x, xc2, Lv.xt, c1,
                                   Lc.G, Lc.x, c->stream));
@@ -1457,14 +1474,20 @@ int nmg_batch_create(int n, const nmg_grid *grids, const nmg_bc *bcs, const nmg_
             rb.add(&b->w_ccells[l], u, kBlock);
             for (int k = 0; k < n; ++k) u[k] = cells(geom(k, l)) * (b->dim == 1 ? 2 : 4);
             rb.add(&b->w_rchild[l], u, kBlock);
+            for (int k = 0; k < n; ++k)
+                u[k] = (long)((geom(k, l).nx + kPairTX - 1) / kPairTX) *
+                       ((geom(k, l).ny + kPairTY - 1) / kPairTY);
+            rb.add(&b->w_tile2d[l], u, 1);
         }
+        for (int k = 0; k < n; ++k) b->cells_l[l] += cells(geom(k, l));
     }
     std::vector<BatchLevel> blv((size_t)(NL + 1) * n);
     for (int l = 0; l <= NL; ++l)
         for (int k = 0; k < n; ++k) {
             const Level &Lf = b->inst[k]->L[l];
             const Level &Lc = b->inst[k]->L[l < NL ? l + 1 : l];
-            blv[(size_t)l * n + k] = BatchLevel{Lf.G, Lc.G, Lf.A, Lf.b, Lf.x, Lc.A, Lc.b, Lc.x};
+            blv[(size_t)l * n + k] = BatchLevel{Lf.G, Lc.G, Lf.A, Lf.b, Lf.x, Lc.A, Lc.b, Lc.x,
+                                                Lf.xt};
         }
     b->h_inst.resize(n);
     for (int k = 0; k < n; ++k) {

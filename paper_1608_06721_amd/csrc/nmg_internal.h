@@ -64,6 +64,7 @@ enum SweepMode {
 };
 
 constexpr int kBlock = 256;
+constexpr int kPairTX = 32, kPairTY = 16;   // cell tiles of the fused half-sweep pairs
 constexpr int kCoarseBlock = 512;     // one workgroup runs the coarse part of a cycle
 constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarseOps = 1 << 16;  // longest recorded coarse program
@@ -210,6 +211,7 @@ struct BatchLevel {
     LevelGeom G, Gc;
     void *A, *b, *x;
     void *Ac, *bc, *xc;
+    void *xt;               // the level's alternate planes for fused half-sweep pairs
 };
 
 // One tile of one instance: a batched launch runs one block per work item.
@@ -243,6 +245,11 @@ hipError_t launch_b_reduce(const double *partial, const int *off, const int *cnt
                            const int *active, double *out, hipStream_t s);
 hipError_t launch_b_blu_half(int dim, const BatchInst *bi, WorkRange w, const int *active,
                              int color, hipStream_t s);
+// Fused half-sweep pair of launch_sgs_pair over a work list of 32x16 tiles
+// (2D): flip 0 reads the second colour from x and writes it to xt, flip 1
+// the reverse.
+hipError_t launch_b_sgs_pair(bool f32, int mode, const BatchLevel *lv, WorkRange w,
+                             const int *active, int color, int flip, hipStream_t s);
 hipError_t launch_b_update(int dim, bool f32, const BatchInst *bi, WorkRange w,
                            const int *active, hipStream_t s);
 hipError_t launch_b_threshold(int dim, const BatchInst *bi, WorkRange w, const int *active,

@@ -1325,27 +1325,23 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
 // different buffers: other tiles may still read the old values).  Every
 // cell update is sgs_cell's arithmetic on the same inputs, so the result is
 // bit for bit that of the two half sweeps launched one by one.
-constexpr int kPairTX = 32, kPairTY = 16;
 constexpr int kPairCells = kPairTX / 2 * kPairTY;        // cells of one colour per tile
 constexpr int kPairRing = kPairTX + kPairTY;             // colour-c cells bordering a tile
 constexpr int kPairThreads = (kPairCells + kPairRing + 63) / 64 * 64;
 
+// The pair on the tile with corner (i0, j0) (both even).
 template <class T, int NC, int MODE>
-__global__ void __launch_bounds__(kPairThreads) k_sgs_pair(LevelGeom G, const T *__restrict__ A,
-                                                           const T *__restrict__ b,
-                                                           T *__restrict__ x,
-                                                           const T *__restrict__ xin,
-                                                           T *__restrict__ xout, int color,
-                                                           LevelGeom Gc, const T *__restrict__ xc,
-                                                           int ntx)
+__device__ __forceinline__ void sgs_pair_tile(const LevelGeom &G, const T *__restrict__ A,
+                                              const T *__restrict__ b, T *__restrict__ x,
+                                              const T *__restrict__ xin, T *__restrict__ xout,
+                                              int color, const LevelGeom &Gc,
+                                              const T *__restrict__ xc, int i0, int j0)
 {
     constexpr int NF = 4;
     constexpr int NN = NC * NC;
     constexpr int NE = (NF + 1) * NN;
     constexpr int LX = kPairTX + 2, LY = kPairTY + 2;
     __shared__ T lx[NC][LY][LX];
-    const int tile = xcd_block(blockIdx.x, gridDim.x);
-    const int i0 = (tile % ntx) * kPairTX, j0 = (tile / ntx) * kPairTY;   // both even
     const int tid = (int)threadIdx.x;
     const int c1 = color, c2 = color ^ 1;
 
@@ -1434,6 +1430,20 @@ __global__ void __launch_bounds__(kPairThreads) k_sgs_pair(LevelGeom G, const T 
     gs_update<T, NC, false, false>(a2, nullptr, bv2, v, ok, xi);
 #pragma unroll
     for (int r = 0; r < NC; ++r) xout[r * G.plane + t2] = xi[r];
+}
+
+template <class T, int NC, int MODE>
+__global__ void __launch_bounds__(kPairThreads) k_sgs_pair(LevelGeom G, const T *__restrict__ A,
+                                                           const T *__restrict__ b,
+                                                           T *__restrict__ x,
+                                                           const T *__restrict__ xin,
+                                                           T *__restrict__ xout, int color,
+                                                           LevelGeom Gc, const T *__restrict__ xc,
+                                                           int ntx)
+{
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    sgs_pair_tile<T, NC, MODE>(G, A, b, x, xin, xout, color, Gc, xc, (tile % ntx) * kPairTX,
+                               (tile / ntx) * kPairTY);
 }
 
 // Three consecutive half sweeps (colours c, c^1, c; the first in MODE) in one
@@ -2118,6 +2128,25 @@ __global__ void __launch_bounds__(TB) kb_sgs_half(const BatchLevel *__restrict__
                               (const T *)L.xc, t);
 }
 
+template <class T, int MODE>
+__global__ void __launch_bounds__(kPairThreads) kb_sgs_pair(const BatchLevel *__restrict__ lv,
+                                                            WorkRange w,
+                                                            const int *__restrict__ active,
+                                                            int color, int flip)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchLevel &L = lv[it.inst];
+    const int ntx = (L.G.nx + kPairTX - 1) / kPairTX;
+    T *x2 = (T *)L.x + (long)(color ^ 1) * 3 * L.G.plane;
+    const T *xin = flip ? (const T *)L.xt : x2;
+    T *xout = flip ? x2 : (T *)L.xt;
+    sgs_pair_tile<T, 3, MODE>(L.G, (const T *)L.A, (const T *)L.b, (T *)L.x, xin, xout, color,
+                              L.Gc, (const T *)L.xc, (it.tile % ntx) * kPairTX,
+                              (it.tile / ntx) * kPairTY);
+}
+
 template <class T, int NC>
 __global__ void __launch_bounds__(kBlock) kb_restrict(const BatchLevel *__restrict__ lv,
                                                       WorkRange w,
@@ -2616,6 +2645,33 @@ hipError_t launch_b_sgs_half(int dim, bool f32, int mode, int tile, const BatchL
     }
     if (dim == 1) return bsgs_tile<double, 2>(mode, tile, lv, w, active, color, s);
     return bsgs_tile<double, 3>(mode, tile, lv, w, active, color, s);
+}
+
+template <class T>
+static hipError_t b_pair_dispatch(int mode, const BatchLevel *lv, WorkRange w, const int *active,
+                                  int color, int flip, hipStream_t s)
+{
+#define NMG_BPAIR(M)                                                                          \
+    do {                                                                                      \
+        hipLaunchKernelGGL((kb_sgs_pair<T, M>), dim3(w.n), dim3(kPairThreads), 0, s, lv, w,   \
+                           active, color, flip);                                              \
+        return hipGetLastError();                                                             \
+    } while (0)
+    switch (mode) {
+    case MODE_NORMAL: NMG_BPAIR(MODE_NORMAL);
+    case MODE_ZERO: NMG_BPAIR(MODE_ZERO);
+    case MODE_PROLONG: NMG_BPAIR(MODE_PROLONG);
+    default: NMG_BPAIR(MODE_PROLONG_ZERO);
+    }
+#undef NMG_BPAIR
+}
+
+hipError_t launch_b_sgs_pair(bool f32, int mode, const BatchLevel *lv, WorkRange w,
+                             const int *active, int color, int flip, hipStream_t s)
+{
+    if (w.n == 0) return hipSuccess;
+    if (f32) return b_pair_dispatch<float>(mode, lv, w, active, color, flip, s);
+    return b_pair_dispatch<double>(mode, lv, w, active, color, flip, s);
 }
 
 hipError_t launch_b_restrict(int dim, bool f32, const BatchLevel *lv, WorkRange w,

@@ -92,9 +92,12 @@ CASES = {
     # W-cycle with the FP32 inner cycle
     "w_fp32": (lambda: W.batch_channels(4, sizes=(32, 64), seed=12, n_levels=3, gamma=2,
                                         inner_fp32=1, max_newton=60), 1e-10, "1024"),
-    # every level launched on its own (no coarse kernel)
+    # every level launched on its own (no coarse kernel), half sweeps fused in pairs
     "launched": (lambda: W.batch_channels(3, sizes=(32, 64), seed=13, n_levels=3, gamma=2,
                                           max_newton=40), 1e-10, "0"),
+    # the same with every half sweep launched on its own
+    "launched_unfused": (lambda: W.batch_channels(3, sizes=(32, 64), seed=13, n_levels=3, gamma=2,
+                                                  max_newton=40), 1e-10, "0", "1"),
     # 1D: two bed families, uneven lengths, the coarse kernel on the 8..25-cell levels
     "one_d": (lambda: [W.bump_1d(64, n_levels=3, max_newton=80),
                        W.smooth_1d(96, n_levels=3, max_newton=80),
@@ -108,8 +111,9 @@ CASES = {
 
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_batch_matches_oracle_and_single(nmg, case, monkeypatch):
-    mk, tol, cc = CASES[case]
+    mk, tol, cc = CASES[case][:3]
     monkeypatch.setenv("NMG_COARSE_CELLS", cc)
+    monkeypatch.setenv("NMG_FUSE", CASES[case][3] if len(CASES[case]) > 3 else "3")
     probs = mk()
     say(case, [p.name for p in probs])
     Ub, rb = run_batch(nmg, probs, tol)
