@@ -307,6 +307,24 @@ def test_full_size_assembly_and_cycle(nmg):
     same(host(x), xo, "dU after one V-cycle 1024^2")
 
 
+def test_full_size_benchmark_cycles(nmg):
+    """The benchmark's own configuration and launch path (1024 x 1024 channel,
+    6 levels, W-cycle: streamed 1024x1024 and 512x512 levels, fused pairs and
+    a triple on the launched coarse levels, one coarse-kernel launch per two
+    32x32 visits with register-resident runs): assembly and two W-cycles from
+    zero, bit for bit."""
+    prob = W.channel(1024, 1024, n_levels=6, gamma=2, bump_width=(0.2, 0.8), mound_amp=0.8)
+    say("full size 1024^2 benchmark W-cycles")
+    ctx = nmg.Context.from_problem(prob)
+    z, U = dev(prob.z), dev(prob.U0)
+    ctx.assemble_residual_jacobian(z, U)
+    Ao, bo, _ = oracle.assemble(prob, prob.U0)
+    x = torch.zeros_like(U)
+    ctx.mg_vcycle(x, 2)
+    same(host(x), oracle.vcycles(Ao, bo, np.zeros_like(bo), prob.params, 2),
+         "dU after two W-cycles 1024^2")
+
+
 # --- FP32 inner V-cycle (hierarchy and smoother in FP32, Newton in FP64) ---
 
 @pytest.mark.parametrize("case", LIN + TILED)
