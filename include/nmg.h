@@ -130,7 +130,17 @@ typedef struct {
 /* Create a context for one grid / BC / parameter set on HIP stream `stream`
  * (hipStream_t, may be NULL for the null stream).  Allocates the
  * hierarchy.  Errors: EINVAL (inconsistent grid, BC or params), ENOMEM,
- * EHIP. */
+ * EHIP.
+ *
+ * Launch-structure switches, read from the environment here (and by
+ * nmg_batch_create); none changes a bit of any result:
+ *   NMG_COARSE_CELLS  levels of at most this many cells run inside one
+ *                     single-workgroup kernel per cycle (default 1024; 0:
+ *                     every level launched on its own);
+ *   NMG_COARSE_REG    0 turns off register-resident runs on that kernel's
+ *                     first level (default on);
+ *   NMG_FUSE          most half sweeps per launch on the launched coarse
+ *                     levels: 3 (default), 2 or 1. */
 int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
                void *stream, nmg_ctx **out);
 void nmg_destroy(nmg_ctx *ctx);
