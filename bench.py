@@ -218,15 +218,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=1024)
     # W-cycle (gamma = 2) on 7 levels (coarsest 16x16): 39 Newton steps on the
-    # channel against 216 for the V-cycle on 9 levels.
+    # channel against 216 for the V-cycle on 9 levels, which is 2.2x slower.
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--gamma", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-newton", type=int, default=500)
     # Bed of the measured channel: 16 seeded Gaussians (amplitude U[0, 0.3],
     # width U[0.2, 0.8]) and two mounds of amplitude 0.8 (one emerges as a
-    # dry island).  Narrower bumps or higher mounds do not converge with
-    # this method at 1024^2 (workload section).
+    # dry island).  With narrower bumps (widths U[0.05, 0.4]) or mounds of
+    # amplitude 0.9 and more the method does not converge at 1024^2.
     ap.add_argument("--bump-width", type=float, nargs=2, default=[0.2, 0.8])
     ap.add_argument("--mound-amp", type=float, default=0.8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -245,9 +245,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the method's single solve is not sharded "
-              "across GPUs in this build (see DESIGN.md); run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: a single solve is not sharded across GPUs; "
+              "run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
