@@ -182,7 +182,7 @@ REG = [(2, 64, 64, 5, 2), (2, 64, 48, 6, 3), (1, 2048, 1, 7, 2), (2, 120, 80, 10
 
 @pytest.mark.parametrize("case", REG)
 @pytest.mark.parametrize("nus", [(2, 2, 10), (1, 0, 3), (0, 1, 2)])
-@pytest.mark.parametrize("gamma", [1, 2])
+@pytest.mark.parametrize("gamma", [1, 2, 3])
 @pytest.mark.parametrize("reg", ["1", "0"])
 @pytest.mark.parametrize("fp32", [0, 1])
 def test_vcycle_register_runs_bitwise(nmg, case, nus, gamma, reg, fp32, monkeypatch):
