@@ -78,7 +78,7 @@ struct nmg_ctx {
     int lc = -1;
     bool recording = false;
     std::vector<CoarseOp> rec;
-    int prog_off[2] = {0, 0}, prog_len[2] = {0, 0};   // [0]: the coarse program, [1]: unused
+    int prog_len = 0;                 // operations of the recorded coarse program (rec)
     int l_lds = -1;                   // levels l_lds..NL run from LDS in the coarse kernel
     CoarseOp *d_ops = nullptr;
     LevelDev *d_lv = nullptr;
@@ -420,17 +420,17 @@ int cycle(nmg_ctx *c, int l)
                                       stream_level(cells(Lv.G), c->nc, c->f32 ? 4 : 8),
                                       c->stream));
         set_zero(c, l + 1);
-        if (l + 1 == c->lc && !c->recording && c->prog_len[0] > 0) {
+        if (l + 1 == c->lc && !c->recording && c->prog_len > 0) {
             // The coarse calls below, from level lc down, run in one
             // workgroup (the program recorded by record_coarse) and leave
             // level lc's correction materialized.
             if (c->batch)
-                HIPCHK(c, launch_b_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[0],
-                                                c->prog_len[0], c->batch->d_clv, c->batch->n,
+                HIPCHK(c, launch_b_coarse_cycle(c->dim, c->f32, c->d_ops, c->prog_len,
+                                                c->batch->d_clv, c->batch->n,
                                                 c->batch->d_active, c->l_lds, c->NL, c->stream));
             else
-                HIPCHK(c, launch_coarse_cycle(c->dim, c->f32, c->d_ops + c->prog_off[0],
-                                              c->prog_len[0], c->d_lv, c->l_lds, c->NL,
+                HIPCHK(c, launch_coarse_cycle(c->dim, c->f32, c->d_ops, c->prog_len, c->d_lv,
+                                              c->l_lds, c->NL,
                                               c->stream));
             Lc.st[0] = Lc.st[1] = ST_VALID;
             Lc.last = -1;
@@ -473,33 +473,25 @@ void merge_runs(nmg_ctx *c, bool fits)
     const int nl = c->NL;
     if (c->l_lds < 0 || !fits) return;
     std::vector<CoarseOp> out;
-    int off[2], len[2];
-    for (int prog = 0; prog < 2; ++prog) {
-        off[prog] = (int)out.size();
-        const CoarseOp *r = c->rec.data() + c->prog_off[prog];
-        const int n = c->prog_len[prog];
-        for (int q = 0; q < n;) {
-            CoarseOp o = r[q];
-            if (o.kind == COP_SGS && o.level == nl && (o.mode == MODE_NORMAL || o.mode == MODE_ZERO)) {
-                int e = q + 1;
-                while (e < n && r[e].kind == COP_SGS && r[e].level == nl && r[e].mode == MODE_NORMAL &&
-                       r[e].color == (r[e - 1].color ^ 1))
-                    ++e;
-                o.kind = COP_RUN;
-                o.count = e - q;
-                q = e;
-            } else {
-                ++q;
-            }
-            out.push_back(o);
+    const CoarseOp *r = c->rec.data();
+    const int n = (int)c->rec.size();
+    for (int q = 0; q < n;) {
+        CoarseOp o = r[q];
+        if (o.kind == COP_SGS && o.level == nl && (o.mode == MODE_NORMAL || o.mode == MODE_ZERO)) {
+            int e = q + 1;
+            while (e < n && r[e].kind == COP_SGS && r[e].level == nl && r[e].mode == MODE_NORMAL &&
+                   r[e].color == (r[e - 1].color ^ 1))
+                ++e;
+            o.kind = COP_RUN;
+            o.count = e - q;
+            q = e;
+        } else {
+            ++q;
         }
-        len[prog] = (int)out.size() - off[prog];
+        out.push_back(o);
     }
     c->rec.swap(out);
-    for (int prog = 0; prog < 2; ++prog) {
-        c->prog_off[prog] = off[prog];
-        c->prog_len[prog] = len[prog];
-    }
+    c->prog_len = (int)c->rec.size();
 }
 
 // Replace each maximal sequence of alternating half sweeps on the first
@@ -514,39 +506,31 @@ void merge_reg_runs(nmg_ctx *c, bool ok, long rs_off)
         if (std::atoi(e) == 0) return;
     const int lc = c->lc;
     std::vector<CoarseOp> out;
-    int off[2], len[2];
-    for (int prog = 0; prog < 2; ++prog) {
-        off[prog] = (int)out.size();
-        const CoarseOp *r = c->rec.data() + c->prog_off[prog];
-        const int n = c->prog_len[prog];
-        for (int q = 0; q < n;) {
-            CoarseOp o = r[q];
-            if (o.kind == COP_SGS && o.level == lc) {
-                int e = q + 1;
-                while (e < n && r[e].kind == COP_SGS && r[e].level == lc &&
-                       r[e].mode == MODE_NORMAL && r[e].color == (r[e - 1].color ^ 1))
-                    ++e;
-                o.kind = COP_REGRUN;
-                o.count = e - q;
-                o.aux = 0;
-                o.lds_off = (int)rs_off;
-                if (e < n && r[e].kind == COP_RESTRICT && r[e].level == lc) {
-                    o.aux = 1;
-                    ++e;
-                }
-                q = e;
-            } else {
-                ++q;
+    const CoarseOp *r = c->rec.data();
+    const int n = (int)c->rec.size();
+    for (int q = 0; q < n;) {
+        CoarseOp o = r[q];
+        if (o.kind == COP_SGS && o.level == lc) {
+            int e = q + 1;
+            while (e < n && r[e].kind == COP_SGS && r[e].level == lc && r[e].mode == MODE_NORMAL &&
+                   r[e].color == (r[e - 1].color ^ 1))
+                ++e;
+            o.kind = COP_REGRUN;
+            o.count = e - q;
+            o.aux = 0;
+            o.lds_off = (int)rs_off;
+            if (e < n && r[e].kind == COP_RESTRICT && r[e].level == lc) {
+                o.aux = 1;
+                ++e;
             }
-            out.push_back(o);
+            q = e;
+        } else {
+            ++q;
         }
-        len[prog] = (int)out.size() - off[prog];
+        out.push_back(o);
     }
     c->rec.swap(out);
-    for (int prog = 0; prog < 2; ++prog) {
-        c->prog_off[prog] = off[prog];
-        c->prog_len[prog] = len[prog];
-    }
+    c->prog_len = (int)c->rec.size();
 }
 
 // LDS bytes of the coarse-cycle kernel's level copies (levels l_lds..NL).
@@ -634,21 +618,19 @@ int record_coarse(nmg_ctx *c, bool fits, bool reg_ok, long rs_off)
     // zero correction, then level lc's correction materialized.  Runs of half
     // sweeps continue across the calls (the repeated colour at the junction
     // is elided as in the level-by-level launches).
-    c->prog_off[0] = 0;
     c->recording = true;
     set_zero(c, c->lc);
     const int calls = (c->lc == 1) ? 1 : c->prm.gamma;
     for (int g = 0; g < calls && !rc; ++g) rc = cycle(c, c->lc);
     if (!rc) rc = materialize(c, c->lc);
     c->recording = false;
-    c->prog_len[0] = (int)c->rec.size();
-    c->prog_off[1] = c->prog_len[0];
-    c->prog_len[1] = 0;
+    c->prog_len = (int)c->rec.size();
     for (int l = 0; l <= c->NL; ++l) c->L[l] = saved[l];
     if (rc) return rc;
-    if (c->prog_len[0] > kMaxCoarseOps || c->prog_len[1] > kMaxCoarseOps) {
+    if (c->prog_len > kMaxCoarseOps) {
         c->lc = -1;                              // too long: per-level launches
         c->rec.clear();
+        c->prog_len = 0;
         return NMG_OK;
     }
     merge_runs(c, fits);
