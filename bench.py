@@ -92,7 +92,8 @@ def cpu_baseline(prob, n_steps, budget_s):
 
 def timed_solves(ctx, z, U0, steps, warmup, tol, cap):
     """Warm-up solves, then `steps` timed solves from U0 (inputs resident in
-    HBM); returns (seconds, stats, timing of the finest full SGS sweeps)."""
+    HBM); returns (seconds, stats, timing of the finest full SGS sweeps, the
+    last solve's state)."""
     import torch
     for _ in range(warmup):
         ctx.newton_mg_solve(z, U0.clone(), tol)
@@ -104,7 +105,7 @@ def timed_solves(ctx, z, U0, steps, warmup, tol, cap):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.timing_enable(False)
-    return dt, stats, ctx.timing_read()
+    return dt, stats, ctx.timing_read(), Us[-1]
 
 
 def batched(args):
@@ -348,8 +349,12 @@ def main():
     # The same solve with the FP32 inner V-cycle (hierarchy and smoother in
     # FP32, residual, update and stop test in FP64).
     ctx32 = nmg.Context.from_problem(prob, inner_fp32=1)
-    dt32, st32, tm32 = timed_solves(ctx32, z, U0, args.steps, args.warmup, args.tol,
-                                    args.timing_cap)
+    dt32, st32, tm32, U32 = timed_solves(ctx32, z, U0, args.steps, args.warmup, args.tol,
+                                         args.timing_cap)
+    # error of the FP32-inner steady state against the FP64 one (which equals
+    # the FP64 oracle's bit for bit): largest cell difference per component
+    dU = (U32 - Us[-1]).abs().amax(dim=(1, 2)).tolist()
+    scale = Us[-1].abs().amax(dim=(1, 2)).tolist()
     ok32 = all(st["status"] == "OK" for st in st32)
     avg32 = tm32["ms"] / max(1, tm32["launches"])
     bpl32 = tm32["cells"] / max(1, tm32["launches"]) * SGS_BYTES_2D_FP32
@@ -358,6 +363,8 @@ def main():
         "value": (args.steps / dt32) if ok32 else None, "unit": "solves/s",
         "ms_per_step": 1e3 * dt32 / args.steps, "converged": ok32,
         "newton_steps": st32[-1]["newton_steps"], "final_res_l1": st32[-1]["res_l1"],
+        "max_abs_diff_vs_fp64": {"h": dU[0], "hu": dU[1], "hv": dU[2]},
+        "max_abs_fp64": {"h": scale[0], "hu": scale[1], "hv": scale[2]},
         "roofline": {"bound": "hbm", "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (ach32 / HBM_PEAK_GBS) if ach32 else None,
                      "avg_launch_us": avg32 * 1e3, "bytes_per_launch": bpl32},
