@@ -325,6 +325,20 @@ def test_full_size_benchmark_cycles(nmg):
          "dU after two W-cycles 1024^2")
 
 
+def test_vcycle_long_smoothing_bitwise(nmg, monkeypatch):
+    """A smoothing call of more than 16 iterations on a launched level (here
+    the coarsest, 40 iterations, no coarse kernel) is planned without fused
+    launches; the result is unchanged."""
+    prob, A, b, x0 = random_case(2, 96, 40, 9, 2)
+    monkeypatch.setenv("NMG_COARSE_CELLS", "0")
+    p = dict(prob.params, nu1=2, nu2=2, nu_coarse=40, gamma=2)
+    ctx = nmg.Context.from_problem(prob, **p)
+    ctx.load_system(dev(A), dev(b))
+    x = dev(x0)
+    ctx.mg_vcycle(x, 2)
+    same(host(x), oracle.vcycles(A, b, x0, p, 2), "x after cycles with nu_coarse = 40")
+
+
 # --- FP32 inner V-cycle (hierarchy and smoother in FP32, Newton in FP64) ---
 
 @pytest.mark.parametrize("case", LIN + TILED)
