@@ -1147,17 +1147,49 @@ struct RegCell {
 // level: restrict_cell's sums in its child order, the children's residuals
 // exchanged through the same LDS area.  The caller's barrier follows.
 template <class T, int NC>
+__device__ __forceinline__ void reg_run_body(const CoarseOp &op, const LevelGeom &G,
+                                             const T *A, const T *b, T *x, const LevelGeom &Gc,
+                                             T *bc, const T *xc, T *xl,
+                                             const RegCell<T, NC> &red,
+                                             const RegCell<T, NC> &black);
+
+// KEEP: the block rows live in *keep (loaded by the first run of the
+// program, *loaded set); otherwise they are loaded here for this run.
+template <class T, int NC, bool KEEP>
 __device__ __forceinline__ void coarse_reg_run(const CoarseOp &op, const LevelGeom &G,
                                                const T *A, const T *b, T *x, const LevelGeom &Gc,
-                                               T *bc, const T *xc, T *xl)
+                                               T *bc, const T *xc, T *xl, RegCell<T, NC> *keep,
+                                               bool *loaded)
 {
     const int t = (int)threadIdx.x;
     const int nv = 2 * NC * (int)G.plane;
     for (int k = t; k < nv; k += kCoarseBlock) xl[k] = x[k];
-    RegCell<T, NC> red, black;
-    red.load(G, A, 0, t);
-    black.load(G, A, 1, t);
-    __syncthreads();
+    if constexpr (KEEP) {
+        if (!*loaded) {
+            keep[0].load(G, A, 0, t);
+            keep[1].load(G, A, 1, t);
+            *loaded = true;
+        }
+        __syncthreads();
+        reg_run_body<T, NC>(op, G, A, b, x, Gc, bc, xc, xl, keep[0], keep[1]);
+    } else {
+        RegCell<T, NC> red, black;
+        red.load(G, A, 0, t);
+        black.load(G, A, 1, t);
+        __syncthreads();
+        reg_run_body<T, NC>(op, G, A, b, x, Gc, bc, xc, xl, red, black);
+    }
+}
+
+template <class T, int NC>
+__device__ __forceinline__ void reg_run_body(const CoarseOp &op, const LevelGeom &G,
+                                             const T *A, const T *b, T *x, const LevelGeom &Gc,
+                                             T *bc, const T *xc, T *xl,
+                                             const RegCell<T, NC> &red,
+                                             const RegCell<T, NC> &black)
+{
+    const int t = (int)threadIdx.x;
+    const int nv = 2 * NC * (int)G.plane;
     if (op.color == 0) red.first(op.mode, G, b, xl, 0, Gc, xc, t);
     else black.first(op.mode, G, b, xl, 1, Gc, xc, t);
     __syncthreads();
@@ -1218,6 +1250,26 @@ struct LdsLevel {
     }
 };
 
+// COP_REGRUN on level Ld (global) with the next level Lc (LDS or global).
+template <class T, int NC, bool KEEP>
+__device__ __forceinline__ void coarse_reg_level(const CoarseOp &op, const LevelDev &Ld,
+                                                 const LevelDev &Lc, char *lds,
+                                                 RegCell<T, NC> *keep, bool *loaded)
+{
+    T *xl = (T *)(lds + op.lds_off);
+    if (Lc.lds_off >= 0) {
+        const LdsLevel<T, NC> Cl(lds, Lc);
+        coarse_reg_run<T, NC, KEEP>(op, Ld.G, in_global((const T *)Ld.A),
+                                    in_global((const T *)Ld.b), in_global((T *)Ld.x), Lc.G, Cl.b,
+                                    Cl.x, xl, keep, loaded);
+    } else {
+        coarse_reg_run<T, NC, KEEP>(op, Ld.G, in_global((const T *)Ld.A),
+                                    in_global((const T *)Ld.b), in_global((T *)Ld.x), Lc.G,
+                                    in_global((T *)Lc.b), in_global((const T *)Lc.x), xl, keep,
+                                    loaded);
+    }
+}
+
 // The coarse levels of a cycle in one workgroup: the host records the exact
 // sequence of half sweeps, restrictions and colour fixes that the
 // level-by-level launches would perform, and this kernel executes it with a
@@ -1269,6 +1321,9 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
         }
         __syncthreads();
     }
+    constexpr bool kKeepRegRuns = sizeof(T) == 4;
+    RegCell<T, NC> keep[kKeepRegRuns ? 2 : 1];      // unused in FP64
+    bool keep_loaded = false;
     for (int q = 0; q < nops; ++q) {
         const CoarseOp op = ops[q];
         const LevelDev &Ld = lv[op.level];
@@ -1277,17 +1332,10 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
             const LdsLevel<T, NC> F(lds, Ld);
             coarse_run<T, NC>(op, Ld.G, F.A, F.Ai, F.b, F.x);
         } else if (op.kind == COP_REGRUN) {
-            T *xl = (T *)(lds + op.lds_off);
-            if (Lc.lds_off >= 0) {
-                const LdsLevel<T, NC> Cl(lds, Lc);
-                coarse_reg_run<T, NC>(op, Ld.G, in_global((const T *)Ld.A),
-                                      in_global((const T *)Ld.b), in_global((T *)Ld.x), Lc.G,
-                                      Cl.b, Cl.x, xl);
-            } else {
-                coarse_reg_run<T, NC>(op, Ld.G, in_global((const T *)Ld.A),
-                                      in_global((const T *)Ld.b), in_global((T *)Ld.x), Lc.G,
-                                      in_global((T *)Lc.b), in_global((const T *)Lc.x), xl);
-            }
+            // FP32: the level's block rows stay in registers from the first
+            // run to the end of the program; FP64: reloaded per run (the
+            // register file holds them only while no other level's run does)
+            coarse_reg_level<T, NC, kKeepRegRuns>(op, Ld, Lc, lds, keep, &keep_loaded);
         } else if (Ld.lds_off >= 0) {
             const LdsLevel<T, NC> F(lds, Ld), Cl(lds, Lc);
             coarse_op<T, NC, true>(op, Ld.G, Lc.G, F.A, F.Ai, F.b, F.x, Cl.b, Cl.x);
