@@ -139,6 +139,10 @@ typedef struct {
  *                     every level launched on its own);
  *   NMG_COARSE_REG    0 turns off register-resident runs on that kernel's
  *                     first level (default on);
+ *   NMG_COARSE_SPLIT  0 gives every cell of the LDS-resident coarsest level
+ *                     one lane in its runs of half sweeps (default: two
+ *                     lanes per cell in 2D where the level has at most 128
+ *                     cells per colour);
  *   NMG_FUSE          most half sweeps per launch on the launched coarse
  *                     levels: 3 (default), 2 or 1. */
 int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,

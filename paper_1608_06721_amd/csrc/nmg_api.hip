@@ -49,6 +49,7 @@ struct nmg_ctx {
     int dim = 0, nc = 0, nb = 0, ne = 0, NL = 0;
     bool f32 = false;                 // FP32 inner V-cycle
     int fuse = 3;                     // most half sweeps per launch on launched coarse levels
+    int split = 1;                    // coarsest-level runs may use two lanes per cell
     Level L[16];
     void *pool = nullptr;             // the hierarchy's allocation
     void *At_alloc = nullptr;         // second level-0 matrix (adjoint transpose), owned
@@ -484,6 +485,7 @@ void merge_runs(nmg_ctx *c, bool fits)
                 ++e;
             o.kind = COP_RUN;
             o.count = e - q;
+            o.aux = c->split;
             q = e;
         } else {
             ++q;
@@ -977,6 +979,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
 
     c->f32 = params->inner_fp32 != 0;
     if (const char *e = std::getenv("NMG_FUSE")) c->fuse = std::atoi(e);
+    if (const char *e = std::getenv("NMG_COARSE_SPLIT")) c->split = std::atoi(e) != 0;
     const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
     size_t total = 0;   // elements
     for (int l = 0; l <= c->NL; ++l) {

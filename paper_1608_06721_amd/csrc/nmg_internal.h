@@ -70,8 +70,8 @@ constexpr int kMaxLevels = 16;
 constexpr int kMaxCoarseOps = 1 << 16;  // longest recorded coarse program
 // LDS bytes of the coarse-cycle kernel for level data: the coarsest levels
 // whose blocks, block inverses and vectors fit are copied in and run from
-// LDS (gfx950 allows 160 KB per workgroup).
-constexpr long kCoarseLdsBytes = 160 * 1024;
+// LDS (gfx950 allows 160 KB per workgroup; 16 bytes stay for a zero slot).
+constexpr long kCoarseLdsBytes = 160 * 1024 - 16;
 
 // Device-side description of one level (for the coarse-cycle kernel); the
 // arrays hold the hierarchy's scalar type (double, or float for the FP32
@@ -87,7 +87,9 @@ struct LevelDev {
 // One operation of the recorded coarse part of a cycle.  COP_RUN is count
 // consecutive half sweeps of alternating colour on an LDS-resident level
 // with a thread per cell, the first of them in `mode` (any start mode for
-// COP_REGRUN, normal or zero start for COP_RUN) and the rest normal.
+// COP_REGRUN, normal or zero start for COP_RUN) and the rest normal; for
+// COP_RUN, aux = 1 allows two lanes per cell (3x3 blocks, where the level
+// has at most kCoarseBlock / 4 cells per colour).
 // COP_REGRUN is the same on a level in global memory with at most one slot
 // per colour and thread, whose block rows stay in registers and whose x
 // moves to the LDS bytes at lds_off for the run; aux = 1 appends the
@@ -100,7 +102,7 @@ struct CoarseOp {
     int color;              // SGS / FIX: colour; RUN, REGRUN: colour of the first half sweep
     int mode;               // SGS / RUN / REGRUN: SweepMode; FIX: 0 zero, 1 add parent, 2 set parent
     int count;              // RUN, REGRUN: number of half sweeps
-    int aux;                // REGRUN: 1 if the restriction follows
+    int aux;                // REGRUN: 1 if the restriction follows; RUN: 1 allows two lanes per cell
     int lds_off;            // REGRUN: byte offset of the run's x / exchange area in LDS
 };
 

@@ -893,13 +893,32 @@ __global__ void __launch_bounds__(kBlock) k_fix_color(LevelGeom G, int op, T *__
     fix_cell<T, NC>(G, op, x, color, Gc, xc, t);
 }
 
-// A pointer known to address global memory: the round trip through the
-// global address space lets the compiler use global (not generic) loads and
-// stores for everything derived from it.
+// A pointer known to address global memory.  Its bits are taken as a
+// global-address-space pointer (a global address is the same value in the
+// generic space) and converted back, so the compiler uses global (not
+// generic) loads and stores for everything derived from it.  A plain cast
+// to the global space and back is folded away and leaves generic accesses,
+// whose completion the LDS wait counter also tracks.
 template <class T>
 __device__ __forceinline__ T *in_global(T *p)
 {
-    return (T *)(__attribute__((address_space(1))) T *)p;
+    __attribute__((address_space(1))) void *g;
+    __builtin_memcpy(&g, &p, sizeof(g));
+    return (T *)g;
+}
+
+// A batch level entry with its arrays as global pointers (in_global).
+__device__ __forceinline__ BatchLevel global_view(const BatchLevel &L)
+{
+    BatchLevel J = L;
+    J.A = in_global(L.A);
+    J.b = in_global(L.b);
+    J.x = in_global(L.x);
+    J.Ac = in_global(L.Ac);
+    J.bc = in_global(L.bc);
+    J.xc = in_global(L.xc);
+    J.xt = in_global(L.xt);
+    return J;
 }
 
 // One recorded operation on level G (blocks A, inverse data Ai when INV,
@@ -1004,6 +1023,130 @@ __device__ __forceinline__ void coarse_run(const CoarseOp &op, const LevelGeom &
     }
 }
 
+// Exchange a value with the neighbouring lane of the pair (lanes 2m, 2m+1).
+template <class T>
+__device__ __forceinline__ T swap_pair(T v)
+{
+    constexpr int kSwap = 0xB1;     // quad_perm [1, 0, 3, 2]
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, kSwap, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), kSwap, 0xF, 0xF, false);
+        return __builtin_bit_cast(T, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), kSwap,
+                                                              0xF, 0xF, false));
+    }
+}
+
+// coarse_run for 3x3 blocks with two lanes per cell (4 * plane <= kCoarseBlock):
+// lane 0 of a pair sums rows 0 and 1 of b_i - sum_j A_ij x_j, lane 1 row 2
+// (its second row is a zero row that nothing reads); the pair swaps the
+// three right-hand sides and each lane applies its rows of the inverse data.
+// A half sweep then occupies twice as many waves with about half the
+// instructions each, so all four SIMDs share it.  Every row's sum, the
+// right-hand side and the products with the inverse data are the
+// operations of gs_update and solve_inv in their order, so the result is
+// bit for bit that of coarse_run.  A missing face reads the zero at zslot
+// instead of selecting zero.
+template <class T>
+__device__ __forceinline__ void coarse_run_split(const CoarseOp &op, const LevelGeom &G,
+                                                 const T *A, const T *Ai, const T *b, T *x,
+                                                 const T *zslot)
+{
+    constexpr int NC = 3, NF = 4, NN = 9, NE = 45, NI = inv_entries(3);
+    const int plane = (int)G.plane;
+    const int tau = (int)threadIdx.x >> 1, h = (int)threadIdx.x & 1;
+    const int color = tau < plane ? 0 : 1;
+    const int t = tau - color * plane;
+    const int j = t / G.W, k = t - (t / G.W) * G.W;
+    const int i = 2 * k + ((j + color) & 1);
+    const bool mine = tau < 2 * plane && i < G.nx;
+    const T *xo = x + (color ^ 1) * NC * plane;
+    const T *src[NF][NC];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        int ni = i, nj = j;
+        bool ok;
+        if (f == FW) { ni = i - 1; ok = i > 0; }
+        else if (f == FE) { ni = i + 1; ok = i + 1 < G.nx; }
+        else if (f == FS) { nj = j - 1; ok = j > 0; }
+        else { nj = j + 1; ok = j + 1 < G.ny; }
+        const int q = nj * G.W + (ni >> 1);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) src[f][c] = ok ? xo + c * plane + q : zslot;
+    }
+    // this lane's rows: 2h and (h == 0 only) 1
+    T a[2][NF * NC], inv[2][NC], bv[2], idet = T(0);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+#pragma unroll
+        for (int e = 0; e < NF * NC; ++e) a[r][e] = T(0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) inv[r][c] = T(0);
+        bv[r] = T(0);
+    }
+    if (mine) {
+        const T *Am = A + mat_off(G, NE, color, t);
+        const T *Im = Ai + mat_off(G, NI, color, t);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int row = r == 0 ? 2 * h : 1;
+            if (r == 1 && h) break;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    a[r][f * NC + c] = Am[(((f + 1) * NC + row) * NC + c) * kTile];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) inv[r][c] = Im[(NC * row + c) * kTile];
+            bv[r] = b[(color * NC + row) * plane + t];
+        }
+        idet = Im[NN * kTile];
+    }
+    const bool sing = idet != idet;
+    T *xm = x + color * NC * plane + t;
+    for (int s = 0; s < op.count; ++s) {
+        if (mine && color == (op.color ^ (s & 1))) {
+            T acc[2] = {T(0), T(0)};
+            if (!(s == 0 && op.mode == MODE_ZERO)) {
+                T v[NF][NC];
+#pragma unroll
+                for (int f = 0; f < NF; ++f)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) v[f][c] = *src[f][c];
+                // all twelve reads in flight before the arithmetic (one LDS
+                // round trip instead of the scheduler's three)
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    T p[2][NC];
+#pragma unroll
+                    for (int r = 0; r < 2; ++r)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) p[r][c] = a[r][f * NC + c] * v[f][c];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+#pragma unroll
+                        for (int r = 0; r < 2; ++r) acc[r] = acc[r] + p[r][c];
+                }
+            }
+            const T own0 = bv[0] - acc[0], own1 = bv[1] - acc[1];
+            const T oth0 = swap_pair(own0), oth1 = swap_pair(own1);
+            const T r0 = h ? oth0 : own0, r1 = h ? oth1 : own1, r2 = h ? own0 : oth0;
+            T xr[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                xr[r] = (inv[r][0] * r0 + inv[r][1] * r1 + inv[r][2] * r2) * idet;
+                xr[r] = sing ? T(0) : xr[r];
+            }
+            xm[2 * h * plane] = xr[0];
+            if (!h) xm[plane] = xr[1];
+        }
+        if (s + 1 < op.count) __syncthreads();
+    }
+}
+
 // One cell of a register-resident run: the cell of colour `color` at slot
 // threadIdx.x of a level in global memory (if it exists), its off-diagonal
 // blocks and the inverse data of its diagonal block (block_inverse), loaded
@@ -1043,7 +1186,7 @@ struct RegCell {
         where(G, color, t, i, j);
         mine = t < G.plane && i < G.nx;
         if (mine) {
-            const T *Am = A + mat_off(G, NE, color, t);
+            const T *Am = in_global(A) + mat_off(G, NE, color, t);
             T D[NN];
 #pragma unroll
             for (int e = 0; e < NN; ++e) D[e] = Am[e * kTile];
@@ -1078,8 +1221,9 @@ struct RegCell {
                 }
             }
         }
+        const T *bg = in_global(b);
 #pragma unroll
-        for (int r = 0; r < NC; ++r) bv[r] = b[((long)color * NC + r) * G.plane + t];
+        for (int r = 0; r < NC; ++r) bv[r] = bg[((long)color * NC + r) * G.plane + t];
         gs_update<T, NC, MODE == MODE_ZERO, true>(a, inv, bv, v, ok, xi);
         T *xm = x + (long)color * NC * G.plane + t;
 #pragma unroll
@@ -1105,7 +1249,8 @@ struct RegCell {
     {
         int i, j;
         where(G, color, t, i, j);
-        const T *Am = A + mat_off(G, NE, color, t);
+        const T *Am = in_global(A) + mat_off(G, NE, color, t);
+        const T *bg = in_global(b);
         const T *xm = x + (long)color * NC * G.plane + t;
         const T *xo = x + (long)(color ^ 1) * NC * G.plane;
         T xi[NC], acc[NC];
@@ -1117,24 +1262,32 @@ struct RegCell {
 #pragma unroll
             for (int c = 0; c < NC; ++c) acc[q] = acc[q] + Am[(q * NC + c) * kTile] * xi[c];
         }
+        // every face's values are read at once (a missing face reads a valid
+        // slot and takes zero); a missing face has a zero block, so its +0
+        // terms leave acc as lin_residual_cell's skipped face does (acc
+        // starts at +0 and never becomes -0)
+        T v[NF][NC];
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             int ni, nj;
             bool ok;
             face(G, i, j, f, ni, nj, ok);
-            if (!ok) continue;
-            const T *p = xo + (long)nj * G.W + (ni >> 1);
-            T v[NC];
+            const long q = ok ? (long)nj * G.W + (ni >> 1) : (long)t;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) v[c] = p[c * G.plane];
+            for (int c = 0; c < NC; ++c) {
+                const T val = xo[c * G.plane + q];
+                v[f][c] = ok ? val : T(0);
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int q = 0; q < NC; ++q)
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
-                    acc[q] = acc[q] + a[((f + 1) * NC + q) * NC + c] * v[c];
-        }
+                    acc[q] = acc[q] + a[((f + 1) * NC + q) * NC + c] * v[f][c];
 #pragma unroll
-        for (int q = 0; q < NC; ++q) r[q] = b[((long)color * NC + q) * G.plane + t] - acc[q];
+        for (int q = 0; q < NC; ++q) r[q] = bg[((long)color * NC + q) * G.plane + t] - acc[q];
     }
 };
 
@@ -1295,9 +1448,11 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
     constexpr int NE = (NF + 1) * NN;
     constexpr int NI = inv_entries(NC);
     __shared__ __attribute__((aligned(16))) char lds[kCoarseLdsBytes];
+    __shared__ T zslot[1];       // a zero that split runs read for missing faces
     if (active && !active[blockIdx.x]) return;
     lv += (long)blockIdx.x * kMaxLevels;
     if (l_lds >= 0) {
+        if (threadIdx.x == 0) zslot[0] = T(0);
         for (int l = l_lds; l <= nl; ++l) {
             const LevelDev &L = lv[l];
             const LdsLevel<T, NC> S(lds, L);
@@ -1330,6 +1485,13 @@ __global__ void __launch_bounds__(kCoarseBlock) k_coarse_cycle(const CoarseOp *_
         const LevelDev &Lc = lv[op.level < nl ? op.level + 1 : op.level];
         if (op.kind == COP_RUN) {
             const LdsLevel<T, NC> F(lds, Ld);
+            if constexpr (NC == 3) {
+                if (op.aux && 4 * Ld.G.plane <= kCoarseBlock) {
+                    coarse_run_split<T>(op, Ld.G, F.A, F.Ai, F.b, F.x, zslot);
+                    __syncthreads();
+                    continue;
+                }
+            }
             coarse_run<T, NC>(op, Ld.G, F.A, F.Ai, F.b, F.x);
         } else if (op.kind == COP_REGRUN) {
             // FP32: the level's block rows stay in registers from the first
@@ -2036,7 +2198,7 @@ __global__ void __launch_bounds__(kBlock) kb_isolated(const BatchInst *__restric
     if (!active[it.inst]) return;
     const BatchInst &I = bi[it.inst];
     const long idx = (long)it.tile * kBlock + threadIdx.x;
-    if (idx < (long)I.P.nx * I.P.ny) isolated_cell<NC>(I.P, I.z, I.U, I.iso, idx);
+    if (idx < (long)I.P.nx * I.P.ny) isolated_cell<NC>(I.P, in_global(I.z), in_global(I.U), in_global(I.iso), idx);
 }
 
 template <int NC, class T>
@@ -2051,7 +2213,8 @@ __global__ void __launch_bounds__(kBlock) kb_assemble(const BatchInst *__restric
     const long idx = (long)it.tile * kBlock + threadIdx.x;
     double nrm = 0.0;
     if (idx < (long)I.P.nx * I.P.ny)
-        nrm = assemble_cell<NC, T>(I.P, I.G0, I.z, I.U, I.iso, (T *)I.A, (T *)I.b, nullptr, idx);
+        nrm = assemble_cell<NC, T>(I.P, I.G0, in_global(I.z), in_global(I.U), in_global(I.iso),
+                                  in_global((T *)I.A), in_global((T *)I.b), nullptr, idx);
     double s = block_sum(nrm);
     if (threadIdx.x == 0) partial[pos] = s;
 }
@@ -2067,7 +2230,7 @@ __global__ void __launch_bounds__(kBlock) kb_residual(const BatchInst *__restric
     const BatchInst &I = bi[it.inst];
     const long idx = (long)it.tile * kBlock + threadIdx.x;
     double nrm = 0.0;
-    if (idx < (long)I.P.nx * I.P.ny) nrm = residual_cell<NC>(I.P, I.z, I.U, nullptr, idx);
+    if (idx < (long)I.P.nx * I.P.ny) nrm = residual_cell<NC>(I.P, in_global(I.z), in_global(I.U), nullptr, idx);
     double s = block_sum(nrm);
     if (threadIdx.x == 0) partial[pos] = s;
 }
@@ -2082,7 +2245,7 @@ __global__ void __launch_bounds__(kBlock) kb_count_iso(const BatchInst *__restri
     if (!active[it.inst]) return;
     const BatchInst &I = bi[it.inst];
     const long idx = (long)it.tile * kBlock + threadIdx.x;
-    double c = (idx < (long)I.P.nx * I.P.ny && I.iso[idx]) ? 1.0 : 0.0;
+    double c = (idx < (long)I.P.nx * I.P.ny && in_global(I.iso)[idx]) ? 1.0 : 0.0;
     double s = block_sum(c);
     if (threadIdx.x == 0) partial[pos] = s;
 }
@@ -2113,7 +2276,7 @@ __global__ void __launch_bounds__(kBlock) kb_blu_half(const BatchInst *__restric
     if (!active[it.inst]) return;
     const BatchInst &I = bi[it.inst];
     const long t = (long)it.tile * kBlock + threadIdx.x;
-    if (t < I.G0.plane) blu_cell<NC>(I.P, I.z, I.U, color, t);
+    if (t < I.G0.plane) blu_cell<NC>(I.P, in_global(I.z), in_global(I.U), color, t);
 }
 
 template <int NC, class T>
@@ -2125,7 +2288,7 @@ __global__ void __launch_bounds__(kBlock) kb_update(const BatchInst *__restrict_
     if (!active[it.inst]) return;
     const BatchInst &I = bi[it.inst];
     const long idx = (long)it.tile * kBlock + threadIdx.x;
-    if (idx < (long)I.P.nx * I.P.ny) update_cell<NC, T>(I.P, I.G0, (const T *)I.x, I.U, idx);
+    if (idx < (long)I.P.nx * I.P.ny) update_cell<NC, T>(I.P, I.G0, in_global((const T *)I.x), in_global(I.U), idx);
 }
 
 template <int NC>
@@ -2138,7 +2301,7 @@ __global__ void __launch_bounds__(kBlock) kb_threshold(const BatchInst *__restri
     if (!active[it.inst]) return;
     const BatchInst &I = bi[it.inst];
     const long idx = (long)it.tile * kBlock + threadIdx.x;
-    if (idx < (long)I.P.nx * I.P.ny) threshold_cell<NC>(I.P, I.U, idx);
+    if (idx < (long)I.P.nx * I.P.ny) threshold_cell<NC>(I.P, in_global(I.U), idx);
 }
 
 template <int NC>
@@ -2155,10 +2318,11 @@ __global__ void __launch_bounds__(kBlock) kb_copy_state(const BatchInst *__restr
     if (idx >= N) return;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+        double *U = in_global(I.U), *Ulast = in_global(I.Ulast);
         if (dir == 0)
-            I.Ulast[c * N + idx] = I.U[c * N + idx];
+            Ulast[c * N + idx] = U[c * N + idx];
         else
-            I.U[c * N + idx] = I.Ulast[c * N + idx];
+            U[c * N + idx] = Ulast[c * N + idx];
     }
 }
 
@@ -2169,7 +2333,7 @@ __global__ void __launch_bounds__(TB) kb_sgs_half(const BatchLevel *__restrict__
     int pos;
     const WorkItem it = work_item(w, pos);
     if (!active[it.inst]) return;
-    const BatchLevel &L = lv[it.inst];
+    const BatchLevel L = global_view(lv[it.inst]);
     const long t = (long)it.tile * TB + threadIdx.x;
     if (t < L.G.plane)
         sgs_cell<T, NC, MODE>(L.G, (const T *)L.A, nullptr, (const T *)L.b, (T *)L.x, color, L.Gc,
@@ -2185,7 +2349,7 @@ __global__ void __launch_bounds__(kPairThreads) kb_sgs_pair(const BatchLevel *__
     int pos;
     const WorkItem it = work_item(w, pos);
     if (!active[it.inst]) return;
-    const BatchLevel &L = lv[it.inst];
+    const BatchLevel L = global_view(lv[it.inst]);
     const int ntx = (L.G.nx + kPairTX - 1) / kPairTX;
     T *x2 = (T *)L.x + (long)(color ^ 1) * 3 * L.G.plane;
     const T *xin = flip ? (const T *)L.xt : x2;
@@ -2203,7 +2367,7 @@ __global__ void __launch_bounds__(kBlock) kb_restrict(const BatchLevel *__restri
     int pos;
     const WorkItem it = work_item(w, pos);
     if (!active[it.inst]) return;
-    const BatchLevel &L = lv[it.inst];
+    const BatchLevel L = global_view(lv[it.inst]);
     // tiles of kBlock children = kBlock / nch coarse cells
     restrict_block<T, NC>(L.G, (const T *)L.A, (const T *)L.b, (const T *)L.x, L.Gc, (T *)L.bc,
                           (long)it.tile * (kBlock / ((NC == 2) ? 2 : 4)));
@@ -2218,7 +2382,7 @@ __global__ void __launch_bounds__(kBlock) kb_fix_color(const BatchLevel *__restr
     int pos;
     const WorkItem it = work_item(w, pos);
     if (!active[it.inst]) return;
-    const BatchLevel &L = lv[it.inst];
+    const BatchLevel L = global_view(lv[it.inst]);
     const long t = (long)it.tile * kBlock + threadIdx.x;
     if (t < L.G.plane) fix_cell<T, NC>(L.G, op, (T *)L.x, color, L.Gc, (const T *)L.xc, t);
 }
@@ -2231,7 +2395,7 @@ __global__ void __launch_bounds__(kBlock) kb_galerkin(const BatchLevel *__restri
     int pos;
     const WorkItem it = work_item(w, pos);
     if (!active[it.inst]) return;
-    const BatchLevel &L = lv[it.inst];
+    const BatchLevel L = global_view(lv[it.inst]);
     const long t = (long)it.tile * kBlock + threadIdx.x;
     if (t < (long)L.Gc.nx * L.Gc.ny) galerkin_cell<T, NC>(L.G, (const T *)L.A, L.Gc, (T *)L.Ac, t);
 }

@@ -177,7 +177,13 @@ def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, gamma, fuse, monke
 # the level's block rows in registers (COP_REGRUN); NMG_COARSE_REG=0 runs the
 # same operations one by one.  nu1 = 0 leaves a restriction with no run
 # before it, nu2 = 0 a level whose correction is fixed up at the end.
-REG = [(2, 64, 64, 5, 2), (2, 64, 48, 6, 3), (1, 2048, 1, 7, 2), (2, 120, 80, 10, 3)]
+# The coarsest level's runs use two lanes per cell where it has at most 128
+# cells per colour (16x16, 8x6, the odd 15x10) and one lane per cell beyond
+# that or in 1D: 18x16 (144 per colour, below a launched 36x32 level) fits
+# LDS only in FP32 and runs one lane per cell there, from global memory in
+# FP64.  NMG_COARSE_SPLIT=0 runs one lane per cell everywhere.
+REG = [(2, 64, 64, 5, 2), (2, 64, 48, 6, 3), (1, 2048, 1, 7, 2), (2, 120, 80, 10, 3),
+       (2, 72, 64, 11, 2)]
 
 
 @pytest.mark.parametrize("case", REG)
@@ -185,11 +191,13 @@ REG = [(2, 64, 64, 5, 2), (2, 64, 48, 6, 3), (1, 2048, 1, 7, 2), (2, 120, 80, 10
 @pytest.mark.parametrize("gamma", [1, 2, 3])
 @pytest.mark.parametrize("reg", ["1", "0"])
 @pytest.mark.parametrize("fp32", [0, 1])
-def test_vcycle_register_runs_bitwise(nmg, case, nus, gamma, reg, fp32, monkeypatch):
+@pytest.mark.parametrize("split", ["1", "0"])
+def test_vcycle_register_runs_bitwise(nmg, case, nus, gamma, reg, fp32, split, monkeypatch):
     prob, A, b, x0 = random_case(*case)
-    say("vcycle register runs", case, nus, gamma, reg, fp32)
+    say("vcycle register runs", case, nus, gamma, reg, fp32, split)
     monkeypatch.setenv("NMG_COARSE_CELLS", "1024")
     monkeypatch.setenv("NMG_COARSE_REG", reg)
+    monkeypatch.setenv("NMG_COARSE_SPLIT", split)
     p = dict(prob.params, nu1=nus[0], nu2=nus[1], nu_coarse=nus[2], gamma=gamma,
              inner_fp32=fp32)
     ctx = nmg.Context.from_problem(prob, **p)
