@@ -178,12 +178,13 @@ def test_vcycle_bitwise(nmg, case, nus, cycles, coarse_cells, gamma, fuse, monke
 # same operations one by one.  nu1 = 0 leaves a restriction with no run
 # before it, nu2 = 0 a level whose correction is fixed up at the end.
 # The coarsest level's runs use two lanes per cell where it has at most 128
-# cells per colour (16x16, 8x6, the odd 15x10) and one lane per cell beyond
+# cells per colour (16x16, 8x6, the odd 15x10, 14x10 and the odd-by-odd 11x9
+# under register-run 28x20 and 22x18 levels) and one lane per cell beyond
 # that or in 1D: 18x16 (144 per colour, below a launched 36x32 level) fits
 # LDS only in FP32 and runs one lane per cell there, from global memory in
 # FP64.  NMG_COARSE_SPLIT=0 runs one lane per cell everywhere.
 REG = [(2, 64, 64, 5, 2), (2, 64, 48, 6, 3), (1, 2048, 1, 7, 2), (2, 120, 80, 10, 3),
-       (2, 72, 64, 11, 2)]
+       (2, 72, 64, 11, 2), (2, 56, 40, 12, 2), (2, 44, 36, 13, 2)]
 
 
 @pytest.mark.parametrize("case", REG)
