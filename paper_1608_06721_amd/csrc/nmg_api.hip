@@ -52,6 +52,11 @@ struct nmg_ctx {
     int split = 1;                    // coarsest-level runs may use two lanes per cell
     Level L[16];
     void *pool = nullptr;             // the hierarchy's allocation
+    // residuals of one colour of level res_level, written by the last half
+    // sweep of a pre-smoothing for the restriction that follows it (NC planes
+    // of level 0's size in the hierarchy's type; -1: none valid)
+    void *rres = nullptr;
+    int res_level = -1, res_color = -1;
     void *At_alloc = nullptr;         // second level-0 matrix (adjoint transpose), owned
     void *At_spare = nullptr;         // whichever of the two level-0 matrices is not L[0].A
     // Algorithm 1, Step 1 (allocated on first use): coarse beds and states
@@ -179,10 +184,13 @@ int check_params(const nmg_grid *g, const nmg_bc *bc, const nmg_params *p, std::
 
 // ---- multigrid on the colour-split hierarchy -----------------------------
 
-int halfsweep(nmg_ctx *c, int l, int color)
+// res: the caller's restriction follows; a normal-mode launch then also
+// writes the updated cells' residuals (c->rres), which it reads instead.
+int halfsweep(nmg_ctx *c, int l, int color, bool res = false)
 {
     Level &Lv = c->L[l];
     if (Lv.last == color) return NMG_OK;   // same colour again: result identical, elide
+    if (c->res_level == l) c->res_level = -1;
     int oc = color ^ 1;
     int mode;
     switch (Lv.st[oc]) {
@@ -209,16 +217,26 @@ int halfsweep(nmg_ctx *c, int l, int color)
         Lv.last = color;
         return NMG_OK;
     }
+    res = res && mode == MODE_NORMAL && c->rres;
     // Measurement hook: full half sweeps (all neighbour blocks read) of the
     // finest level.  A run of them launched back to back (within one
     // smoothing call) shares one pair of events around the whole run.
-    const bool want = c->timing && l == 0 && mode == MODE_NORMAL;
+    const bool want = c->timing && l == 0 && mode == MODE_NORMAL && !res;
     const bool open = want && c->tgroup >= 0;
     const int k = open ? c->tgroup : c->nrec;
     const bool rec = want && k < (int)c->ev.size();
     if (rec && !open) HIPCHK(c, hipEventRecord(c->ev[k].first, c->stream));
-    HIPCHK(c, launch_sgs_half(c->dim, c->f32, mode, Lv.G, Lv.A, Lv.b, Lv.x, color, Lc.G, Lc.x,
-                              stream_level(cells(Lv.G), c->nc, c->f32 ? 4 : 8), c->stream));
+    if (res) {
+        HIPCHK(c, launch_sgs_half_res(c->dim, c->f32, Lv.G, Lv.A, Lv.b, Lv.x, color, c->rres,
+                                      stream_level(cells(Lv.G), c->nc, c->f32 ? 4 : 8),
+                                      c->stream));
+        c->res_level = l;
+        c->res_color = color;
+    } else {
+        HIPCHK(c, launch_sgs_half(c->dim, c->f32, mode, Lv.G, Lv.A, Lv.b, Lv.x, color, Lc.G,
+                                  Lc.x, stream_level(cells(Lv.G), c->nc, c->f32 ? 4 : 8),
+                                  c->stream));
+    }
     if (rec) {
         HIPCHK(c, hipEventRecord(c->ev[k].second, c->stream));
         long n = 0;
@@ -237,7 +255,7 @@ int halfsweep(nmg_ctx *c, int l, int color)
     return NMG_OK;
 }
 
-int smooth_single(nmg_ctx *c, int l, int iters);
+int smooth_single(nmg_ctx *c, int l, int iters, bool res_last = false);
 
 // Whether the half sweeps of level l are launched as fused pairs: 2D levels
 // launched level by level whose half sweep is bound by launch latency rather
@@ -346,19 +364,20 @@ int smooth_pairs(nmg_ctx *c, int l, int iters)
     return NMG_OK;
 }
 
-int smooth(nmg_ctx *c, int l, int iters)
+// res_last: a restriction from level l follows (see halfsweep).
+int smooth(nmg_ctx *c, int l, int iters, bool res_last = false)
 {
     if (fuse_pairs(c, l)) return smooth_pairs(c, l, iters);
-    return smooth_single(c, l, iters);
+    return smooth_single(c, l, iters, res_last);
 }
 
-int smooth_single(nmg_ctx *c, int l, int iters)
+int smooth_single(nmg_ctx *c, int l, int iters, bool res_last)
 {
     c->tgroup = -1;               // timed runs never span other launches
     for (int it = 0; it < iters; ++it) {
         int rc;
         if ((rc = halfsweep(c, l, 0)) || (rc = halfsweep(c, l, 1)) || (rc = halfsweep(c, l, 1)) ||
-            (rc = halfsweep(c, l, 0)))
+            (rc = halfsweep(c, l, 0, res_last && it + 1 == iters)))
             return rc;
     }
     c->tgroup = -1;
@@ -376,6 +395,7 @@ int materialize(nmg_ctx *c, int l)
         else if (Lv.st[color] == ST_VALID_PP) op = 1;
         else if (Lv.st[color] == ST_ZERO_PP) op = 2;
         if (op < 0) continue;
+        if (c->res_level == l) c->res_level = -1;
         if (c->recording) {
             c->rec.push_back(CoarseOp{COP_FIX, l, color, op});
         } else if (c->batch) {
@@ -397,6 +417,7 @@ void set_zero(nmg_ctx *c, int l)
 {
     c->L[l].st[0] = c->L[l].st[1] = ST_ZERO;
     c->L[l].last = -1;
+    if (c->res_level == l) c->res_level = -1;
 }
 
 // Algorithm 0 with gamma = 1 (V-cycle) on level l.
@@ -404,7 +425,8 @@ int cycle(nmg_ctx *c, int l)
 {
     const nmg_params &p = c->prm;
     int rc;
-    if ((rc = smooth(c, l, p.nu1))) return rc;
+    c->res_level = -1;
+    if ((rc = smooth(c, l, p.nu1, l < c->NL && !c->recording && !c->batch))) return rc;
     if (l == c->NL) {
         if ((rc = smooth(c, l, p.nu_coarse))) return rc;
     } else {
@@ -416,10 +438,16 @@ int cycle(nmg_ctx *c, int l)
         else if (c->batch)
             HIPCHK(c, launch_b_restrict(c->dim, c->f32, c->batch->d_lv + (long)l * c->batch->n,
                                         c->batch->w_rchild[l + 1], c->batch->d_active, c->stream));
+        else if (c->res_level == l)
+            HIPCHK(c, launch_restrict_res(c->dim, c->f32, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b,
+                                          c->rres, c->res_color,
+                                          stream_level(cells(Lv.G), c->nc, c->f32 ? 4 : 8),
+                                          c->stream));
         else
             HIPCHK(c, launch_restrict(c->dim, c->f32, Lv.G, Lv.A, Lv.b, Lv.x, Lc.G, Lc.b,
                                       stream_level(cells(Lv.G), c->nc, c->f32 ? 4 : 8),
                                       c->stream));
+        c->res_level = -1;
         set_zero(c, l + 1);
         if (l + 1 == c->lc && !c->recording && c->prog_len > 0) {
             // The coarse calls below, from level lc down, run in one
@@ -988,6 +1016,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
         total += (size_t)2 * c->ne * c->L[l].G.planeP + (size_t)2 * 2 * c->nc * c->L[l].G.plane +
                  (l > 0 ? (size_t)c->nc * c->L[l].G.plane : 0);
     }
+    if (plan) total += (size_t)c->nc * c->L[0].G.plane;      // rres (not used by batches)
     char *pool = nullptr;
     if (hipMalloc(&pool, total * esz) != hipSuccess) {
         delete c;
@@ -1004,6 +1033,10 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
             Lv.xt = pool + off * esz;
             off += (size_t)c->nc * Lv.G.plane;
         }
+    }
+    if (plan) {
+        c->rres = pool + off * esz;
+        off += (size_t)c->nc * c->L[0].G.plane;
     }
     long N = cells(c->L[0].G);
     int nparts = nblocks(N);

@@ -144,6 +144,17 @@ hipError_t launch_sgs_half(int dim, bool f32, int mode, const LevelGeom &G, cons
 hipError_t launch_restrict(int dim, bool f32, const LevelGeom &G, const void *A, const void *b,
                            const void *x, const LevelGeom &Gc, void *bc, bool stream,
                            hipStream_t s);
+// A normal-mode half sweep of colour `color` that also writes the updated
+// cells' linear residuals to rout (NC planes of G.plane slots), and the
+// restriction that takes the residuals of the children of colour rcol from
+// rin instead of recomputing them (valid while both colours of x are as the
+// half sweep left them).
+hipError_t launch_sgs_half_res(int dim, bool f32, const LevelGeom &G, const void *A,
+                               const void *b, void *x, int color, void *rout, bool stream,
+                               hipStream_t s);
+hipError_t launch_restrict_res(int dim, bool f32, const LevelGeom &G, const void *A,
+                               const void *b, const void *x, const LevelGeom &Gc, void *bc,
+                               const void *rin, int rcol, bool stream, hipStream_t s);
 // Two consecutive half sweeps (colour `color` in `mode`, then the other colour
 // in normal mode) in one launch, 2D only: colour `color` is updated in x, the
 // other colour is read from xin (NC planes) and written to xout (NC planes).

@@ -740,11 +740,16 @@ __device__ __forceinline__ void restrict_cell(const LevelGeom &G, const T *__res
 // block's first CB threads sum the children's residuals, exchanged through
 // LDS, in the order of restrict_cell.  base: index of the block's first
 // coarse cell.  Every thread of the block reaches the barrier.
-template <class T, int NC, bool STREAM = false>
+// RIN: the residuals of the children of colour rcol were written by the half
+// sweep that last updated them (k_sgs_half_res, NC planes of that colour's
+// slots in rin) and are read instead of recomputed; a child position has
+// one colour, so each wave either reads or computes.
+template <class T, int NC, bool STREAM = false, bool RIN = false>
 __device__ __forceinline__ void restrict_block(const LevelGeom &G, const T *__restrict__ A,
                                                const T *__restrict__ b,
                                                const T *__restrict__ x, const LevelGeom &Gc,
-                                               T *__restrict__ bc, long base)
+                                               T *__restrict__ bc, long base,
+                                               const T *__restrict__ rin = nullptr, int rcol = 0)
 {
     constexpr int nch = (NC == 2) ? 2 : 4;
     constexpr int CB = kBlock / nch;
@@ -757,7 +762,13 @@ __device__ __forceinline__ void restrict_block(const LevelGeom &G, const T *__re
         T r[NC];
         const int i = 2 * I + (ch & 1);
         const int j = (NC == 2) ? 0 : 2 * J + (ch >> 1);
-        lin_residual_cell<T, NC, STREAM>(G, A, b, x, i, j, r);
+        if (RIN && ((i + j) & 1) == rcol) {
+            const long slot = (long)j * G.W + (i >> 1);
+#pragma unroll
+            for (int q = 0; q < NC; ++q) r[q] = rin[q * G.plane + slot];
+        } else {
+            lin_residual_cell<T, NC, STREAM>(G, A, b, x, i, j, r);
+        }
 #pragma unroll
         for (int q = 0; q < NC; ++q) rs[ch][q][k] = r[q];
     }
@@ -785,6 +796,18 @@ __global__ void __launch_bounds__(kBlock) k_restrict(LevelGeom G, const T *__res
 {
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     restrict_block<T, NC, STREAM>(G, A, b, x, Gc, bc, (long)xb * (kBlock / ((NC == 2) ? 2 : 4)));
+}
+
+template <class T, int NC, bool STREAM>
+__global__ void __launch_bounds__(kBlock) k_restrict_res(LevelGeom G, const T *__restrict__ A,
+                                                         const T *__restrict__ b,
+                                                         const T *__restrict__ x, LevelGeom Gc,
+                                                         T *__restrict__ bc,
+                                                         const T *__restrict__ rin, int rcol)
+{
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    restrict_block<T, NC, STREAM, true>(G, A, b, x, Gc, bc,
+                                        (long)xb * (kBlock / ((NC == 2) ? 2 : 4)), rin, rcol);
 }
 
 // Galerkin coarse blocks (eq:ProjectAR, left) with the child-pair order of
@@ -2515,6 +2538,30 @@ hipError_t launch_sgs_half(int dim, bool f32, int mode, const LevelGeom &G, cons
     return sgs_stream<double, 3>(stream, mode, G, A, b, x, color, Gc, xc, s);
 }
 
+template <class T, int NC>
+static hipError_t sgs_res_stream(bool stream, const LevelGeom &G, const void *A, const void *b,
+                                 void *x, int color, void *rout, hipStream_t s)
+{
+    int g = nblocks(G.plane);
+    if (stream)
+        NMG_LAUNCH((k_sgs_half_res<T, NC, true>), g, G, (const T *)A, (const T *)b, (T *)x, color,
+                   (T *)rout);
+    NMG_LAUNCH((k_sgs_half_res<T, NC, false>), g, G, (const T *)A, (const T *)b, (T *)x, color,
+               (T *)rout);
+}
+
+hipError_t launch_sgs_half_res(int dim, bool f32, const LevelGeom &G, const void *A,
+                               const void *b, void *x, int color, void *rout, bool stream,
+                               hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) return sgs_res_stream<float, 2>(stream, G, A, b, x, color, rout, s);
+        return sgs_res_stream<float, 3>(stream, G, A, b, x, color, rout, s);
+    }
+    if (dim == 1) return sgs_res_stream<double, 2>(stream, G, A, b, x, color, rout, s);
+    return sgs_res_stream<double, 3>(stream, G, A, b, x, color, rout, s);
+}
+
 template <class T>
 static hipError_t pair_dispatch(int mode, const LevelGeom &G, const T *A, const T *b, T *x,
                                 const T *xin, T *xout, int color, const LevelGeom &Gc, const T *xc,
@@ -2607,6 +2654,31 @@ hipError_t launch_restrict(int dim, bool f32, const LevelGeom &G, const void *A,
     }
     if (dim == 1) return restrict_stream<double, 2>(stream, G, A, b, x, Gc, bc, s);
     return restrict_stream<double, 3>(stream, G, A, b, x, Gc, bc, s);
+}
+
+template <class T, int NC>
+static hipError_t restrict_res_stream(bool stream, const LevelGeom &G, const void *A,
+                                      const void *b, const void *x, const LevelGeom &Gc, void *bc,
+                                      const void *rin, int rcol, hipStream_t s)
+{
+    int g = nblocks((long)Gc.nx * Gc.ny * (NC == 2 ? 2 : 4));
+    if (stream)
+        NMG_LAUNCH((k_restrict_res<T, NC, true>), g, G, (const T *)A, (const T *)b, (const T *)x,
+                   Gc, (T *)bc, (const T *)rin, rcol);
+    NMG_LAUNCH((k_restrict_res<T, NC, false>), g, G, (const T *)A, (const T *)b, (const T *)x, Gc,
+               (T *)bc, (const T *)rin, rcol);
+}
+
+hipError_t launch_restrict_res(int dim, bool f32, const LevelGeom &G, const void *A,
+                               const void *b, const void *x, const LevelGeom &Gc, void *bc,
+                               const void *rin, int rcol, bool stream, hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) return restrict_res_stream<float, 2>(stream, G, A, b, x, Gc, bc, rin, rcol, s);
+        return restrict_res_stream<float, 3>(stream, G, A, b, x, Gc, bc, rin, rcol, s);
+    }
+    if (dim == 1) return restrict_res_stream<double, 2>(stream, G, A, b, x, Gc, bc, rin, rcol, s);
+    return restrict_res_stream<double, 3>(stream, G, A, b, x, Gc, bc, rin, rcol, s);
 }
 
 hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *Af,

@@ -199,13 +199,20 @@ __device__ __forceinline__ void gs_update(const T *a, const T *inv, const T *bv,
 // INV: the diagonal block is applied through its precomputed inverse data
 // Ai (tiled like A, inv_entries(NC) entries per slot) instead of solve_block.
 // STREAM: off-diagonal blocks loaded through ld_once.
-template <class T, int NC, int MODE, bool INV = false, bool STREAM = false>
+// RES (normal mode, INV false): also write the cell's linear residual after
+// its update, b_i - (D_i x_i + sum over existing faces A_ij x_j) in the
+// order of the restriction's residual, to rout (NC planes of the colour's
+// slots): the other colour is unchanged until the next half sweep, so it is
+// bit for bit the residual the restriction would compute.
+template <class T, int NC, int MODE, bool INV = false, bool STREAM = false, bool RES = false>
 __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const T *__restrict__ A,
                                          const T *__restrict__ Ai,
                                          const T *__restrict__ b, T *__restrict__ x,
                                          int color, const LevelGeom &Gc,
-                                         const T *__restrict__ xc, long t)
+                                         const T *__restrict__ xc, long t,
+                                         T *__restrict__ rout = nullptr)
 {
+    static_assert(!RES || (MODE == MODE_NORMAL && !INV), "residual output needs D and x_j");
     constexpr int NF = (NC == 2) ? 2 : 4;
     constexpr int NN = NC * NC;
     constexpr int NE = (NF + 1) * NN;
@@ -258,6 +265,26 @@ __device__ __forceinline__ void sgs_cell(const LevelGeom &G, const T *__restrict
     T *xm = x + (long)color * NC * G.plane + t;
 #pragma unroll
     for (int r = 0; r < NC; ++r) xm[r * G.plane] = xi[r];
+    if constexpr (RES) {
+        T acc[NC];
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            acc[q] = T(0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[q] = acc[q] + a[q * NC + c] * xi[c];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (!ok[f]) continue;
+#pragma unroll
+            for (int q = 0; q < NC; ++q)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[q] = acc[q] + a[((f + 1) * NC + q) * NC + c] * v[f][c];
+        }
+#pragma unroll
+        for (int q = 0; q < NC; ++q) rout[q * G.plane + t] = bv[q] - acc[q];
+    }
 }
 
 template <class T, int NC, int MODE, bool STREAM>
@@ -269,6 +296,19 @@ __global__ void __launch_bounds__(kBlock) k_sgs_half(LevelGeom G, const T *__res
     long t = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (t >= G.plane) return;
     sgs_cell<T, NC, MODE, false, STREAM>(G, A, nullptr, b, x, color, Gc, xc, t);
+}
+
+// A normal-mode half sweep that also writes its cells' residuals to rout.
+template <class T, int NC, bool STREAM>
+__global__ void __launch_bounds__(kBlock) k_sgs_half_res(LevelGeom G, const T *__restrict__ A,
+                                                         const T *__restrict__ b,
+                                                         T *__restrict__ x, int color,
+                                                         T *__restrict__ rout)
+{
+    long t = (long)xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (t >= G.plane) return;
+    sgs_cell<T, NC, MODE_NORMAL, false, STREAM, true>(G, A, nullptr, b, x, color, G, nullptr, t,
+                                                      rout);
 }
 
 }  // namespace
