@@ -103,6 +103,7 @@ struct nmg_batch {
     std::vector<BatchInst> h_inst;
     BatchInst *d_inst = nullptr;
     BatchLevel *d_lv = nullptr;           // [(NL + 1) * n], level-major
+    void *d_rr = nullptr;                 // each instance's residual planes (level 0's size)
     LevelDev *d_clv = nullptr;            // [n * kMaxLevels] coarse-kernel level tables
     WorkItem *d_work = nullptr;
     WorkRange w_cells0{nullptr, 0};       // 256-cell tiles of level 0
@@ -206,18 +207,25 @@ int halfsweep(nmg_ctx *c, int l, int color, bool res = false)
         Lv.last = color;
         return NMG_OK;
     }
+    res = res && mode == MODE_NORMAL && c->rres;
     if (c->batch) {
         nmg_batch *B = c->batch;
         const int tl = B->tile[l];
         int ti = 0;
         while (kTileChoices[ti] != tl) ++ti;
-        HIPCHK(c, launch_b_sgs_half(c->dim, c->f32, mode, tl, B->d_lv + (long)l * B->n,
-                                    B->w_plane[l][ti], B->d_active, color, c->stream));
+        if (res) {
+            HIPCHK(c, launch_b_sgs_half_res(c->dim, c->f32, tl, B->d_lv + (long)l * B->n,
+                                            B->w_plane[l][ti], B->d_active, color, c->stream));
+            c->res_level = l;
+            c->res_color = color;
+        } else {
+            HIPCHK(c, launch_b_sgs_half(c->dim, c->f32, mode, tl, B->d_lv + (long)l * B->n,
+                                        B->w_plane[l][ti], B->d_active, color, c->stream));
+        }
         Lv.st[color] = ST_VALID;
         Lv.last = color;
         return NMG_OK;
     }
-    res = res && mode == MODE_NORMAL && c->rres;
     // Measurement hook: full half sweeps (all neighbour blocks read) of the
     // finest level.  A run of them launched back to back (within one
     // smoothing call) shares one pair of events around the whole run.
@@ -426,7 +434,7 @@ int cycle(nmg_ctx *c, int l)
     const nmg_params &p = c->prm;
     int rc;
     c->res_level = -1;
-    if ((rc = smooth(c, l, p.nu1, l < c->NL && !c->recording && !c->batch))) return rc;
+    if ((rc = smooth(c, l, p.nu1, l < c->NL && !c->recording))) return rc;
     if (l == c->NL) {
         if ((rc = smooth(c, l, p.nu_coarse))) return rc;
     } else {
@@ -435,6 +443,11 @@ int cycle(nmg_ctx *c, int l)
         Level &Lc = c->L[l + 1];
         if (c->recording)
             c->rec.push_back(CoarseOp{COP_RESTRICT, l, 0, 0});
+        else if (c->batch && c->res_level == l)
+            HIPCHK(c, launch_b_restrict_res(c->dim, c->f32,
+                                            c->batch->d_lv + (long)l * c->batch->n,
+                                            c->batch->w_rchild[l + 1], c->batch->d_active,
+                                            c->res_color, c->stream));
         else if (c->batch)
             HIPCHK(c, launch_b_restrict(c->dim, c->f32, c->batch->d_lv + (long)l * c->batch->n,
                                         c->batch->w_rchild[l + 1], c->batch->d_active, c->stream));
@@ -1499,13 +1512,26 @@ int nmg_batch_create(int n, const nmg_grid *grids, const nmg_bc *bcs, const nmg_
         }
         for (int k = 0; k < n; ++k) b->cells_l[l] += cells(geom(k, l));
     }
+    // residual planes of the last pre-smoothing half sweep, one per instance
+    const size_t esz = b->f32 ? sizeof(float) : sizeof(double);
+    std::vector<size_t> rr_off(n);
+    size_t rr_total = 0;
+    for (int k = 0; k < n; ++k) {
+        rr_off[k] = rr_total;
+        rr_total += (size_t)b->nc * geom(k, 0).plane * esz;
+    }
+    if (hipMalloc(&b->d_rr, rr_total) != hipSuccess) {
+        nmg_batch_destroy(b);
+        return NMG_ENOMEM;
+    }
+    t->rres = b->d_rr;          // enables the batched residual half sweeps
     std::vector<BatchLevel> blv((size_t)(NL + 1) * n);
     for (int l = 0; l <= NL; ++l)
         for (int k = 0; k < n; ++k) {
             const Level &Lf = b->inst[k]->L[l];
             const Level &Lc = b->inst[k]->L[l < NL ? l + 1 : l];
             blv[(size_t)l * n + k] = BatchLevel{Lf.G, Lc.G, Lf.A, Lf.b, Lf.x, Lc.A, Lc.b, Lc.x,
-                                                Lf.xt};
+                                                Lf.xt, (char *)b->d_rr + rr_off[k]};
         }
     b->h_inst.resize(n);
     for (int k = 0; k < n; ++k) {
@@ -1555,6 +1581,7 @@ void nmg_batch_destroy(nmg_batch *b)
     }
     if (b->d_inst) (void)hipFree(b->d_inst);
     if (b->d_lv) (void)hipFree(b->d_lv);
+    if (b->d_rr) (void)hipFree(b->d_rr);
     if (b->d_clv) (void)hipFree(b->d_clv);
     if (b->d_work) (void)hipFree(b->d_work);
     if (b->d_active) (void)hipFree(b->d_active);

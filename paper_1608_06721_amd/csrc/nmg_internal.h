@@ -225,6 +225,7 @@ struct BatchLevel {
     void *A, *b, *x;
     void *Ac, *bc, *xc;
     void *xt;               // the level's alternate planes for fused half-sweep pairs
+    void *rr;               // the instance's residual planes (launch_b_sgs_half_res)
 };
 
 // One tile of one instance: a batched launch runs one block per work item.
@@ -274,6 +275,12 @@ hipError_t launch_b_sgs_half(int dim, bool f32, int mode, int tile, const BatchL
                              WorkRange w, const int *active, int color, hipStream_t s);
 hipError_t launch_b_restrict(int dim, bool f32, const BatchLevel *lv, WorkRange w,
                              const int *active, hipStream_t s);
+// Batched launch_sgs_half_res / launch_restrict_res (normal mode; each
+// instance's residuals in its BatchLevel::rr).
+hipError_t launch_b_sgs_half_res(int dim, bool f32, int tile, const BatchLevel *lv, WorkRange w,
+                                 const int *active, int color, hipStream_t s);
+hipError_t launch_b_restrict_res(int dim, bool f32, const BatchLevel *lv, WorkRange w,
+                                 const int *active, int rcol, hipStream_t s);
 hipError_t launch_b_fix_color(int dim, bool f32, int op, const BatchLevel *lv, WorkRange w,
                               const int *active, int color, hipStream_t s);
 hipError_t launch_b_galerkin(int dim, bool f32, const BatchLevel *lv, WorkRange w,

@@ -941,6 +941,7 @@ __device__ __forceinline__ BatchLevel global_view(const BatchLevel &L)
     J.bc = in_global(L.bc);
     J.xc = in_global(L.xc);
     J.xt = in_global(L.xt);
+    J.rr = in_global(L.rr);
     return J;
 }
 
@@ -2363,6 +2364,22 @@ __global__ void __launch_bounds__(TB) kb_sgs_half(const BatchLevel *__restrict__
                               (const T *)L.xc, t);
 }
 
+template <class T, int NC, int TB>
+__global__ void __launch_bounds__(TB) kb_sgs_half_res(const BatchLevel *__restrict__ lv,
+                                                      WorkRange w, const int *__restrict__ active,
+                                                      int color)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchLevel L = global_view(lv[it.inst]);
+    const long t = (long)it.tile * TB + threadIdx.x;
+    if (t < L.G.plane)
+        sgs_cell<T, NC, MODE_NORMAL, false, false, true>(L.G, (const T *)L.A, nullptr,
+                                                         (const T *)L.b, (T *)L.x, color, L.G,
+                                                         nullptr, t, (T *)L.rr);
+}
+
 template <class T, int MODE>
 __global__ void __launch_bounds__(kPairThreads) kb_sgs_pair(const BatchLevel *__restrict__ lv,
                                                             WorkRange w,
@@ -2394,6 +2411,20 @@ __global__ void __launch_bounds__(kBlock) kb_restrict(const BatchLevel *__restri
     // tiles of kBlock children = kBlock / nch coarse cells
     restrict_block<T, NC>(L.G, (const T *)L.A, (const T *)L.b, (const T *)L.x, L.Gc, (T *)L.bc,
                           (long)it.tile * (kBlock / ((NC == 2) ? 2 : 4)));
+}
+
+template <class T, int NC>
+__global__ void __launch_bounds__(kBlock) kb_restrict_res(const BatchLevel *__restrict__ lv,
+                                                          WorkRange w,
+                                                          const int *__restrict__ active, int rcol)
+{
+    int pos;
+    const WorkItem it = work_item(w, pos);
+    if (!active[it.inst]) return;
+    const BatchLevel L = global_view(lv[it.inst]);
+    restrict_block<T, NC, false, true>(L.G, (const T *)L.A, (const T *)L.b, (const T *)L.x, L.Gc,
+                                       (T *)L.bc, (long)it.tile * (kBlock / ((NC == 2) ? 2 : 4)),
+                                       (const T *)L.rr, rcol);
 }
 
 template <class T, int NC>
@@ -2967,6 +2998,47 @@ hipError_t launch_b_restrict(int dim, bool f32, const BatchLevel *lv, WorkRange 
     }
     if (dim == 1) NMG_BLAUNCH((kb_restrict<double, 2>), lv, w, active);
     NMG_BLAUNCH((kb_restrict<double, 3>), lv, w, active);
+}
+
+hipError_t launch_b_restrict_res(int dim, bool f32, const BatchLevel *lv, WorkRange w,
+                                 const int *active, int rcol, hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) NMG_BLAUNCH((kb_restrict_res<float, 2>), lv, w, active, rcol);
+        NMG_BLAUNCH((kb_restrict_res<float, 3>), lv, w, active, rcol);
+    }
+    if (dim == 1) NMG_BLAUNCH((kb_restrict_res<double, 2>), lv, w, active, rcol);
+    NMG_BLAUNCH((kb_restrict_res<double, 3>), lv, w, active, rcol);
+}
+
+template <class T, int NC>
+static hipError_t bsgs_res_tile(int tile, const BatchLevel *lv, WorkRange w, const int *active,
+                                int color, hipStream_t s)
+{
+    if (w.n <= 0) return hipSuccess;
+#define NMG_BRES(TB)                                                                          \
+    hipLaunchKernelGGL((kb_sgs_half_res<T, NC, TB>), dim3(w.n), dim3(TB), 0, s, lv, w, active, \
+                       color);                                                                \
+    return hipGetLastError()
+    switch (tile) {
+    case 64: NMG_BRES(64);
+    case 128: NMG_BRES(128);
+    case 256: NMG_BRES(256);
+    case 512: NMG_BRES(512);
+    default: return hipErrorInvalidValue;
+    }
+#undef NMG_BRES
+}
+
+hipError_t launch_b_sgs_half_res(int dim, bool f32, int tile, const BatchLevel *lv, WorkRange w,
+                                 const int *active, int color, hipStream_t s)
+{
+    if (f32) {
+        if (dim == 1) return bsgs_res_tile<float, 2>(tile, lv, w, active, color, s);
+        return bsgs_res_tile<float, 3>(tile, lv, w, active, color, s);
+    }
+    if (dim == 1) return bsgs_res_tile<double, 2>(tile, lv, w, active, color, s);
+    return bsgs_res_tile<double, 3>(tile, lv, w, active, color, s);
 }
 
 hipError_t launch_b_fix_color(int dim, bool f32, int op, const BatchLevel *lv, WorkRange w,
