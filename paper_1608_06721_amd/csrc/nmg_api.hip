@@ -52,9 +52,11 @@ struct nmg_ctx {
     int split = 1;                    // coarsest-level runs may use two lanes per cell
     Level L[16];
     void *pool = nullptr;             // the hierarchy's allocation
-    // residuals of one colour of level res_level, written by the last half
-    // sweep of a pre-smoothing for the restriction that follows it (NC planes
-    // of level 0's size in the hierarchy's type; -1: none valid)
+    // Residuals of colour res_color of level res_level (res_level -1: none
+    // valid), written by the last half sweep of a pre-smoothing for the
+    // restriction that follows it: NC planes of level 0's size in the
+    // hierarchy's type (a batch's template instance points at the batch's
+    // per-instance planes instead, through its level table).
     void *rres = nullptr;
     int res_level = -1, res_color = -1;
     void *At_alloc = nullptr;         // second level-0 matrix (adjoint transpose), owned
@@ -185,8 +187,10 @@ int check_params(const nmg_grid *g, const nmg_bc *bc, const nmg_params *p, std::
 
 // ---- multigrid on the colour-split hierarchy -----------------------------
 
-// res: the caller's restriction follows; a normal-mode launch then also
-// writes the updated cells' residuals (c->rres), which it reads instead.
+// res: a restriction from level l follows this half sweep; a normal-mode
+// launch then also writes the updated cells' residuals (c->rres), which the
+// restriction reads instead of recomputing them.  Any other change to the
+// level's x invalidates them.
 int halfsweep(nmg_ctx *c, int l, int color, bool res = false)
 {
     Level &Lv = c->L[l];
