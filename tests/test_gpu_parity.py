@@ -353,10 +353,15 @@ def test_vcycle_long_smoothing_bitwise(nmg, monkeypatch):
 @pytest.mark.parametrize("case", LIN + TILED)
 @pytest.mark.parametrize("nus", [(2, 2, 10), (1, 0, 3)])
 @pytest.mark.parametrize("coarse_cells", ["256", "0"])
-def test_vcycle_fp32_bitwise(nmg, case, nus, coarse_cells, monkeypatch):
+@pytest.mark.parametrize("fuse", ["3", "1"])
+def test_vcycle_fp32_bitwise(nmg, case, nus, coarse_cells, fuse, monkeypatch):
+    """fuse 1: every launched level smoothed one half sweep per launch, so
+    each restriction reads the residuals its last pre-smoothing half sweep
+    wrote (level 0 does so with any fuse)."""
     prob, A, b, x0 = random_case(*case)
-    say("vcycle fp32", case, nus, coarse_cells)
+    say("vcycle fp32", case, nus, coarse_cells, fuse)
     monkeypatch.setenv("NMG_COARSE_CELLS", coarse_cells)
+    monkeypatch.setenv("NMG_FUSE", fuse)
     p = dict(prob.params, nu1=nus[0], nu2=nus[1], nu_coarse=nus[2], inner_fp32=1)
     ctx = nmg.Context.from_problem(prob, **p)
     ctx.load_system(dev(A), dev(b))
