@@ -154,7 +154,10 @@ def adjoint_gradients(args):
     targets from the steady state over a perturbed bed (untimed), and its
     gradient through the autograd Function (adjoint multigrid solve to 1e-12
     relative, then the bed vector-Jacobian product).  Timed: forward solve +
-    objective + backward, per topography."""
+    objective + backward, per topography, after one untimed gradient of the
+    first topography with a steady state (the first backward pass allocates
+    the adjoint's matrix and Krylov buffers and loads its kernels: 0.6 s
+    against ~0.06 s for the later ones)."""
     import torch
     from paper_1608_06721_amd import adjoint, nmg
     from paper_1608_06721_amd import workloads as W
@@ -164,6 +167,7 @@ def adjoint_gradients(args):
                           max_newton=args.max_newton)
     ctx = nmg.Context.from_problem(cases[0].prob)
     times, fwd, adj, steps, skipped = [], [], [], [], []
+    warm = True
     for c in cases:
         p = c.prob
         Ut = torch.from_numpy(p.U0).cuda()
@@ -173,8 +177,16 @@ def adjoint_gradients(args):
             continue
         g = torch.from_numpy(c.gauges).cuda()
         target = (Ut[0] + torch.from_numpy(c.z_true).cuda()).reshape(-1)[g]
-        z = torch.from_numpy(p.z).cuda().requires_grad_(True)
         U0 = torch.from_numpy(p.U0).cuda()
+        if warm:
+            warm = False
+            try:
+                zw = torch.from_numpy(p.z).cuda().requires_grad_(True)
+                adjoint.gauge_misfit(adjoint.steady_state(ctx, zw, U0, tol=args.tol,
+                                                          adj_tol=1e-12), zw, g, target).backward()
+            except nmg.NMGError:
+                warm = True             # no gradient here: warm up on the next topography
+        z = torch.from_numpy(p.z).cuda().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
