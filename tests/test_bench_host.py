@@ -21,7 +21,7 @@ def test_sgs_source_digest_is_stable():
     assert d1 == d2 and len(d1) == 16
 
 
-def test_measured_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
+def test_measured_traffic_follows_the_kernel_sources(monkeypatch):
     """The committed counter record is used only while the half sweep's
     sources are the ones it was taken with; it then reads about the
     algorithmic 432 bytes per update of 524,288 cells."""
