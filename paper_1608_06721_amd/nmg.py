@@ -104,11 +104,22 @@ def lib():
     return _lib
 
 
-def _ptr(t: Optional[torch.Tensor], what: str):
+def _on_device(t: torch.Tensor) -> bool:
+    return t.is_cuda
+
+
+def _ptr(t: Optional[torch.Tensor], what: str, shape=None):
+    """Device address of `t` after checking its dtype, device, contiguity
+    and (if given) its shape: the library trusts the sizes it is passed, so a
+    tensor of the wrong size must be refused here rather than read or written
+    out of bounds on the GPU."""
     if t is None:
         return None
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
-            or not t.is_contiguous():
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % what)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (what, tuple(t.shape), tuple(shape)))
+    if not _on_device(t) or t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError("%s must be a contiguous float64 CUDA tensor" % what)
     return C.c_void_p(t.data_ptr())
 
@@ -191,34 +202,48 @@ class Context:
         ny = 1 if self.dim == 1 else self.ny >> level
         return nx, ny
 
+    def _vec(self, level=0):
+        nx, ny = self.level_shape(level)
+        return (self.nc, ny, nx)
+
+    def _bed(self):
+        return (self.ny, self.nx)
+
     # --- entry points ------------------------------------------------------
     def residual(self, z, U, R_out=None, want_norm=True):
         res = C.c_double(0.0)
-        self._check(lib().nmg_residual(self._h, _ptr(z, "z"), _ptr(U, "U"), _ptr(R_out, "R_out"),
+        self._check(lib().nmg_residual(self._h, _ptr(z, "z", self._bed()),
+                                       _ptr(U, "U", self._vec()),
+                                       _ptr(R_out, "R_out", self._vec()),
                                        C.byref(res) if want_norm else None))
         return res.value if want_norm else None
 
     def assemble_residual_jacobian(self, z, U, R_out=None, want_norm=True):
         res = C.c_double(0.0)
         self._check(lib().nmg_assemble_residual_jacobian(
-            self._h, _ptr(z, "z"), _ptr(U, "U"), _ptr(R_out, "R_out"),
+            self._h, _ptr(z, "z", self._bed()), _ptr(U, "U", self._vec()),
+            _ptr(R_out, "R_out", self._vec()),
             C.byref(res) if want_norm else None))
         return res.value if want_norm else None
 
     def mg_vcycle(self, dU, n_cycles=1):
-        self._check(lib().nmg_mg_vcycle(self._h, _ptr(dU, "dU"), int(n_cycles)))
+        self._check(lib().nmg_mg_vcycle(self._h, _ptr(dU, "dU", self._vec()), int(n_cycles)))
 
     def sgs(self, dU, iters, level=0):
-        self._check(lib().nmg_sgs(self._h, int(level), _ptr(dU, "dU"), int(iters)))
+        if not 0 <= int(level) <= self.n_levels:
+            raise ValueError("level %d outside 0..%d" % (level, self.n_levels))
+        self._check(lib().nmg_sgs(self._h, int(level), _ptr(dU, "dU", self._vec(level)),
+                                  int(iters)))
 
     def blu_sweep(self, z, U):
-        self._check(lib().nmg_blu_sweep(self._h, _ptr(z, "z"), _ptr(U, "U")))
+        self._check(lib().nmg_blu_sweep(self._h, _ptr(z, "z", self._bed()),
+                                        _ptr(U, "U", self._vec())))
 
     def newton_mg_solve(self, z, U, tol, hist_cap=10000):
         hist = (C.c_double * hist_cap)()
         st = nmg_stats(0, 0, 0, 0.0, C.cast(hist, C.POINTER(C.c_double)), hist_cap, 0)
-        rc = lib().nmg_newton_mg_solve(self._h, _ptr(z, "z"), _ptr(U, "U"), float(tol),
-                                       C.byref(st))
+        rc = lib().nmg_newton_mg_solve(self._h, _ptr(z, "z", self._bed()),
+                                       _ptr(U, "U", self._vec()), float(tol), C.byref(st))
         self._check(rc, ok=(0, 1, -4, -5))
         n = st.newton_steps
         nh = min(n + 1 if rc in (0, -4, -5) else n, hist_cap)
@@ -227,9 +252,14 @@ class Context:
                     init_sweeps=st.init_sweeps)
 
     def load_system(self, A0, b0):
-        self._check(lib().nmg_load_system(self._h, _ptr(A0, "A0"), _ptr(b0, "b0")))
+        nx, ny = self.level_shape(0)
+        self._check(lib().nmg_load_system(self._h,
+                                          _ptr(A0, "A0", (self.nb, self.nc, self.nc, ny, nx)),
+                                          _ptr(b0, "b0", self._vec())))
 
     def get_system(self, level=0, want_A=True, want_b=True):
+        if not 0 <= int(level) <= self.n_levels:
+            raise ValueError("level %d outside 0..%d" % (level, self.n_levels))
         nx, ny = self.level_shape(level)
         dev = torch.device("cuda", torch.cuda.current_device())
         A = torch.empty((self.nb, self.nc, self.nc, ny, nx), dtype=torch.float64, device=dev) \
@@ -245,8 +275,10 @@ class Context:
         if lam is None:
             lam = torch.zeros_like(g)
         cyc, rel = C.c_int(0), C.c_double(0.0)
-        self._check(lib().nmg_adjoint_solve(self._h, _ptr(z, "z"), _ptr(U, "U"), _ptr(g, "g"),
-                                            _ptr(lam, "lambda"), float(tol), int(max_cycles),
+        v = self._vec()
+        self._check(lib().nmg_adjoint_solve(self._h, _ptr(z, "z", self._bed()), _ptr(U, "U", v),
+                                            _ptr(g, "g", v), _ptr(lam, "lambda", v),
+                                            float(tol), int(max_cycles),
                                             int(krylov), C.byref(cyc), C.byref(rel)))
         return lam, cyc.value, rel.value
 
@@ -254,8 +286,9 @@ class Context:
         """(dR/dz)^T lam at (z, U) as a [ny][nx] tensor (nmg_bed_vjp)."""
         if out is None:
             out = torch.empty_like(z)
-        self._check(lib().nmg_bed_vjp(self._h, _ptr(z, "z"), _ptr(U, "U"), _ptr(lam, "lambda"),
-                                      _ptr(out, "out")))
+        v = self._vec()
+        self._check(lib().nmg_bed_vjp(self._h, _ptr(z, "z", self._bed()), _ptr(U, "U", v),
+                                      _ptr(lam, "lambda", v), _ptr(out, "out", self._bed())))
         return out
 
     def timing_enable(self, enable=True, cap=4096):
@@ -288,6 +321,8 @@ class Batch:
         params.update(overrides)
         self.n = n
         self.params = params
+        nc = 2 if probs[0].dim == 1 else 3
+        self.shapes = [((nc, p.ny, p.nx), (p.ny, p.nx)) for p in probs]
         grids = (nmg_grid * n)(*[_grid(p.dim, p.nx, p.ny, p.x0, p.x1, p.y0, p.y1) for p in probs])
         bcs = (nmg_bc * n)(*[_bc(p.bc) for p in probs])
         prm = _params(params)
@@ -331,8 +366,10 @@ class Batch:
         per instance (as Context.newton_mg_solve)."""
         if len(zs) != self.n or len(Us) != self.n:
             raise ValueError("need one z and one U per instance")
-        zp = (C.c_void_p * self.n)(*[_ptr(z, "z") for z in zs])
-        up = (C.c_void_p * self.n)(*[_ptr(u, "U") for u in Us])
+        zp = (C.c_void_p * self.n)(*[_ptr(z, "z[%d]" % k, self.shapes[k][1])
+                                     for k, z in enumerate(zs)])
+        up = (C.c_void_p * self.n)(*[_ptr(u, "U[%d]" % k, self.shapes[k][0])
+                                     for k, u in enumerate(Us)])
         hists = [(C.c_double * max(hist_cap, 1))() for _ in range(self.n)]
         st = (nmg_stats * self.n)()
         for k in range(self.n):
