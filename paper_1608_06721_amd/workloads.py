@@ -208,6 +208,27 @@ def channel(nx: int = 1024, ny: int = 1024, seed: int = CHANNEL_SEED, qn: float 
                    default_params(2, **kw), z, U0)
 
 
+# Bed of the measured 1024 x 1024 channel solve.  With the configured bumps
+# (widths U[0.05, 0.4]) and mounds (amplitude 1.6) the method has no steady
+# state to reach; these are the nearest parameters for which it has one.
+BENCH_BED = dict(bump_width=(0.2, 0.8), mound_amp=0.8, mound_width=0.25)
+
+
+def benchmark_channel(n: int = 1024, **kw) -> Problem:
+    """The measured steady channel solve at n x n: bed BENCH_BED, W(2,2)
+    cycles (gamma = 2) down to a 16 x 16 coarsest level, everything else as
+    in channel()."""
+    kw.setdefault("n_levels", int(round(math.log2(n))) - 4)
+    kw.setdefault("gamma", 2)
+    bed = dict(BENCH_BED)
+    for k in list(bed):
+        if k in kw:
+            bed[k] = kw.pop(k)
+    p = channel(n, n, **bed, **kw)
+    p.name = "bench_channel_%d" % n
+    return p
+
+
 BATCH_SEED = CHANNEL_SEED + 1
 
 

@@ -261,3 +261,52 @@ def test_positivity_relaxation():
     assert (t > 0).all() and (t < 1).all()
     for k in range(1, prob.nc):
         np.testing.assert_allclose((Ub[k] - U[k])[full], t * (Ua[k] - U[k])[full], rtol=1e-9, atol=1e-15)
+
+
+def test_pinned_newton_step_is_the_step_on_the_free_unknowns():
+    """Both pins (isolated cells, and the momentum of exactly dry cells)
+    amount to holding those unknowns fixed: the pinned system's solution is
+    zero on them and, on every other unknown, equals the Newton step of the
+    reduced system obtained from the brute-force global forward-difference
+    Jacobian (plus alpha ||R_i||_1 on the diagonal) by deleting the held
+    unknowns' rows and columns.  Dense linear algebra only; the assembly's
+    per-face differences and pin code play no part in the reference."""
+    from blockmat import dense, vec
+    prob = W.dry_hill(24, 12, n_levels=1)
+    rng = np.random.default_rng(5)
+    U = prob.U0.copy()
+    wet = U[0] > 0
+    # raise the wet cells' surface above the beds of the dry cells next to
+    # them, which then take water and are not isolated
+    U[0][wet] = np.maximum(0.4 - prob.z[wet], 0.05) * rng.uniform(0.9, 1.1, wet.sum())
+    U[1][wet] = 0.02 * rng.uniform(-1, 1, wet.sum()) * U[0][wet]
+    U[2][wet] = 0.02 * rng.uniform(-1, 1, wet.sum()) * U[0][wet]
+    nc, n = prob.nc, prob.nx * prob.ny
+    iso = oracle.isolated(prob, U).reshape(-1)
+    dry = (U[0] == 0).reshape(-1)
+    assert iso.sum() > 0 and (dry & ~iso).sum() > 0       # both pins act
+    A, b, _ = oracle.assemble(prob, U)
+    M = dense(A)
+    for c in np.flatnonzero(iso):
+        # an isolated cell's block row is zero (its block solve gives zero);
+        # a unit diagonal makes the dense matrix say the same
+        assert not M[c * nc:(c + 1) * nc].any()
+        M[c * nc:(c + 1) * nc, c * nc:(c + 1) * nc] = np.eye(nc)
+    x_pinned = np.linalg.solve(M, vec(b))
+    R, _ = oracle.residual(prob, U)
+    J = global_fd_jacobian(prob, U, prob.params["fd_eps"])
+    nrm = np.abs(vec(R)).reshape(n, nc).sum(axis=1)
+    J += np.diag(np.repeat(prob.params["alpha"] * nrm, nc))
+    held = np.zeros(n * nc, dtype=bool)
+    for c in range(n):
+        if iso[c]:
+            held[c * nc:(c + 1) * nc] = True
+        elif dry[c]:
+            held[c * nc + 1:(c + 1) * nc] = True
+    free = ~held
+    x_ref = np.zeros(n * nc)
+    x_ref[free] = np.linalg.solve(J[np.ix_(free, free)], -vec(R)[free])
+    assert (x_pinned[held] == 0).all()
+    scale = np.abs(x_ref).max()
+    assert scale > 1e-3
+    np.testing.assert_allclose(x_pinned, x_ref, rtol=0, atol=1e-5 * scale)
