@@ -100,8 +100,9 @@ typedef struct {
  * (children averaged level by level in the order SW, SE, NW, NE), then on
  * each level l = N_L..1 symmetric BLU-SGS sweeps while sum ||R_{i,l}||_1 >=
  * eps_p 2^-l (at most init_max_sweeps sweeps), then injection into the
- * children; eps_p = 0 starts Newton from U0 (the paper suggests about 1 %
- * of the initial residual).  Batches require eps_p = 0. */
+ * children; eps_p = 0 starts Newton from U0 (the paper's experiments use
+ * eps_p = 0.2 unless stated otherwise, and its remark on the parameter
+ * suggests about 1 % of the initial residual).  Batches require eps_p = 0. */
 typedef struct {
     int flux;
     double g, alpha, fd_eps, tau, h_eps, eps_r;
@@ -125,6 +126,8 @@ typedef struct {
     double *res_hist;
     int hist_cap;
     int init_sweeps;         /* Step 1 BLU-SGS sweeps over all coarse levels */
+    int init_level_sweeps[16];   /* Step 1 BLU-SGS sweeps on level l (0 for l = 0 and
+                                    beyond n_levels) */
 } nmg_stats;
 
 /* Create a context for one grid / BC / parameter set on HIP stream `stream`
@@ -242,6 +245,25 @@ int nmg_bed_vjp(nmg_ctx *ctx, const double *z, const double *U, const double *la
 int nmg_timing_enable(nmg_ctx *ctx, int enable, int cap);
 int nmg_timing_read(nmg_ctx *ctx, double *sgs_ms_host, int *sgs_launches_host,
                     long long *sgs_cells_host);
+
+/* Phases of nmg_newton_mg_solve (Algorithm 1).  STEP1: the dry threshold of
+ * U0 and Step 1; BLU: the Step 2.1 sweeps (and the copy of the iterate kept
+ * for a non-finite step); ASSEMBLY: isolation flags, residual and Jacobian of
+ * level 0; GALERKIN: the coarse levels; NORM: the residual norm's reduction,
+ * its transfer to the host and the stop test; CYCLES: the n_mg multigrid
+ * cycles; UPDATE: the relaxed update and threshold; FINAL: the returned
+ * state's residual norm and pinned-cell count. */
+enum { NMG_PHASE_STEP1 = 0, NMG_PHASE_BLU, NMG_PHASE_ASSEMBLY, NMG_PHASE_GALERKIN,
+       NMG_PHASE_NORM, NMG_PHASE_CYCLES, NMG_PHASE_UPDATE, NMG_PHASE_FINAL, NMG_NPHASES };
+
+/* With timing enabled, nmg_newton_mg_solve also records one event on the
+ * stream at each phase boundary (at most `cap` events, the same cap as
+ * above).  nmg_timing_phases synchronizes the stream and returns in
+ * ms_host[NMG_NPHASES] (host) the milliseconds between consecutive events
+ * summed per phase over the recorded solves, i.e. the stream's wall time in
+ * each phase, idle gaps (host round trips of the stop test) included;
+ * marks_host (nullable) the number of events recorded. */
+int nmg_timing_phases(nmg_ctx *ctx, double *ms_host, int *marks_host);
 
 /* ---- Batches of independent problems --------------------------------------
  * A batch solves n independent steady problems (Algorithm 1 on each) of

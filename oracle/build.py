@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "nmg_oracle.c")
 LIB = os.path.join(HERE, "libnmg_oracle.so")
 
-CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-fopenmp",
           "-Wall", "-Wextra", "-Wno-unused-parameter"]
 
 

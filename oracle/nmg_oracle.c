@@ -22,6 +22,18 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Threads of the per-cell loops whose iterations are independent: cells of
+ * one colour in a red-black half sweep, and loops that only read the state
+ * they do not write (residual, assembly, restriction, Galerkin sums,
+ * updates).  One by default; the lexicographic sweeps and every sum over
+ * cells stay sequential in cell order, so results do not depend on it. */
+static int orc_threads = 1;
+
+void orc_set_threads(int n) { orc_threads = n > 0 ? n : 1; }
+int orc_get_threads(void) { return orc_threads; }
+
+#define ORC_PARALLEL_FOR _Pragma("omp parallel for schedule(static) num_threads(orc_threads) if (orc_threads > 1)")
+
 enum { FW = 0, FE = 1, FS = 2, FN = 3 };
 
 /* max/min written as comparisons so that a NaN operand in the second place
@@ -301,14 +313,19 @@ int orc_residual(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
 {
     prob P;
     if (setup(&P, gr, bc, p, z)) return ORC_EINVAL;
-    double tot = 0.0;
+    double *nrm = (double *)malloc(sizeof(double) * (size_t)P.N);
+    if (!nrm) return ORC_EINVAL;
+    ORC_PARALLEL_FOR
     for (int j = 0; j < gr->ny; ++j)
         for (int i = 0; i < gr->nx; ++i) {
             double Rc[3];
             cell_residual(&P, U, i, j, Rc);
             for (int k = 0; k < P.nc; ++k) if (R) R[k * P.N + j * gr->nx + i] = Rc[k];
-            tot = tot + l1(P.nc, Rc);
+            nrm[j * gr->nx + i] = l1(P.nc, Rc);
         }
+    double tot = 0.0;
+    for (int idx = 0; idx < P.N; ++idx) tot = tot + nrm[idx];
+    free(nrm);
     if (res_l1) *res_l1 = tot;
     return ORC_OK;
 }
@@ -342,6 +359,7 @@ int orc_isolated(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
 {
     prob P;
     if (setup(&P, gr, bc, p, z)) return ORC_EINVAL;
+    ORC_PARALLEL_FOR
     for (int j = 0; j < gr->ny; ++j)
         for (int i = 0; i < gr->nx; ++i) iso[j * gr->nx + i] = (unsigned char)cell_isolated(&P, U, i, j);
     return ORC_OK;
@@ -416,18 +434,19 @@ int orc_assemble(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
 {
     prob P;
     if (setup(&P, gr, bc, p, z)) return ORC_EINVAL;
-    int nx = gr->nx, ny = gr->ny, nc = P.nc, nb = P.nf + 1, ni, nj;
+    int nx = gr->nx, ny = gr->ny, nc = P.nc, nb = P.nf + 1;
     unsigned char *iso = (unsigned char *)malloc((size_t)P.N);
-    if (!iso) return ORC_EINVAL;
+    double *nrms = (double *)malloc(sizeof(double) * (size_t)P.N);
+    if (!iso || !nrms) { free(iso); free(nrms); return ORC_EINVAL; }
     orc_isolated(gr, bc, p, z, U, iso);
-    double tot = 0.0;
+    ORC_PARALLEL_FOR
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
-            int idx = j * nx + i;
+            int idx = j * nx + i, ni, nj;
             double Rc[3], Dm[3][3], Off[4][3][3];
             cell_jacobian(&P, U, i, j, Rc, Dm, Off);
             double nrm = l1(nc, Rc);
-            tot = tot + nrm;
+            nrms[idx] = nrm;
             for (int r = 0; r < nc; ++r) Dm[r][r] = Dm[r][r] + p->alpha * nrm;
             if (iso[idx]) {
                 memset(Dm, 0, sizeof Dm);
@@ -447,7 +466,10 @@ int orc_assemble(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
             }
             (void)nb;
         }
+    double tot = 0.0;
+    for (int idx = 0; idx < P.N; ++idx) tot = tot + nrms[idx];
     free(iso);
+    free(nrms);
     if (res_l1) *res_l1 = tot;
     return ORC_OK;
 }
@@ -553,6 +575,7 @@ void orc_threshold(const orc_grid *gr, const orc_params *p, double *U)
     orc_side dummy[4];
     memset(dummy, 0, sizeof dummy);
     if (setup(&P, gr, dummy, p, NULL)) return;
+    ORC_PARALLEL_FOR
     for (int idx = 0; idx < P.N; ++idx) threshold_cell(&P, U, idx);
 }
 
@@ -576,6 +599,7 @@ static void blu_cell(const prob *P, double *U, int i, int j)
 
 static void blu_half(const prob *P, double *U, int color)
 {
+    ORC_PARALLEL_FOR
     for (int j = 0; j < P->gr->ny; ++j)
         for (int i = 0; i < P->gr->nx; ++i)
             if (((i + j) & 1) == color) blu_cell(P, U, i, j);
@@ -607,6 +631,7 @@ int orc_blu_sweep(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
 static void relaxed_update(const prob *P, double *U, const double *x)
 {
     double th = P->p->pos_theta, tau = P->p->tau;
+    ORC_PARALLEL_FOR
     for (int idx = 0; idx < P->N; ++idx) {
         double t = tau;
         double h = U[idx], dh = x[idx];

@@ -75,6 +75,11 @@ double orc_inflow_celerity(double K, double gq);
 void orc_solve_block(int nc, const double *D /* row-major nc*nc */, const double *r, double *x);
 
 /* --- discretization ----------------------------------------------------- */
+/* Threads of the oracle's independent per-cell loops (default 1; results do
+ * not depend on it). */
+void orc_set_threads(int n);
+int orc_get_threads(void);
+
 int orc_residual(const orc_grid *gr, const orc_side bc[4], const orc_params *p,
                  const double *z, const double *U, double *R, double *res_l1);
 int orc_isolated(const orc_grid *gr, const orc_side bc[4], const orc_params *p,

@@ -18,6 +18,9 @@
 
 using namespace nmg;
 
+static_assert(sizeof(((nmg_stats *)nullptr)->init_level_sweeps) == kMaxLevels * sizeof(int),
+              "one Step 1 sweep count per level");
+
 namespace {
 
 // State of one colour of a level's correction vector x.
@@ -81,6 +84,11 @@ struct nmg_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<long long> ev_cells;
     std::vector<int> ev_launches;
+    // phase boundaries of the Newton solve: event k closes phase pev_ph[k]
+    // (NMG_PHASE_*, or -1 for the start of a solve), which began at event k-1
+    std::vector<hipEvent_t> pev;
+    std::vector<signed char> pev_ph;
+    int npev = 0;
     // coarse part of the V-cycle in one workgroup (levels lc..NL), recorded
     // once from the same state machine that drives the per-level launches
     int lc = -1;
@@ -127,6 +135,18 @@ int fail(nmg_ctx *c, int code, const std::string &msg)
 {
     if (c) c->err = msg;
     return code;
+}
+
+// Measurement hook: an event on the stream that closes phase `ph` of the
+// Newton solve (-1: the start of a solve, attributed to no phase).  Marks
+// beyond the event pool are dropped.
+int phase_mark(nmg_ctx *c, int ph)
+{
+    if (!c->timing || c->npev >= (int)c->pev.size()) return NMG_OK;
+    if (hipEventRecord(c->pev[c->npev], c->stream) != hipSuccess)
+        return fail(c, NMG_EHIP, "hipEventRecord failed");
+    c->pev_ph[c->npev++] = (signed char)ph;
+    return NMG_OK;
 }
 
 #define HIPCHK(ctx, call)                                                                   \
@@ -719,9 +739,14 @@ int assemble(nmg_ctx *c, const double *z, const double *U, double *R_out, double
     HIPCHK(c, launch_isolated(c->P, z, U, c->iso, c->stream));
     HIPCHK(c, launch_assemble(c->P, L0.G, z, U, c->iso, L0.A, L0.b, c->f32, R_out, c->partial,
                               c->stream));
-    int rc = build_coarse(c);
+    int rc = phase_mark(c, NMG_PHASE_ASSEMBLY);
+    if (!rc) rc = build_coarse(c);
+    if (!rc) rc = phase_mark(c, NMG_PHASE_GALERKIN);
     if (rc) return rc;
-    if (res) return reduce_to_host(c, nblocks(cells(L0.G)), res);
+    if (res) {
+        if ((rc = reduce_to_host(c, nblocks(cells(L0.G)), res))) return rc;
+        return phase_mark(c, NMG_PHASE_NORM);
+    }
     return NMG_OK;
 }
 
@@ -893,11 +918,13 @@ Phys level_phys(const nmg_ctx *c, int l)
 }
 
 // Algorithm 1, Step 1 on U in place (see nmg_params); *sweeps = the BLU-SGS
-// sweeps done over all levels.
-int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps)
+// sweeps done over all levels, level_sweeps[l] (nullable) those on level l.
+int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_sweeps)
 {
     const int NL = c->NL, nc = c->nc;
     *sweeps = 0;
+    if (level_sweeps)
+        for (int l = 0; l < kMaxLevels; ++l) level_sweeps[l] = 0;
     if (!(c->prm.eps_p > 0.0) || NL < 1) return NMG_OK;
     if (!c->init_pool) {
         size_t tot = 0;
@@ -935,6 +962,7 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps)
             ++cnt;
         }
         *sweeps += cnt;
+        if (level_sweeps) level_sweeps[l] = cnt;
         const LevelGeom &Gf = c->L[l - 1].G;
         HIPCHK(c, launch_inject(c->dim, Gf.nx, Gf.ny, nc, c->Ul[l], l == 1 ? U : c->Ul[l - 1],
                                 c->stream));
@@ -1088,6 +1116,7 @@ void nmg_destroy(nmg_ctx *c)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    for (hipEvent_t e : c->pev) (void)hipEventDestroy(e);
     if (c->pool) (void)hipFree(c->pool);
     if (c->At_alloc) (void)hipFree(c->At_alloc);
     for (double *q : {c->kV, c->kg, c->kx, c->kw, c->kpart, c->kdots, c->kcoef})
@@ -1195,13 +1224,17 @@ int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_
     const size_t vbytes = sizeof(double) * c->nc * N;
     int status = NMG_NOT_CONVERGED, n = 0, rc;
     double res = 0.0, res0 = 0.0;
+    if ((rc = phase_mark(c, -1))) return rc;
     HIPCHK(c, launch_threshold(c->P, U, c->stream));
     int init_sweeps = 0;
-    if ((rc = nested_init(c, z, U, &init_sweeps))) return rc;     // Step 1 (eps_p > 0)
+    if ((rc = nested_init(c, z, U, &init_sweeps, st ? st->init_level_sweeps : nullptr)))
+        return rc;                                                  // Step 1 (eps_p > 0)
+    if ((rc = phase_mark(c, NMG_PHASE_STEP1))) return rc;
     for (n = 0; n < p.max_newton; ++n) {
         HIPCHK(c, hipMemcpyAsync(c->Ulast, U, vbytes, hipMemcpyDeviceToDevice, c->stream));
         for (int s = 0; s < p.blu_sweeps; ++s)
             if ((rc = nmg_blu_sweep(c, z, U))) return rc;
+        if ((rc = phase_mark(c, NMG_PHASE_BLU))) return rc;
         if ((rc = assemble(c, z, U, nullptr, &res))) return rc;
         if (st && st->res_hist && n < st->hist_cap) st->res_hist[n] = res;
         if (n == 0) res0 = res;
@@ -1215,8 +1248,10 @@ int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_
         set_zero(c, 0);
         for (int m = 0; m < p.n_mg; ++m)
             if ((rc = cycle(c, 0))) return rc;
+        if ((rc = phase_mark(c, NMG_PHASE_CYCLES))) return rc;
         if ((rc = materialize(c, 0))) return rc;
         HIPCHK(c, launch_update(c->P, L0.G, L0.x, c->f32, U, c->stream));
+        if ((rc = phase_mark(c, NMG_PHASE_UPDATE))) return rc;
     }
     if (status == NMG_NOT_CONVERGED) {
         HIPCHK(c, launch_residual(c->P, z, U, nullptr, c->partial, c->stream));
@@ -1231,6 +1266,7 @@ int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_
         st->res_l1 = res;
         st->init_sweeps = init_sweeps;
     }
+    if ((rc = phase_mark(c, NMG_PHASE_FINAL))) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return status;
 }
@@ -1312,6 +1348,13 @@ int nmg_timing_enable(nmg_ctx *c, int enable, int cap)
         c->ev_launches.assign(c->ev.size(), 0);
         c->nrec = 0;
         c->tgroup = -1;
+        while ((int)c->pev.size() < cap) {
+            hipEvent_t a;
+            HIPCHK(c, hipEventCreate(&a));
+            c->pev.push_back(a);
+        }
+        c->pev_ph.assign(c->pev.size(), -1);
+        c->npev = 0;
     }
     c->timing = enable != 0;
     return NMG_OK;
@@ -1334,6 +1377,23 @@ int nmg_timing_read(nmg_ctx *c, double *ms_host, int *launches_host, long long *
     if (ms_host) *ms_host = tot;
     if (launches_host) *launches_host = nl;
     if (cells_host) *cells_host = cl;
+    return NMG_OK;
+}
+
+int nmg_timing_phases(nmg_ctx *c, double *ms_host, int *marks_host)
+{
+    if (!c) return NMG_EINVAL;
+    if (!ms_host) return fail(c, NMG_EINVAL, "null ms_host");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int q = 0; q < NMG_NPHASES; ++q) ms_host[q] = 0.0;
+    for (int k = 1; k < c->npev; ++k) {
+        const int ph = c->pev_ph[k];
+        if (ph < 0) continue;
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->pev[k - 1], c->pev[k]));
+        ms_host[ph] += ms;
+    }
+    if (marks_host) *marks_host = c->npev;
     return NMG_OK;
 }
 
@@ -1755,6 +1815,7 @@ int nmg_batch_newton_mg_solve(nmg_batch *b, const double *const *z, double *cons
             stats[k].status = status[k];
             stats[k].res_l1 = res[k];
             stats[k].init_sweeps = 0;
+            for (int l = 0; l < kMaxLevels; ++l) stats[k].init_level_sweeps[l] = 0;
         }
     }
     BHIPCHK(b, hipStreamSynchronize(b->stream));

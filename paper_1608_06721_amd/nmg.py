@@ -47,14 +47,18 @@ class nmg_params(C.Structure):
 class nmg_stats(C.Structure):
     _fields_ = [("newton_steps", C.c_int), ("status", C.c_int), ("n_pinned", C.c_int),
                 ("res_l1", C.c_double), ("res_hist", C.POINTER(C.c_double)),
-                ("hist_cap", C.c_int), ("init_sweeps", C.c_int)]
+                ("hist_cap", C.c_int), ("init_sweeps", C.c_int),
+                ("init_level_sweeps", C.c_int * 16)]
+
+
+PHASES = ["step1", "blu", "assembly", "galerkin", "norm", "cycles", "update", "final"]
 
 
 _lib = None
 EXPORTS = ["nmg_create", "nmg_destroy", "nmg_last_error", "nmg_residual",
            "nmg_assemble_residual_jacobian", "nmg_mg_vcycle", "nmg_sgs", "nmg_blu_sweep",
            "nmg_newton_mg_solve", "nmg_load_system", "nmg_get_system", "nmg_timing_enable",
-           "nmg_timing_read", "nmg_batch_create", "nmg_batch_destroy", "nmg_batch_last_error",
+           "nmg_timing_read", "nmg_timing_phases", "nmg_batch_create", "nmg_batch_destroy", "nmg_batch_last_error",
            "nmg_batch_autotune", "nmg_batch_newton_mg_solve", "nmg_adjoint_solve",
            "nmg_bed_vjp"]
 
@@ -88,6 +92,7 @@ def lib():
         L.nmg_timing_enable.argtypes = [vp, C.c_int, C.c_int]
         L.nmg_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                       C.POINTER(C.c_longlong)]
+        L.nmg_timing_phases.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.nmg_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int, C.c_int,
                                         C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.nmg_bed_vjp.argtypes = [vp, vp, vp, vp, vp]
@@ -242,6 +247,7 @@ class Context:
     def newton_mg_solve(self, z, U, tol, hist_cap=10000):
         hist = (C.c_double * hist_cap)()
         st = nmg_stats(0, 0, 0, 0.0, C.cast(hist, C.POINTER(C.c_double)), hist_cap, 0)
+        n_lev = self.n_levels
         rc = lib().nmg_newton_mg_solve(self._h, _ptr(z, "z", self._bed()),
                                        _ptr(U, "U", self._vec()), float(tol), C.byref(st))
         self._check(rc, ok=(0, 1, -4, -5))
@@ -249,7 +255,8 @@ class Context:
         nh = min(n + 1 if rc in (0, -4, -5) else n, hist_cap)
         return dict(status=STATUS.get(rc, rc), newton_steps=n, n_pinned=st.n_pinned,
                     res_l1=st.res_l1, res_hist=[hist[k] for k in range(nh)],
-                    init_sweeps=st.init_sweeps)
+                    init_sweeps=st.init_sweeps,
+                    init_level_sweeps=[st.init_level_sweeps[l] for l in range(n_lev + 1)])
 
     def load_system(self, A0, b0):
         nx, ny = self.level_shape(0)
@@ -293,6 +300,15 @@ class Context:
 
     def timing_enable(self, enable=True, cap=4096):
         self._check(lib().nmg_timing_enable(self._h, int(bool(enable)), int(cap)))
+
+    def timing_phases(self):
+        """Stream time per phase of the recorded Newton solves (ms), by name."""
+        ms = (C.c_double * len(PHASES))()
+        marks = C.c_int(0)
+        self._check(lib().nmg_timing_phases(self._h, ms, C.byref(marks)))
+        out = {name: ms[k] for k, name in enumerate(PHASES)}
+        out["marks"] = marks.value
+        return out
 
     def timing_read(self):
         ms, n, cells = C.c_double(0), C.c_int(0), C.c_longlong(0)

@@ -114,9 +114,39 @@ def test_dry_hill_step1_converges(nmg):
 def test_full_size_newton_steps(nmg):
     """The benchmark solve (1024 x 1024 channel in the benchmark's
     configuration and launch path), three whole Newton steps from the
-    resting state: BLU-SGS, assembly, Galerkin levels, three W-cycles and the
-    update per step, bit for bit, with the residual history."""
-    prob = W.benchmark_channel(1024, max_newton=3)
+    resting state without Step 1: BLU-SGS, assembly, Galerkin levels, three
+    W-cycles and the update per step, bit for bit, with the residual
+    history."""
+    prob = W.benchmark_channel(1024, max_newton=3, eps_p=0.0)
     say("full size Newton steps", prob.name)
     st = solve_both(nmg, prob, 0.0)
     assert st["newton_steps"] == 3 and st["status"] == "NOT_CONVERGED"
+
+
+def test_phase_timing_and_step1_levels(nmg):
+    """The phase hook: every phase of a solve with Step 1 is recorded, the
+    phases add up to no more than the solve's wall time, and the per-level
+    Step 1 sweep counts add up to the total and equal the oracle's."""
+    import time
+    prob = W.dry_hill(128, 64, n_levels=4, gamma=2, eps_p=0.2)
+    ctx = nmg.Context.from_problem(prob)
+    ctx.timing_enable(True, 5000)
+    U = dev(prob.U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.newton_mg_solve(dev(prob.z), U, 1e-10)
+    wall = time.perf_counter() - t0
+    ph = ctx.timing_phases()
+    ctx.close()
+    say("phases", st["status"], st["newton_steps"], st["init_level_sweeps"], ph)
+    n = st["newton_steps"]
+    # start, Step 1, then per step blu, assembly, galerkin, norm (+ cycles,
+    # update before the last stop test), and the final mark
+    assert ph["marks"] == 2 + 4 * (n + 1) + 2 * n + 1
+    for k in nmg.PHASES:
+        assert ph[k] > 0.0, k
+    assert sum(ph[k] for k in nmg.PHASES) <= 1e3 * wall
+    lv = st["init_level_sweeps"]
+    assert len(lv) == 5 and lv[0] == 0 and sum(lv) == st["init_sweeps"] > 0
+    _, so = oracle.nested_init(prob)
+    assert lv == so
