@@ -590,7 +590,7 @@ def main():
                                       max_newton=args.v3_max_newton)
         print("[bench] V N_L=3: %s" % ex["paper_default_v3"], file=sys.stderr, flush=True)
         # The bed measured before: one emergent island, no Step 1.
-        pb = W.benchmark_channel(args.size, bed=W.ONE_ISLAND_BED, eps_p=0.0,
+        pb = W.benchmark_channel(args.size, bed=W.ONE_ISLAND_BED, eps_p=0.0, n_levels=6,
                                  max_newton=args.max_newton)
         ex["one_island_bed"] = dict(one_solve(nmg, pb, args.tol, reps=3),
                                     bed=describe_bed(W.ONE_ISLAND_BED), step1=False,

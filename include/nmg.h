@@ -147,7 +147,11 @@ typedef struct {
  *                     lanes per cell in 2D where the level has at most 128
  *                     cells per colour);
  *   NMG_FUSE          most half sweeps per launch on the launched coarse
- *                     levels: 3 (default), 2 or 1. */
+ *                     levels: 3 (default), 2 or 1;
+ *   NMG_BLU_QUAD      0 runs every BLU-SGS half sweep (Step 1 and Step 2.1)
+ *                     with one lane per cell (default: four lanes per cell,
+ *                     one per perturbation of the forward differences, on
+ *                     meshes of at most 2^16 cells per colour). */
 int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
                void *stream, nmg_ctx **out);
 void nmg_destroy(nmg_ctx *ctx);

@@ -53,6 +53,7 @@ struct nmg_ctx {
     bool f32 = false;                 // FP32 inner V-cycle
     int fuse = 3;                     // most half sweeps per launch on launched coarse levels
     int split = 1;                    // coarsest-level runs may use two lanes per cell
+    bool blu_quad = true;             // BLU-SGS half sweeps with four lanes per cell
     Level L[16];
     void *pool = nullptr;             // the hierarchy's allocation
     // Residuals of colour res_color of level res_level (res_level -1: none
@@ -919,6 +920,26 @@ Phys level_phys(const nmg_ctx *c, int l)
 
 // Algorithm 1, Step 1 on U in place (see nmg_params); *sweeps = the BLU-SGS
 // sweeps done over all levels, level_sweeps[l] (nullable) those on level l.
+// Step 1's coarse beds and states (allocated with the context when
+// eps_p > 0).
+int alloc_step1(nmg_ctx *c)
+{
+    const int NL = c->NL, nc = c->nc;
+    size_t tot = 0;
+    for (int l = 1; l <= NL; ++l) tot += (size_t)(1 + nc) * cells(c->L[l].G);
+    if (hipMalloc(&c->init_pool, sizeof(double) * tot) != hipSuccess)
+        return fail(c, NMG_ENOMEM, "Step 1 levels");
+    size_t off = 0;
+    for (int l = 1; l <= NL; ++l) {
+        c->zl[l] = c->init_pool + off; off += cells(c->L[l].G);
+        c->Ul[l] = c->init_pool + off; off += (size_t)nc * cells(c->L[l].G);
+    }
+    return NMG_OK;
+}
+
+// Most sweeps of Step 1 enqueued between two looks at the stop flag.
+constexpr int kStep1Ahead = 16;
+
 int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_sweeps)
 {
     const int NL = c->NL, nc = c->nc;
@@ -926,17 +947,7 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
     if (level_sweeps)
         for (int l = 0; l < kMaxLevels; ++l) level_sweeps[l] = 0;
     if (!(c->prm.eps_p > 0.0) || NL < 1) return NMG_OK;
-    if (!c->init_pool) {
-        size_t tot = 0;
-        for (int l = 1; l <= NL; ++l) tot += (size_t)(1 + nc) * cells(c->L[l].G);
-        if (hipMalloc(&c->init_pool, sizeof(double) * tot) != hipSuccess)
-            return fail(c, NMG_ENOMEM, "Step 1 levels");
-        size_t off = 0;
-        for (int l = 1; l <= NL; ++l) {
-            c->zl[l] = c->init_pool + off; off += cells(c->L[l].G);
-            c->Ul[l] = c->init_pool + off; off += (size_t)nc * cells(c->L[l].G);
-        }
-    }
+    if (!c->init_pool) return fail(c, NMG_EINVAL, "Step 1 levels not allocated");
     const double *zp = z;
     const double *Up = U;
     for (int l = 1; l <= NL; ++l) {
@@ -946,20 +957,38 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
         zp = c->zl[l];
         Up = c->Ul[l];
     }
+    // On each level: residual, stop test (sum ||R_i||_1 < eps_p 2^-l or the
+    // sweep cap), symmetric BLU-SGS sweep, repeated.  The test runs on the
+    // device and gates the launches behind it, so runs of sweeps are enqueued
+    // ahead (2, 4, ... up to kStep1Ahead) and the host reads the flag once per
+    // run; launches after the stop do nothing.  The sweeps performed are
+    // those of the loop with the test on the host.
     const int order[4] = {0, 1, 1, 0};
+    int *ctrl = reinterpret_cast<int *>(c->scal + 1);
+    int *h_ctrl = reinterpret_cast<int *>(c->h_scal + 1);
     for (int l = NL; l >= 1; --l) {
         const Phys P = level_phys(c, l);
         const double thr = std::ldexp(c->prm.eps_p, -l);
+        const int nparts = nblocks(cells(c->L[l].G));
+        HIPCHK(c, launch_step1_reset(ctrl, c->stream));
         int cnt = 0;
-        for (;;) {
-            double res = 0.0;
-            HIPCHK(c, launch_residual(P, c->zl[l], c->Ul[l], nullptr, c->partial, c->stream));
-            int rc = reduce_to_host(c, nblocks(cells(c->L[l].G)), &res);
-            if (rc) return rc;
-            if (!(res >= thr) || cnt >= c->prm.init_max_sweeps) break;
-            for (int q = 0; q < 4; ++q)
-                HIPCHK(c, launch_blu_half(P, c->zl[l], c->Ul[l], order[q], c->stream));
-            ++cnt;
+        for (int ahead = 2;; ahead = std::min(2 * ahead, kStep1Ahead)) {
+            for (int k = 0; k < ahead; ++k) {
+                HIPCHK(c, launch_residual(P, c->zl[l], c->Ul[l], nullptr, c->partial, c->stream,
+                                          ctrl));
+                HIPCHK(c, launch_step1_test(c->partial, nparts, thr, c->prm.init_max_sweeps, ctrl,
+                                            c->stream));
+                for (int q = 0; q < 4; ++q)
+                    HIPCHK(c, launch_blu_half(P, c->zl[l], c->Ul[l], order[q], c->blu_quad,
+                                              c->stream, ctrl));
+            }
+            HIPCHK(c, hipMemcpyAsync(h_ctrl, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                                     c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (h_ctrl[0]) {
+                cnt = h_ctrl[1];
+                break;
+            }
         }
         *sweeps += cnt;
         if (level_sweeps) level_sweeps[l] = cnt;
@@ -1053,6 +1082,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     c->f32 = params->inner_fp32 != 0;
     if (const char *e = std::getenv("NMG_FUSE")) c->fuse = std::atoi(e);
     if (const char *e = std::getenv("NMG_COARSE_SPLIT")) c->split = std::atoi(e) != 0;
+    if (const char *e = std::getenv("NMG_BLU_QUAD")) c->blu_quad = std::atoi(e) != 0;
     const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
     size_t total = 0;   // elements
     for (int l = 0; l <= c->NL; ++l) {
@@ -1086,6 +1116,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     long N = cells(c->L[0].G);
     int nparts = nblocks(N);
     bool ok = hipMemsetAsync(pool, 0, total * esz, c->stream) == hipSuccess &&
+              (!(params->eps_p > 0.0) || c->NL < 1 || alloc_step1(c) == NMG_OK) &&
               hipMalloc(&c->iso, N) == hipSuccess &&
               hipMalloc(&c->partial, sizeof(double) * (nparts + 1)) == hipSuccess &&
               hipMalloc(&c->scal, sizeof(double) * 4) == hipSuccess &&
@@ -1190,7 +1221,8 @@ int nmg_blu_sweep(nmg_ctx *c, const double *z, double *U)
     if (!c) return NMG_EINVAL;
     if (!z || !U) return fail(c, NMG_EINVAL, "null z or U");
     const int order[4] = {0, 1, 1, 0};
-    for (int k = 0; k < 4; ++k) HIPCHK(c, launch_blu_half(c->P, z, U, order[k], c->stream));
+    for (int k = 0; k < 4; ++k)
+        HIPCHK(c, launch_blu_half(c->P, z, U, order[k], c->blu_quad, c->stream));
     return NMG_OK;
 }
 

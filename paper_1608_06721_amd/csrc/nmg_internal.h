@@ -127,11 +127,26 @@ hipError_t launch_isolated(const Phys &P, const double *z, const double *U, unsi
 hipError_t launch_assemble(const Phys &P, const LevelGeom &G, const double *z, const double *U,
                            const unsigned char *iso, void *A, void *b, bool f32, double *R_out,
                            double *partial, hipStream_t s);
+// gate (nullable): the launch does nothing while *gate is set (Step 1).
 hipError_t launch_residual(const Phys &P, const double *z, const double *U, double *R_out,
-                           double *partial, hipStream_t s);
+                           double *partial, hipStream_t s, const int *gate = nullptr);
+// Step 1 stop test on the device over n partials (k_step1_test) and the
+// reset of its control words {stop flag, sweeps done}.
+hipError_t launch_step1_test(const double *partial, int n, double thr, int max_sweeps, int *ctrl,
+                             hipStream_t s);
+hipError_t launch_step1_reset(int *ctrl, hipStream_t s);
 hipError_t launch_reduce(const double *partial, int n, double *out, hipStream_t s);
 hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipStream_t s);
-hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, hipStream_t s);
+// quad: four lanes per cell (k_blu_half_quad) instead of one, on levels of
+// at most kBluQuadMaxCells cells per colour.  Measured per half sweep, one
+// lane against four per cell: 79 against 94 us with 524,288 cells per
+// colour and 22 against 25 us with 131,072 (the arithmetic bounds these
+// launches and four lanes repeat the cell's own side and block solve), 17
+// against 10 us with 16,384 and 20-32 against 8-11 us on smaller levels
+// (there a launch lasts as long as one cell's chain of dependent arithmetic).
+constexpr long kBluQuadMaxCells = 1L << 16;
+hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, bool quad,
+                           hipStream_t s, const int *gate = nullptr);
 hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool f32, double *U,
                          hipStream_t s);
 hipError_t launch_threshold(const Phys &P, double *U, hipStream_t s);

@@ -510,12 +510,16 @@ __device__ __forceinline__ double residual_cell(const Phys &P, const double *__r
     return nrm;
 }
 
+// gate (nullable): a flag set by the Step 1 stop test; the launch does
+// nothing once it is set.
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_residual(Phys P, const double *__restrict__ z,
                                                      const double *__restrict__ U,
                                                      double *__restrict__ R_out,
-                                                     double *__restrict__ partial)
+                                                     double *__restrict__ partial,
+                                                     const int *__restrict__ gate)
 {
+    if (gate && *gate) return;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     long idx = (long)xb * kBlock + threadIdx.x;
     double nrm = 0.0;
@@ -524,13 +528,43 @@ __global__ void __launch_bounds__(kBlock) k_residual(Phys P, const double *__res
     if (threadIdx.x == 0) partial[xb] = s;
 }
 
-__global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ partial, int n,
-                                                   double *__restrict__ out)
+// Sum of n block partials in a fixed order (one block): thread t sums
+// partials t, t + kBlock, ..., then the block's tree; thread 0 holds the sum.
+__device__ __forceinline__ double sum_partials(const double *__restrict__ partial, int n)
 {
     double v = 0.0;
     for (int k = threadIdx.x; k < n; k += kBlock) v = v + partial[k];
-    double s = block_sum(v);
+    return block_sum(v);
+}
+
+__global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ partial, int n,
+                                                   double *__restrict__ out)
+{
+    double s = sum_partials(partial, n);
     if (threadIdx.x == 0) out[0] = s;
+}
+
+// Stop test of Step 1 on one level, on the device: ctrl[0] is the stop
+// flag, ctrl[1] the sweeps done.  Unless stopped, the level's residual norm
+// (the partials of the preceding residual launch, summed as k_reduce does)
+// below thr, or max_sweeps sweeps done, sets the flag; otherwise the sweep
+// that follows is counted.
+__global__ void __launch_bounds__(kBlock) k_step1_test(const double *__restrict__ partial, int n,
+                                                       double thr, int max_sweeps,
+                                                       int *__restrict__ ctrl)
+{
+    if (ctrl[0]) return;
+    double s = sum_partials(partial, n);
+    if (threadIdx.x == 0) {
+        if (!(s >= thr) || ctrl[1] >= max_sweeps) ctrl[0] = 1;
+        else ctrl[1] = ctrl[1] + 1;
+    }
+}
+
+__global__ void k_step1_reset(int *__restrict__ ctrl)
+{
+    ctrl[0] = 0;
+    ctrl[1] = 0;
 }
 
 __global__ void __launch_bounds__(kBlock) k_count_u8(const unsigned char *__restrict__ v, long n,
@@ -588,13 +622,142 @@ __device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict
 
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__restrict__ z,
-                                                     double *__restrict__ U, int color)
+                                                     double *__restrict__ U, int color,
+                                                     const int *__restrict__ gate)
 {
+    if (gate && *gate) return;
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     long t = (long)xb * kBlock + threadIdx.x;
     if (t >= (long)W * P.ny) return;
     blu_cell<NC>(P, z, U, color, t);
+}
+
+// Value of lane Q of each aligned group of four lanes, in all four (DPP
+// quad_perm broadcast).
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    constexpr int kCtrl = Q * 0x55;     // quad_perm [Q, Q, Q, Q]
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), kCtrl, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// blu_cell with four lanes per cell, lane k of the cell's aligned quad
+// (the lanes of a cell run in lockstep in one wave).  Lane 0 evaluates each
+// face's edge term at the cell's state, lane k = 1..NC the edge term with
+// component k-1 of the cell's state perturbed (ghost states re-evaluated from
+// that perturbed state on boundary faces); per face the unperturbed term is
+// broadcast from lane 0 and lane k accumulates column k-1 of the diagonal
+// block, lane 0 the residual, each in the face order W, E, S, N.  After the
+// faces every lane gathers R_i and the block, and does the regularization,
+// the pin, the block solve and the threshold; lane 0 stores.  Each sum,
+// difference quotient and product is blu_cell's, in its order, so the result
+// is the same bit for bit; a cell's longest chain of dependent arithmetic is
+// one edge term (and ghost) per face instead of NC + 1.
+template <int NC>
+__device__ __forceinline__ void blu_cell_quad(const Phys &P, const double *__restrict__ z,
+                                              double *__restrict__ U, int color, long t, int k)
+{
+    const int NF = (NC == 2) ? 2 : 4;
+    const int W = (P.nx + 1) / 2;
+    int j = (int)(t / W), kk = (int)(t % W);
+    int i = 2 * kk + ((j + color) & 1);
+    if (i >= P.nx) return;
+    const long N = (long)P.nx * P.ny;
+    const long idx = (long)j * P.nx + i;
+    const double eps = P.eps;
+    double qi[NC];
+    load_state<NC>(P, U, idx, qi);
+    const double zi = z[idx];
+    // this lane's own side: unperturbed (k = 0) or component k-1 + eps
+    double qk[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) qk[c] = qi[c];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (k == c + 1) qk[c] = qk[c] + eps;
+    const Side mine = cell_side<NC>(P, qk, zi);
+    double acc[NC];     // lane 0: R_i; lane k: column k-1 of sum_e |e| dT/dU_i
+#pragma unroll
+    for (int r = 0; r < NC; ++r) acc[r] = 0.0;
+    for (int f = 0; f < NF; ++f) {
+        const double e = P.elen[f];
+        int ni, nj;
+        double T[NC], T0[NC];
+        if (neighbour(P, i, j, f, ni, nj)) {
+            long nidx = (long)nj * P.nx + ni;
+            double qj[NC];
+            load_state<NC>(P, U, nidx, qj);
+            Side oth = cell_side<NC>(P, qj, z[nidx]);
+            edge_term<NC>(P, f, mine, oth, T);
+        } else {
+            Side gh = ghost(P, f, mine);
+            edge_term<NC>(P, f, mine, gh, T);
+        }
+#pragma unroll
+        for (int r = 0; r < NC; ++r) T0[r] = quad_bcast<0>(T[r]);
+        if (k == 0) {
+#pragma unroll
+            for (int r = 0; r < NC; ++r) acc[r] = acc[r] + e * T[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < NC; ++r) acc[r] = acc[r] + e * ((T[r] - T0[r]) / eps);
+        }
+    }
+    double Rc[NC], D[NC][NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        Rc[r] = quad_bcast<0>(acc[r]);
+        D[r][0] = quad_bcast<1>(acc[r]);
+        D[r][1] = quad_bcast<2>(acc[r]);
+        if (NC == 3) D[r][NC - 1] = quad_bcast<3>(acc[r]);
+    }
+    double nrm = l1norm<NC>(Rc);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
+    if (P.dry_pin && qi[0] == 0.0) {
+#pragma unroll
+        for (int r = 1; r < NC; ++r) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
+            D[r][r] = D[0][0];
+            Rc[r] = 0.0;
+        }
+    }
+    double M[NC * NC], d[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) M[r * NC + c] = D[r][c];
+    solve_block<double, NC>(M, Rc, d);
+    double q[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q[c] = qi[c] - d[c];
+    if (q[0] < P.h_eps) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = 0.0;
+    }
+    if (k == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
+    }
+}
+
+template <int NC>
+__global__ void __launch_bounds__(kBlock) k_blu_half_quad(Phys P, const double *__restrict__ z,
+                                                          double *__restrict__ U, int color,
+                                                          const int *__restrict__ gate)
+{
+    if (gate && *gate) return;
+    const int W = (P.nx + 1) / 2;
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    const long g = (long)xb * kBlock + threadIdx.x;
+    const long t = g >> 2;
+    if (t >= (long)W * P.ny) return;
+    blu_cell_quad<NC>(P, z, U, color, t, (int)(g & 3));
 }
 
 // Relaxed update U += tau_i dU (positivity-limited tau_i) and dry threshold.
@@ -2489,11 +2652,23 @@ hipError_t launch_assemble(const Phys &P, const LevelGeom &G, const double *z, c
 }
 
 hipError_t launch_residual(const Phys &P, const double *z, const double *U, double *R_out,
-                           double *partial, hipStream_t s)
+                           double *partial, hipStream_t s, const int *gate)
 {
     int g = nblocks((long)P.nx * P.ny);
-    if (P.dim == 1) NMG_LAUNCH(k_residual<2>, g, P, z, U, R_out, partial);
-    NMG_LAUNCH(k_residual<3>, g, P, z, U, R_out, partial);
+    if (P.dim == 1) NMG_LAUNCH(k_residual<2>, g, P, z, U, R_out, partial, gate);
+    NMG_LAUNCH(k_residual<3>, g, P, z, U, R_out, partial, gate);
+}
+
+hipError_t launch_step1_test(const double *partial, int n, double thr, int max_sweeps, int *ctrl,
+                             hipStream_t s)
+{
+    NMG_LAUNCH(k_step1_test, 1, partial, n, thr, max_sweeps, ctrl);
+}
+
+hipError_t launch_step1_reset(int *ctrl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_step1_reset, dim3(1), dim3(1), 0, s, ctrl);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double *partial, int n, double *out, hipStream_t s)
@@ -2506,11 +2681,18 @@ hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipS
     NMG_LAUNCH(k_count_u8, nblocks(n), v, n, partial);
 }
 
-hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, hipStream_t s)
+hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, bool quad,
+                           hipStream_t s, const int *gate)
 {
-    int g = nblocks((long)((P.nx + 1) / 2) * P.ny);
-    if (P.dim == 1) NMG_LAUNCH(k_blu_half<2>, g, P, z, U, color);
-    NMG_LAUNCH(k_blu_half<3>, g, P, z, U, color);
+    const long cells = (long)((P.nx + 1) / 2) * P.ny;
+    if (quad && cells <= kBluQuadMaxCells) {
+        int g = nblocks(4 * cells);
+        if (P.dim == 1) NMG_LAUNCH(k_blu_half_quad<2>, g, P, z, U, color, gate);
+        NMG_LAUNCH(k_blu_half_quad<3>, g, P, z, U, color, gate);
+    }
+    int g = nblocks(cells);
+    if (P.dim == 1) NMG_LAUNCH(k_blu_half<2>, g, P, z, U, color, gate);
+    NMG_LAUNCH(k_blu_half<3>, g, P, z, U, color, gate);
 }
 
 hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool f32, double *U,

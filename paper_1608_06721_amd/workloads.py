@@ -221,9 +221,9 @@ ONE_ISLAND_BED = dict(bump_width=(0.2, 0.8), mound_amp=0.8, mound_width=0.25)
 def benchmark_channel(n: int = 1024, bed: dict = None, **kw) -> Problem:
     """The measured steady channel solve at n x n: bed BENCH_BED (or `bed`),
     Algorithm 1 with Step 1 (eps_p = 0.2, the value of the paper's
-    experiments), W(2,2) cycles (gamma = 2) down to a 16 x 16 coarsest level,
+    experiments), W(2,2) cycles (gamma = 2) down to a 32 x 32 coarsest level,
     everything else as in channel()."""
-    kw.setdefault("n_levels", int(round(math.log2(n))) - 4)
+    kw.setdefault("n_levels", int(round(math.log2(n))) - 5)
     kw.setdefault("gamma", 2)
     kw.setdefault("eps_p", 0.2)
     bed = dict(BENCH_BED if bed is None else bed)

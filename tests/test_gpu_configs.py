@@ -150,3 +150,25 @@ def test_phase_timing_and_step1_levels(nmg):
     assert len(lv) == 5 and lv[0] == 0 and sum(lv) == st["init_sweeps"] > 0
     _, so = oracle.nested_init(prob)
     assert lv == so
+
+
+def test_full_size_step1(nmg):
+    """Step 1 of the benchmark solve at full size (1024 x 1024 channel with
+    two emergent mounds, eps_p = 0.2, five coarse levels, the sweep cap
+    reached on the finer ones): the nested BLU-SGS initial guess, its
+    per-level sweep counts and the residual of the state it hands to Newton,
+    bit for bit (max_newton = 0 stops right after Step 1).  The oracle runs
+    its independent per-cell loops on the host's cores (its results do not
+    depend on the thread count)."""
+    import ctypes as C
+    import os
+    prob = W.benchmark_channel(1024, max_newton=0)
+    say("full size Step 1", prob.name)
+    L = oracle.lib()
+    L.orc_set_threads(max(1, min(16, len(os.sched_getaffinity(0)))))
+    try:
+        st = solve_both(nmg, prob, 1e-10)
+    finally:
+        L.orc_set_threads(1)
+    assert st["status"] == "NOT_CONVERGED" and st["newton_steps"] == 0
+    assert st["init_sweeps"] > 4000

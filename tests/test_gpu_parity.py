@@ -80,6 +80,7 @@ def problems():
     out.append(W.dry_hill(64, 32, n_levels=3))
     out.append(tiny(2, 24, 16, 5, CHAN, W.HLLC, n_levels=3))
     out.append(W.transcritical_bump_2d(80, 32, n_levels=3))
+    out.append(tiny(2, 13, 7, 6, CHAN, W.LLF, n_levels=0))   # odd by odd, ragged colour rows
     return out
 
 
@@ -208,10 +209,14 @@ def test_vcycle_register_runs_bitwise(nmg, case, nus, gamma, reg, fp32, split, m
     same(host(x), oracle.vcycles(A, b, x0, p, 2), "x after cycles")
 
 
-@pytest.mark.parametrize("k", [0, 1, 3, 7, 8, 9])
-def test_blu_sweep_bitwise(nmg, k):
+@pytest.mark.parametrize("quad", ["1", "0"])
+@pytest.mark.parametrize("k", [0, 1, 3, 7, 8, 9, 10, 12])
+def test_blu_sweep_bitwise(nmg, k, quad, monkeypatch):
+    """quad 1: four lanes per cell (one per forward-difference perturbation,
+    the default); 0: one lane per cell."""
     prob = PROBS[k]
-    say("blu", prob.name)
+    say("blu", prob.name, quad)
+    monkeypatch.setenv("NMG_BLU_QUAD", quad)
     ctx = nmg.Context.from_problem(prob)
     z, U = dev(prob.z), dev(prob.U0)
     ctx.blu_sweep(z, U)
