@@ -15,6 +15,11 @@
  * boundary conditions), Sec. 2.2 (Newton, eq:NumerDiff, eq:NewtonREG,
  * eq:NewtonREG-12), Sec. 2.3 (eq:MatrixForm, eq:ProjectAR, eq:correction,
  * Algorithm 0), Sec. 2.4 (Algorithm 1 and the dry-cell remark).
+ *
+ * Parity unpinned: the positivity limit of the relaxed update (pos_theta)
+ * and the cap on Step 1 sweeps per level (init_max_sweeps) are parameters
+ * of this implementation that the paper does not have; their definitions
+ * are checked (tests), but no value in the paper pins them.
  */
 #include "nmg_oracle.h"
 
