@@ -164,6 +164,23 @@ const char *nmg_last_error(const nmg_ctx *ctx);
 int nmg_residual(nmg_ctx *ctx, const double *z, const double *U, double *R_out,
                  double *res_l1_host);
 
+/* nmg_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no context, no allocation, no synchronization.  grid, bc and params are
+ * validated as by nmg_create (n_levels must still divide the grid; nothing
+ * else of params but the physics is used); z, U, R_out (nullable) as in
+ * nmg_residual; res_l1 (DEVICE pointer, nullable) receives sum_i ||R_i||_1,
+ * summed in the same order as nmg_residual's.  Enqueued on `stream`
+ * (hipStream_t, NULL = null stream) of the current device.  The norm's block
+ * partial sums go to a fixed device array of the library (2 MiB per GPU, kept
+ * until the process ends), which limits the grid to nx * ny <= 2^26 cells;
+ * larger grids return NMG_EINVAL, as do invalid arguments.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams, or from several threads) race.  NMG_EHIP if a launch fails. */
+int nmg_residual_noalloc(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
+                         void *stream, const double *z, const double *U, double *R_out,
+                         double *res_l1);
+
 /* Assembly of the level-0 Newton system eq:MatrixForm at state U: right-hand
  * side -R and blocks A_ii = alpha ||R_i||_1 I + sum_e |e| dF/dU_i,
  * A_ij = |e| dF/dU_j by forward differences (eq:NumerDiff, ghosts

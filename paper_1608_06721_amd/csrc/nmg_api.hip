@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -1013,6 +1014,42 @@ int count_pinned(nmg_ctx *c, const double *z, const double *U, int *n)
 int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params, void *stream,
                bool plan, nmg_ctx **out);
 
+// Physics of the finest mesh for the kernels (validated arguments).
+Phys make_phys(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params)
+{
+    Phys P;
+    P.dim = grid->dim;
+    P.nx = grid->nx;
+    P.ny = grid->ny;
+    P.flux = params->flux;
+    P.dry_pin = params->dry_pin;
+    P.g = params->g;
+    P.alpha = params->alpha;
+    P.eps = params->fd_eps;
+    P.h_eps = params->h_eps;
+    P.eps_r = params->eps_r;
+    P.tau = params->tau;
+    P.pos_theta = params->pos_theta;
+    if (grid->dim == 1) {
+        P.elen[0] = P.elen[1] = P.elen[2] = P.elen[3] = 1.0;
+    } else {
+        double dx = (grid->x1 - grid->x0) / grid->nx, dy = (grid->y1 - grid->y0) / grid->ny;
+        P.elen[0] = P.elen[1] = dy;
+        P.elen[2] = P.elen[3] = dx;
+    }
+    for (int f = 0; f < 4; ++f) {
+        const nmg_side &s = bc->side[f];
+        P.bc[f].kind = s.kind;
+        P.bc[f].h = s.h;
+        P.bc[f].qn = s.qn;
+        P.bc[f].ut = s.ut;
+        P.bc[f].hasq = !std::isnan(s.qn);
+        P.bc[f].hash = !std::isnan(s.h);
+        P.bc[f].hast = !std::isnan(s.ut);
+    }
+    return P;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1048,36 +1085,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     c->ne = c->nb * c->nc * c->nc;
     c->NL = params->n_levels;
 
-    Phys &P = c->P;
-    P.dim = grid->dim;
-    P.nx = grid->nx;
-    P.ny = grid->ny;
-    P.flux = params->flux;
-    P.dry_pin = params->dry_pin;
-    P.g = params->g;
-    P.alpha = params->alpha;
-    P.eps = params->fd_eps;
-    P.h_eps = params->h_eps;
-    P.eps_r = params->eps_r;
-    P.tau = params->tau;
-    P.pos_theta = params->pos_theta;
-    if (grid->dim == 1) {
-        P.elen[0] = P.elen[1] = P.elen[2] = P.elen[3] = 1.0;
-    } else {
-        double dx = (grid->x1 - grid->x0) / grid->nx, dy = (grid->y1 - grid->y0) / grid->ny;
-        P.elen[0] = P.elen[1] = dy;
-        P.elen[2] = P.elen[3] = dx;
-    }
-    for (int f = 0; f < 4; ++f) {
-        const nmg_side &s = bc->side[f];
-        P.bc[f].kind = s.kind;
-        P.bc[f].h = s.h;
-        P.bc[f].qn = s.qn;
-        P.bc[f].ut = s.ut;
-        P.bc[f].hasq = !std::isnan(s.qn);
-        P.bc[f].hash = !std::isnan(s.h);
-        P.bc[f].hast = !std::isnan(s.ut);
-    }
+    c->P = make_phys(grid, bc, params);
 
     c->f32 = params->inner_fp32 != 0;
     if (const char *e = std::getenv("NMG_FUSE")) c->fuse = std::atoi(e);
@@ -1857,3 +1865,57 @@ int nmg_batch_newton_mg_solve(nmg_batch *b, const double *const *z, double *cons
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Residual without allocation.  The block partial sums of the norm live in a
+// file-scope device array of fixed size (every GPU the library runs on holds
+// its own copy until the process ends); its device address is looked up
+// once per device with that device current and kept, because in host code
+// the array's name is not a device address.
+
+namespace {
+
+constexpr long kNoAllocMaxCells = 1L << 26;                 // 8192 x 8192
+constexpr int kNoAllocParts = (int)(kNoAllocMaxCells / kBlock);   // 262,144 partials: 2 MiB
+
+__device__ __align__(256) static double scratch[kNoAllocParts + 1];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (nullptr on failure).
+double *scratch_on_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" int nmg_residual_noalloc(const nmg_grid *grid, const nmg_bc *bc,
+                                    const nmg_params *params, void *stream, const double *z,
+                                    const double *U, double *R_out, double *res_l1)
+{
+    std::string msg;
+    if (check_params(grid, bc, params, msg)) return NMG_EINVAL;
+    if (!z || !U) return NMG_EINVAL;
+    const long N = (long)grid->nx * grid->ny;
+    if (N > kNoAllocMaxCells) return NMG_EINVAL;
+    double *part = scratch_on_current_device();
+    if (!part) return NMG_EHIP;
+    const Phys P = make_phys(grid, bc, params);
+    hipStream_t s = (hipStream_t)stream;
+    // every block of the residual writes its partial, and the reduction
+    // reads exactly those, so nothing in the array needs clearing
+    if (launch_residual(P, z, U, R_out, part, s) != hipSuccess) return NMG_EHIP;
+    if (res_l1 && launch_reduce(part, nblocks(N), res_l1, s) != hipSuccess) return NMG_EHIP;
+    return NMG_OK;
+}

@@ -60,7 +60,7 @@ EXPORTS = ["nmg_create", "nmg_destroy", "nmg_last_error", "nmg_residual",
            "nmg_newton_mg_solve", "nmg_load_system", "nmg_get_system", "nmg_timing_enable",
            "nmg_timing_read", "nmg_timing_phases", "nmg_batch_create", "nmg_batch_destroy", "nmg_batch_last_error",
            "nmg_batch_autotune", "nmg_batch_newton_mg_solve", "nmg_adjoint_solve",
-           "nmg_bed_vjp"]
+           "nmg_bed_vjp", "nmg_residual_noalloc"]
 
 
 def library_path() -> str:
@@ -96,6 +96,8 @@ def lib():
         L.nmg_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_int, C.c_int,
                                         C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.nmg_bed_vjp.argtypes = [vp, vp, vp, vp, vp]
+        L.nmg_residual_noalloc.argtypes = [C.POINTER(nmg_grid), C.POINTER(nmg_bc),
+                                           C.POINTER(nmg_params), vp, vp, vp, vp, vp]
         L.nmg_batch_create.argtypes = [C.c_int, C.POINTER(nmg_grid), C.POINTER(nmg_bc),
                                        C.POINTER(nmg_params), vp, C.POINTER(vp)]
         L.nmg_batch_destroy.argtypes = [vp]
@@ -314,6 +316,29 @@ class Context:
         ms, n, cells = C.c_double(0), C.c_int(0), C.c_longlong(0)
         self._check(lib().nmg_timing_read(self._h, C.byref(ms), C.byref(n), C.byref(cells)))
         return dict(ms=ms.value, launches=n.value, cells=cells.value)
+
+
+def residual_noalloc(prob, z, U, R_out=None, res_l1=None, stream=None):
+    """nmg_residual_noalloc: residuals of U over z for the grid, boundary
+    data and physics of `prob` (anything with the attributes of
+    workloads.Problem) without a context or any allocation by the library;
+    R_out (nullable, [nc][ny][nx]) and res_l1 (nullable, a one-element
+    float64 device tensor for sum_i ||R_i||_1) are filled on `stream`
+    (default: torch's current stream) without synchronizing."""
+    nc = 2 if prob.dim == 1 else 3
+    vec, bed = (nc, prob.ny, prob.nx), (prob.ny, prob.nx)
+    g = _grid(prob.dim, prob.nx, prob.ny, prob.x0, prob.x1, prob.y0, prob.y1)
+    b = _bc(prob.bc)
+    p = _params(prob.params)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = lib().nmg_residual_noalloc(C.byref(g), C.byref(b), C.byref(p),
+                                    C.c_void_p(stream.cuda_stream), _ptr(z, "z", bed),
+                                    _ptr(U, "U", vec), _ptr(R_out, "R_out", vec),
+                                    _ptr(res_l1, "res_l1", (1,)))
+    if rc != 0:
+        raise NMGError(rc, "nmg_residual_noalloc refused the call (invalid arguments, or more "
+                           "than 2^26 cells)" if rc == -1 else "nmg_residual_noalloc failed")
 
 
 def newton_mg_solve(prob, z, U, tol, stream=None, **overrides):
