@@ -148,10 +148,11 @@ typedef struct {
  *                     cells per colour);
  *   NMG_FUSE          most half sweeps per launch on the launched coarse
  *                     levels: 3 (default), 2 or 1;
- *   NMG_BLU_QUAD      0 runs every BLU-SGS half sweep (Step 1 and Step 2.1)
- *                     with one lane per cell (default: four lanes per cell,
- *                     one per perturbation of the forward differences, on
- *                     meshes of at most 2^16 cells per colour). */
+ *   NMG_BLU_LANES     lanes per cell of every BLU-SGS half sweep (Step 1 and
+ *                     Step 2.1): 1, 4 (one per evaluation of the forward
+ *                     differences) or 16 (one per face and evaluation, 2D;
+ *                     4 in 1D); default: 16 in 2D on meshes of at most 2^14
+ *                     cells per colour, 4 up to 2^16, else 1. */
 int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
                void *stream, nmg_ctx **out);
 void nmg_destroy(nmg_ctx *ctx);

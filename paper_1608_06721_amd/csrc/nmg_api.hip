@@ -54,7 +54,7 @@ struct nmg_ctx {
     bool f32 = false;                 // FP32 inner V-cycle
     int fuse = 3;                     // most half sweeps per launch on launched coarse levels
     int split = 1;                    // coarsest-level runs may use two lanes per cell
-    bool blu_quad = true;             // BLU-SGS half sweeps with four lanes per cell
+    int blu_lanes = -1;               // lanes per cell of BLU-SGS half sweeps (-1: by mesh)
     Level L[16];
     void *pool = nullptr;             // the hierarchy's allocation
     // Residuals of colour res_color of level res_level (res_level -1: none
@@ -980,7 +980,7 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
                 HIPCHK(c, launch_step1_test(c->partial, nparts, thr, c->prm.init_max_sweeps, ctrl,
                                             c->stream));
                 for (int q = 0; q < 4; ++q)
-                    HIPCHK(c, launch_blu_half(P, c->zl[l], c->Ul[l], order[q], c->blu_quad,
+                    HIPCHK(c, launch_blu_half(P, c->zl[l], c->Ul[l], order[q], c->blu_lanes,
                                               c->stream, ctrl));
             }
             HIPCHK(c, hipMemcpyAsync(h_ctrl, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost,
@@ -1090,7 +1090,10 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
     c->f32 = params->inner_fp32 != 0;
     if (const char *e = std::getenv("NMG_FUSE")) c->fuse = std::atoi(e);
     if (const char *e = std::getenv("NMG_COARSE_SPLIT")) c->split = std::atoi(e) != 0;
-    if (const char *e = std::getenv("NMG_BLU_QUAD")) c->blu_quad = std::atoi(e) != 0;
+    if (const char *e = std::getenv("NMG_BLU_LANES")) {
+        const int v = std::atoi(e);
+        c->blu_lanes = (v == 1 || v == 4 || v == 16) ? v : -1;
+    }
     const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
     size_t total = 0;   // elements
     for (int l = 0; l <= c->NL; ++l) {
@@ -1230,7 +1233,7 @@ int nmg_blu_sweep(nmg_ctx *c, const double *z, double *U)
     if (!z || !U) return fail(c, NMG_EINVAL, "null z or U");
     const int order[4] = {0, 1, 1, 0};
     for (int k = 0; k < 4; ++k)
-        HIPCHK(c, launch_blu_half(c->P, z, U, order[k], c->blu_quad, c->stream));
+        HIPCHK(c, launch_blu_half(c->P, z, U, order[k], c->blu_lanes, c->stream));
     return NMG_OK;
 }
 

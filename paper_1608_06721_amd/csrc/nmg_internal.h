@@ -137,15 +137,19 @@ hipError_t launch_step1_test(const double *partial, int n, double thr, int max_s
 hipError_t launch_step1_reset(int *ctrl, hipStream_t s);
 hipError_t launch_reduce(const double *partial, int n, double *out, hipStream_t s);
 hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipStream_t s);
-// quad: four lanes per cell (k_blu_half_quad) instead of one, on levels of
-// at most kBluQuadMaxCells cells per colour.  Measured per half sweep, one
+// lanes: lanes per cell, 1, 4 (k_blu_half_quad) or 16 (k_blu_half_x16, 2D;
+// 4 in 1D), or -1 to choose by the mesh: 16 in 2D on meshes of at most
+// kBluX16MaxCells cells per colour, 4 up to kBluQuadMaxCells, else 1.  Measured per half sweep, one
 // lane against four per cell: 79 against 94 us with 524,288 cells per
 // colour and 22 against 25 us with 131,072 (the arithmetic bounds these
 // launches and four lanes repeat the cell's own side and block solve), 17
 // against 10 us with 16,384 and 20-32 against 8-11 us on smaller levels
 // (there a launch lasts as long as one cell's chain of dependent arithmetic).
 constexpr long kBluQuadMaxCells = 1L << 16;
-hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, bool quad,
+// 2D meshes of at most kBluX16MaxCells cells per colour run the half sweep
+// with sixteen lanes per cell (k_blu_half_x16: one per face and evaluation).
+constexpr long kBluX16MaxCells = 1L << 14;
+hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int lanes,
                            hipStream_t s, const int *gate = nullptr);
 hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool f32, double *U,
                          hipStream_t s);

@@ -760,6 +760,134 @@ __global__ void __launch_bounds__(kBlock) k_blu_half_quad(Phys P, const double *
     blu_cell_quad<NC>(P, z, U, color, t, (int)(g & 3));
 }
 
+// Value of lane i + S of the 16-lane row (DPP row_shl:S; lanes whose source
+// is past the row's end read garbage that nothing uses).
+template <int S>
+__device__ __forceinline__ double row_shl(double v)
+{
+    constexpr int kCtrl = 0x100 + S;
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), kCtrl, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the four faces, in the order W, E, S, N, of the value that lane
+// Q of each face's quad holds; valid in lane 0 of the cell's 16 lanes.
+template <int Q>
+__device__ __forceinline__ double faces_sum(double v)
+{
+    const double w = quad_bcast<Q>(v);
+    double s = 0.0;
+    s = s + w;
+    s = s + row_shl<4>(w);
+    s = s + row_shl<8>(w);
+    s = s + row_shl<12>(w);
+    return s;
+}
+
+// blu_cell for 2D cells with sixteen lanes per cell, one per (face f,
+// evaluation k): lane 4 f + k evaluates face f's edge term at the cell's
+// state (k = 0) or with component k-1 perturbed (ghost states re-evaluated
+// from that state on boundary faces), forms its term of R_i (k = 0) or of
+// column k-1 of the diagonal block, |e| ((T_k - T_0) / eps), with T_0 taken
+// from lane 4 f; lane 0 of the cell then sums the four faces' terms in the
+// order W, E, S, N, and does the regularization, the pin, the block solve,
+// the threshold and the store.  Every operation is blu_cell's in its order,
+// so the result is the same bit for bit; a cell's chain of dependent
+// arithmetic is one edge term and one ghost state.
+__device__ __forceinline__ void blu_cell_x16(const Phys &P, const double *__restrict__ z,
+                                             double *__restrict__ U, int color, long t, int lane)
+{
+    constexpr int NC = 3;
+    const int W = (P.nx + 1) / 2;
+    int j = (int)(t / W), kk = (int)(t % W);
+    int i = 2 * kk + ((j + color) & 1);
+    if (i >= P.nx) return;
+    const int f = lane >> 2, k = lane & 3;
+    const long N = (long)P.nx * P.ny;
+    const long idx = (long)j * P.nx + i;
+    const double eps = P.eps;
+    double qi[NC];
+    load_state<NC>(P, U, idx, qi);
+    const double zi = z[idx];
+    double qk[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) qk[c] = qi[c];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (k == c + 1) qk[c] = qk[c] + eps;
+    const Side mine = cell_side<NC>(P, qk, zi);
+    const double e = P.elen[f];
+    double T[NC];
+    int ni, nj;
+    if (neighbour(P, i, j, f, ni, nj)) {
+        long nidx = (long)nj * P.nx + ni;
+        double qj[NC];
+        load_state<NC>(P, U, nidx, qj);
+        Side oth = cell_side<NC>(P, qj, z[nidx]);
+        edge_term<NC>(P, f, mine, oth, T);
+    } else {
+        Side gh = ghost(P, f, mine);
+        edge_term<NC>(P, f, mine, gh, T);
+    }
+    double term[NC];    // lane k = 0: |e| T_0; lane k > 0: |e| (T_k - T_0) / eps
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        const double T0 = quad_bcast<0>(T[r]);
+        term[r] = (k == 0) ? e * T[r] : e * ((T[r] - T0) / eps);
+    }
+    double Rc[NC], D[NC][NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        Rc[r] = faces_sum<0>(term[r]);
+        D[r][0] = faces_sum<1>(term[r]);
+        D[r][1] = faces_sum<2>(term[r]);
+        D[r][2] = faces_sum<3>(term[r]);
+    }
+    if (lane != 0) return;
+    double nrm = l1norm<NC>(Rc);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
+    if (P.dry_pin && qi[0] == 0.0) {
+#pragma unroll
+        for (int r = 1; r < NC; ++r) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
+            D[r][r] = D[0][0];
+            Rc[r] = 0.0;
+        }
+    }
+    double M[NC * NC], d[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) M[r * NC + c] = D[r][c];
+    solve_block<double, NC>(M, Rc, d);
+    double q[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) q[c] = qi[c] - d[c];
+    if (q[0] < P.h_eps) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
+}
+
+__global__ void __launch_bounds__(kBlock) k_blu_half_x16(Phys P, const double *__restrict__ z,
+                                                         double *__restrict__ U, int color,
+                                                         const int *__restrict__ gate)
+{
+    if (gate && *gate) return;
+    const int W = (P.nx + 1) / 2;
+    const int xb = xcd_block(blockIdx.x, gridDim.x);
+    const long g = (long)xb * kBlock + threadIdx.x;
+    const long t = g >> 4;
+    if (t >= (long)W * P.ny) return;
+    blu_cell_x16(P, z, U, color, t, (int)(g & 15));
+}
+
 // Relaxed update U += tau_i dU (positivity-limited tau_i) and dry threshold.
 template <int NC, class T>
 __device__ __forceinline__ void update_cell(const Phys &P, const LevelGeom &G,
@@ -2681,11 +2809,16 @@ hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipS
     NMG_LAUNCH(k_count_u8, nblocks(n), v, n, partial);
 }
 
-hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, bool quad,
+hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int lanes,
                            hipStream_t s, const int *gate)
 {
     const long cells = (long)((P.nx + 1) / 2) * P.ny;
-    if (quad && cells <= kBluQuadMaxCells) {
+    if (lanes < 0) lanes = (cells <= kBluX16MaxCells) ? 16 : (cells <= kBluQuadMaxCells) ? 4 : 1;
+    if (lanes == 16 && P.dim == 2) {
+        int g = nblocks(16 * cells);
+        NMG_LAUNCH(k_blu_half_x16, g, P, z, U, color, gate);
+    }
+    if (lanes >= 4) {
         int g = nblocks(4 * cells);
         if (P.dim == 1) NMG_LAUNCH(k_blu_half_quad<2>, g, P, z, U, color, gate);
         NMG_LAUNCH(k_blu_half_quad<3>, g, P, z, U, color, gate);

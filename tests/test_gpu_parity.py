@@ -209,14 +209,18 @@ def test_vcycle_register_runs_bitwise(nmg, case, nus, gamma, reg, fp32, split, m
     same(host(x), oracle.vcycles(A, b, x0, p, 2), "x after cycles")
 
 
-@pytest.mark.parametrize("quad", ["1", "0"])
+@pytest.mark.parametrize("lanes", ["default", "1", "4", "16"])
 @pytest.mark.parametrize("k", [0, 1, 3, 7, 8, 9, 10, 12])
-def test_blu_sweep_bitwise(nmg, k, quad, monkeypatch):
-    """quad 1: four lanes per cell (one per forward-difference perturbation,
-    the default); 0: one lane per cell."""
+def test_blu_sweep_bitwise(nmg, k, lanes, monkeypatch):
+    """Lanes per cell of the BLU-SGS half sweep: 1, 4 (one per evaluation of
+    the forward differences), 16 (one per face and evaluation; 4 in 1D) or
+    the default choice by mesh size."""
     prob = PROBS[k]
-    say("blu", prob.name, quad)
-    monkeypatch.setenv("NMG_BLU_QUAD", quad)
+    say("blu", prob.name, lanes)
+    if lanes == "default":
+        monkeypatch.delenv("NMG_BLU_LANES", raising=False)
+    else:
+        monkeypatch.setenv("NMG_BLU_LANES", lanes)
     ctx = nmg.Context.from_problem(prob)
     z, U = dev(prob.z), dev(prob.U0)
     ctx.blu_sweep(z, U)
