@@ -278,15 +278,16 @@ def batched(args):
 
 
 def adjoint_gradients(args):
-    """Bed gradients of a gauge misfit: for each of `args.adjoint`
-    topographies (512^2 channels), the steady state (FP64 W-cycle Newton
-    multigrid), the objective sum over 64 gauges of (h + z - target)^2 with
-    targets from the steady state over a perturbed bed (untimed), and its
-    gradient through the autograd Function (adjoint multigrid solve to 1e-12
-    relative, then the bed vector-Jacobian product).  Timed: forward solve +
-    objective + backward, per topography, after one untimed gradient of the
-    first topography with a steady state (the first backward pass allocates
-    the adjoint's matrix and Krylov buffers and loads its kernels)."""
+    """Bed gradients of a gauge misfit on a batch of topographies (512^2
+    channels): the objective is the sum over 64 gauges of (h + z - target)^2
+    with targets from the steady state over a perturbed bed (one untimed
+    batched solve).  Timed: one batched FP64 W-cycle Newton solve of every
+    topography, then for each converged one the objective, its adjoint
+    multigrid solve (GMRES(30)-accelerated cycles to 1e-12 relative) and the
+    bed vector-Jacobian product, the topographies' adjoint solves running
+    concurrently on their own contexts and streams.  One untimed round
+    first (each context's first adjoint solve allocates its transposed matrix
+    and Krylov vectors).  Only converged topographies count."""
     import torch
     from paper_1608_06721_amd import adjoint, nmg
     from paper_1608_06721_amd import workloads as W
@@ -294,61 +295,52 @@ def adjoint_gradients(args):
     levels = int(math.log2(n)) - 4
     cases = W.gauge_cases(args.adjoint, size=n, n_levels=levels, gamma=2,
                           max_newton=args.max_newton)
-    ctx = nmg.Context.from_problem(cases[0].prob)
-    times, fwd, adj, steps, skipped = [], [], [], [], []
-    warm = True
-    for c in cases:
-        p = c.prob
-        Ut = torch.from_numpy(p.U0).cuda()
-        st = ctx.newton_mg_solve(torch.from_numpy(c.z_true).cuda(), Ut, args.tol)
-        if st["status"] != "OK":           # no steady state, no target: not a gradient case
-            skipped.append("%s (target solve %s)" % (p.name, st["status"]))
-            continue
-        g = torch.from_numpy(c.gauges).cuda()
-        target = (Ut[0] + torch.from_numpy(c.z_true).cuda()).reshape(-1)[g]
-        U0 = torch.from_numpy(p.U0).cuda()
-        if warm:
-            warm = False
-            try:
-                zw = torch.from_numpy(p.z).cuda().requires_grad_(True)
-                adjoint.gauge_misfit(adjoint.steady_state(ctx, zw, U0, tol=args.tol,
-                                                          adj_tol=1e-12), zw, g, target).backward()
-            except nmg.NMGError:
-                warm = True             # no gradient here: warm up on the next topography
-        z = torch.from_numpy(p.z).cuda().requires_grad_(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        try:
-            U = adjoint.steady_state(ctx, z, U0, tol=args.tol, adj_tol=1e-12)
-        except nmg.NMGError as e:
-            torch.cuda.synchronize()
-            skipped.append("%s (%s)" % (p.name, e))
-            continue
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        J = adjoint.gauge_misfit(U, z, g, target)
-        J.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        times.append(t2 - t0)
-        fwd.append(t1 - t0)
-        adj.append(t2 - t1)
-        steps.append(U.grad_fn.stats["newton_steps"])
-    ctx.close()
-    tot = sum(times)
-    ng = len(fwd)
-    print("[bench] adjoint: %d gradients in %.3f s (forward %.3f s), %d skipped"
-          % (ng, tot, sum(fwd), len(skipped)), file=sys.stderr, flush=True)
+    probs = [c.prob for c in cases]
+    # targets: steady states over the perturbed beds (one batched solve)
+    tb = nmg.Batch(probs)
+    Ut = [torch.from_numpy(p.U0).cuda() for p in probs]
+    zt = [torch.from_numpy(c.z_true).cuda() for c in cases]
+    tres = tb.newton_mg_solve(zt, Ut, args.tol)
+    tb.close()
+    gauges = [torch.from_numpy(c.gauges).cuda() for c in cases]
+    targets = [(Ut[k][0] + zt[k]).reshape(-1)[gauges[k]] for k in range(len(cases))]
+    keep = [k for k in range(len(cases)) if tres[k]["status"] == "OK"]
+    skipped = ["%s (target solve %s)" % (probs[k].name, tres[k]["status"])
+               for k in range(len(cases)) if k not in keep]
+
+    def objective(q, U, z):
+        k = keep[q]
+        return adjoint.gauge_misfit(U, z, gauges[k], targets[k])
+
+    bg = adjoint.BatchGradients([probs[k] for k in keep], tol=args.tol, adj_tol=1e-12)
+    zs = [torch.from_numpy(probs[k].z).cuda() for k in keep]
+    U0s = [torch.from_numpy(probs[k].U0).cuda() for k in keep]
+    bg(zs, U0s, objective)                         # untimed: first adjoint solves allocate
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    statuses, _, grads, cycles = bg(zs, U0s, objective)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    secs = dict(bg.last_seconds)
+    steps = list(bg.newton_steps)
+    bg.close()
+    ng = sum(g is not None for g in grads)
+    skipped += ["%s (steady solve %s)" % (probs[keep[q]].name, statuses[q])
+                for q in range(len(keep)) if grads[q] is None]
+    print("[bench] adjoint: %d gradients in %.3f s (batched forward %.3f s, concurrent "
+          "adjoints %.3f s), %d skipped" % (ng, dt, secs["forward"], secs["adjoint"],
+                                            len(skipped)), file=sys.stderr, flush=True)
     return {
-        "value": ng / tot if ng else None, "unit": "gradients/s", "topographies": len(cases),
-        "gradients": ng, "skipped": skipped,
-        "grid": "%dx%d" % (n, n), "ms_per_gradient": 1e3 * tot / max(ng, 1),
-        "ms_forward_mean": 1e3 * sum(fwd) / max(ng, 1),
-        "ms_adjoint_mean": 1e3 * sum(adj) / max(ng, 1),
-        "newton_steps_mean": float(sum(steps)) / max(len(steps), 1), "n_levels": levels,
-        "dtype": "f64", "gauges": 64, "adjoint_rel_tol": 1e-12,
-        "workload": "gauge misfit on %d channels %dx%d (seeds %d+b)" % (len(cases), n, n,
-                                                                      W.ADJOINT_SEED),
+        "value": ng / dt if ng else None, "unit": "gradients/s", "topographies": len(cases),
+        "gradients": ng, "skipped": skipped, "grid": "%dx%d" % (n, n),
+        "ms_per_batch": 1e3 * dt, "ms_forward_batch": 1e3 * secs["forward"],
+        "ms_adjoint_concurrent": 1e3 * secs["adjoint"],
+        "newton_steps_mean": float(sum(steps)) / max(len(steps), 1),
+        "adjoint_cycles_mean": float(sum(c for c in cycles if c)) / max(ng, 1),
+        "n_levels": levels, "dtype": "f64", "gauges": 64, "adjoint_rel_tol": 1e-12,
+        "workload": "gauge misfit on %d channels %dx%d (seeds %d+b), bed %s; forward solves "
+                    "batched, adjoint solves concurrent" % (len(cases), n, n, W.ADJOINT_SEED,
+                                                            describe_bed(W.ONE_ISLAND_BED)),
     }
 
 

@@ -227,3 +227,47 @@ def test_full_size_gradient_spot_check(nmg):
         gk = grad.ravel()[k]
         say("  cell", k, "fd", fd, "adjoint", gk)
         assert abs(fd - gk) <= 1e-5 * max(abs(fd), 1e-2 * scale), (k, fd, gk)
+
+
+def test_batch_gradients_equal_single_gradients(nmg):
+    """Batched bed gradients (one batched Newton solve of all topographies,
+    then concurrent adjoint solves on per-topography contexts and streams)
+    equal each topography's own autograd gradient bit for bit, with the same
+    statuses; topographies without a steady state get no gradient."""
+    from paper_1608_06721_amd import adjoint
+    cases = W.gauge_cases(5, size=64, n_gauges=16, n_levels=3, gamma=2, max_newton=80)
+    probs = [c.prob for c in cases]
+    targets = []
+    for c in cases:
+        ctx = nmg.Context.from_problem(c.prob)
+        Ut = dev(c.prob.U0)
+        ctx.newton_mg_solve(dev(c.z_true), Ut, 1e-10)
+        ctx.close()
+        targets.append((Ut[0] + dev(c.z_true)).reshape(-1)[torch.from_numpy(c.gauges).cuda()])
+    gauges = [torch.from_numpy(c.gauges).cuda() for c in cases]
+
+    def objective(k, U, z):
+        return adjoint.gauge_misfit(U, z, gauges[k], targets[k])
+
+    bg = adjoint.BatchGradients(probs)
+    try:
+        zs = [dev(p.z) for p in probs]
+        statuses, Us, grads, cycles = bg(zs, [dev(p.U0) for p in probs], objective)
+    finally:
+        bg.close()
+    say("batch gradients", statuses, cycles)
+    assert statuses.count("OK") >= 3
+    for k, p in enumerate(probs):
+        ctx = nmg.Context.from_problem(p)
+        z = dev(p.z).requires_grad_(True)
+        try:
+            U = adjoint.steady_state(ctx, z, dev(p.U0))
+        except nmg.NMGError:
+            ctx.close()
+            assert statuses[k] != "OK" and grads[k] is None
+            continue
+        assert statuses[k] == "OK"
+        same(host(Us[k]), host(U.detach()), "steady state %d" % k)
+        objective(k, U, z).backward()
+        same(host(grads[k]), host(z.grad), "gradient %d" % k)
+        ctx.close()
