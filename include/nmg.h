@@ -301,7 +301,11 @@ int nmg_timing_phases(nmg_ctx *ctx, double *ms_host, int *marks_host);
 typedef struct nmg_batch nmg_batch;
 
 /* grids[n], bcs[n] (host arrays), one params for all instances, stream as in
- * nmg_create.  Allocates one hierarchy per instance plus the work lists. */
+ * nmg_create.  Allocates one hierarchy per instance plus the work lists.
+ * Launch-structure switch read here (changes no bit of any result):
+ * NMG_BATCH_PERSISTENT = k > 0 runs the batched half sweeps on a persistent
+ * grid of k blocks per compute unit looping over the work list (default:
+ * one block per work item). */
 int nmg_batch_create(int n, const nmg_grid *grids, const nmg_bc *bcs,
                      const nmg_params *params, void *stream, nmg_batch **out);
 void nmg_batch_destroy(nmg_batch *batch);

@@ -127,9 +127,9 @@ hipError_t launch_isolated(const Phys &P, const double *z, const double *U, unsi
 hipError_t launch_assemble(const Phys &P, const LevelGeom &G, const double *z, const double *U,
                            const unsigned char *iso, void *A, void *b, bool f32, double *R_out,
                            double *partial, hipStream_t s);
-// gate (nullable): the launch does nothing while *gate is set (Step 1).
 hipError_t launch_residual(const Phys &P, const double *z, const double *U, double *R_out,
-                           double *partial, hipStream_t s, const int *gate = nullptr);
+                           double *partial, hipStream_t s);
+
 // Step 1 stop test on the device over n partials (k_step1_test) and the
 // reset of its control words {stop flag, sweeps done}.
 hipError_t launch_step1_test(const double *partial, int n, double thr, int max_sweeps, int *ctrl,
@@ -290,8 +290,11 @@ hipError_t launch_b_threshold(int dim, const BatchInst *bi, WorkRange w, const i
 // dir 0: Ulast = U, dir 1: U = Ulast.
 hipError_t launch_b_copy_state(int dim, const BatchInst *bi, WorkRange w, const int *active,
                                int dir, hipStream_t s);
+// persist > 0: a persistent grid of that many blocks looping over the work
+// list instead of one block per work item (kb_sgs_half_loop).
 hipError_t launch_b_sgs_half(int dim, bool f32, int mode, int tile, const BatchLevel *lv,
-                             WorkRange w, const int *active, int color, hipStream_t s);
+                             WorkRange w, const int *active, int color, int persist,
+                             hipStream_t s);
 hipError_t launch_b_restrict(int dim, bool f32, const BatchLevel *lv, WorkRange w,
                              const int *active, hipStream_t s);
 // Batched launch_sgs_half_res / launch_restrict_res (normal mode; each

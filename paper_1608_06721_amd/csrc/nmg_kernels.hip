@@ -16,6 +16,8 @@
 // piecewise-constant prolongation, red-black block Gauss-Seidel.
 #include "nmg_sgs.h"
 
+#include <algorithm>
+
 namespace nmg {
 namespace {
 
@@ -229,6 +231,18 @@ __device__ __forceinline__ double block_sum(double v)
         __syncthreads();
     }
     return sh[0];
+}
+
+// Value of lane Q of each aligned group of four lanes, in all four (DPP
+// quad_perm broadcast).
+template <int Q>
+__device__ __forceinline__ double quad_bcast(double v)
+{
+    constexpr int kCtrl = Q * 0x55;     // quad_perm [Q, Q, Q, Q]
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), kCtrl, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 // Residual and forward-difference blocks of one cell.  D receives
@@ -510,16 +524,12 @@ __device__ __forceinline__ double residual_cell(const Phys &P, const double *__r
     return nrm;
 }
 
-// gate (nullable): a flag set by the Step 1 stop test; the launch does
-// nothing once it is set.
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_residual(Phys P, const double *__restrict__ z,
                                                      const double *__restrict__ U,
                                                      double *__restrict__ R_out,
-                                                     double *__restrict__ partial,
-                                                     const int *__restrict__ gate)
+                                                     double *__restrict__ partial)
 {
-    if (gate && *gate) return;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     long idx = (long)xb * kBlock + threadIdx.x;
     double nrm = 0.0;
@@ -581,7 +591,8 @@ __global__ void __launch_bounds__(kBlock) k_count_u8(const unsigned char *__rest
 // threshold.  Cells of one colour only read the other colour.
 template <int NC>
 __device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict__ z,
-                                         double *__restrict__ U, int color, long t)
+                                         double *__restrict__ U, int color, long t,
+                                         const int *__restrict__ gate = nullptr)
 {
     const int W = (P.nx + 1) / 2;
     int j = (int)(t / W), k = (int)(t % W);
@@ -616,33 +627,24 @@ __device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = 0.0;
     }
+    if (gate && *gate) return;
 #pragma unroll
     for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
 }
 
+// gate (nullable): a flag set by the Step 1 stop test; once it is set the
+// launch stores nothing.  It is read with the cell's data and tested only
+// before the store, so its latency overlaps the arithmetic.
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__restrict__ z,
                                                      double *__restrict__ U, int color,
                                                      const int *__restrict__ gate)
 {
-    if (gate && *gate) return;
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     long t = (long)xb * kBlock + threadIdx.x;
     if (t >= (long)W * P.ny) return;
-    blu_cell<NC>(P, z, U, color, t);
-}
-
-// Value of lane Q of each aligned group of four lanes, in all four (DPP
-// quad_perm broadcast).
-template <int Q>
-__device__ __forceinline__ double quad_bcast(double v)
-{
-    constexpr int kCtrl = Q * 0x55;     // quad_perm [Q, Q, Q, Q]
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, kCtrl, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), kCtrl, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    blu_cell<NC>(P, z, U, color, t, gate);
 }
 
 // blu_cell with four lanes per cell, lane k of the cell's aligned quad
@@ -659,7 +661,8 @@ __device__ __forceinline__ double quad_bcast(double v)
 // one edge term (and ghost) per face instead of NC + 1.
 template <int NC>
 __device__ __forceinline__ void blu_cell_quad(const Phys &P, const double *__restrict__ z,
-                                              double *__restrict__ U, int color, long t, int k)
+                                              double *__restrict__ U, int color, long t, int k,
+                                              const int *__restrict__ gate)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const int W = (P.nx + 1) / 2;
@@ -740,7 +743,7 @@ __device__ __forceinline__ void blu_cell_quad(const Phys &P, const double *__res
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = 0.0;
     }
-    if (k == 0) {
+    if (k == 0 && !(gate && *gate)) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
     }
@@ -751,13 +754,12 @@ __global__ void __launch_bounds__(kBlock) k_blu_half_quad(Phys P, const double *
                                                           double *__restrict__ U, int color,
                                                           const int *__restrict__ gate)
 {
-    if (gate && *gate) return;
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     const long g = (long)xb * kBlock + threadIdx.x;
     const long t = g >> 2;
     if (t >= (long)W * P.ny) return;
-    blu_cell_quad<NC>(P, z, U, color, t, (int)(g & 3));
+    blu_cell_quad<NC>(P, z, U, color, t, (int)(g & 3), gate);
 }
 
 // Value of lane i + S of the 16-lane row (DPP row_shl:S; lanes whose source
@@ -797,7 +799,8 @@ __device__ __forceinline__ double faces_sum(double v)
 // so the result is the same bit for bit; a cell's chain of dependent
 // arithmetic is one edge term and one ghost state.
 __device__ __forceinline__ void blu_cell_x16(const Phys &P, const double *__restrict__ z,
-                                             double *__restrict__ U, int color, long t, int lane)
+                                             double *__restrict__ U, int color, long t, int lane,
+                                             const int *__restrict__ gate)
 {
     constexpr int NC = 3;
     const int W = (P.nx + 1) / 2;
@@ -845,7 +848,7 @@ __device__ __forceinline__ void blu_cell_x16(const Phys &P, const double *__rest
         D[r][1] = faces_sum<2>(term[r]);
         D[r][2] = faces_sum<3>(term[r]);
     }
-    if (lane != 0) return;
+    if (lane != 0 || (gate && *gate)) return;
     double nrm = l1norm<NC>(Rc);
 #pragma unroll
     for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
@@ -879,13 +882,12 @@ __global__ void __launch_bounds__(kBlock) k_blu_half_x16(Phys P, const double *_
                                                          double *__restrict__ U, int color,
                                                          const int *__restrict__ gate)
 {
-    if (gate && *gate) return;
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     const long g = (long)xb * kBlock + threadIdx.x;
     const long t = g >> 4;
     if (t >= (long)W * P.ny) return;
-    blu_cell_x16(P, z, U, color, t, (int)(g & 15));
+    blu_cell_x16(P, z, U, color, t, (int)(g & 15), gate);
 }
 
 // Relaxed update U += tau_i dU (positivity-limited tau_i) and dry threshold.
@@ -2655,6 +2657,24 @@ __global__ void __launch_bounds__(TB) kb_sgs_half(const BatchLevel *__restrict__
                               (const T *)L.xc, t);
 }
 
+// kb_sgs_half as a persistent kernel: a fixed grid whose blocks loop over
+// the work list (block b takes items b, b + gridDim.x, ...).
+template <class T, int NC, int MODE, int TB>
+__global__ void __launch_bounds__(TB) kb_sgs_half_loop(const BatchLevel *__restrict__ lv,
+                                                       WorkRange w,
+                                                       const int *__restrict__ active, int color)
+{
+    for (int pos = blockIdx.x; pos < w.n; pos += gridDim.x) {
+        const WorkItem it = w.items[pos];
+        if (!active[it.inst]) continue;
+        const BatchLevel L = global_view(lv[it.inst]);
+        const long t = (long)it.tile * TB + threadIdx.x;
+        if (t < L.G.plane)
+            sgs_cell<T, NC, MODE>(L.G, (const T *)L.A, nullptr, (const T *)L.b, (T *)L.x, color,
+                                  L.Gc, (const T *)L.xc, t);
+    }
+}
+
 template <class T, int NC, int TB>
 __global__ void __launch_bounds__(TB) kb_sgs_half_res(const BatchLevel *__restrict__ lv,
                                                       WorkRange w, const int *__restrict__ active,
@@ -2780,11 +2800,11 @@ hipError_t launch_assemble(const Phys &P, const LevelGeom &G, const double *z, c
 }
 
 hipError_t launch_residual(const Phys &P, const double *z, const double *U, double *R_out,
-                           double *partial, hipStream_t s, const int *gate)
+                           double *partial, hipStream_t s)
 {
     int g = nblocks((long)P.nx * P.ny);
-    if (P.dim == 1) NMG_LAUNCH(k_residual<2>, g, P, z, U, R_out, partial, gate);
-    NMG_LAUNCH(k_residual<3>, g, P, z, U, R_out, partial, gate);
+    if (P.dim == 1) NMG_LAUNCH(k_residual<2>, g, P, z, U, R_out, partial);
+    NMG_LAUNCH(k_residual<3>, g, P, z, U, R_out, partial);
 }
 
 hipError_t launch_step1_test(const double *partial, int n, double thr, int max_sweeps, int *ctrl,
@@ -3231,11 +3251,31 @@ hipError_t launch_b_copy_state(int dim, const BatchInst *bi, WorkRange w, const 
     NMG_BLAUNCH(kb_copy_state<3>, bi, w, active, dir);
 }
 
+// persist > 0: the persistent form with that many blocks (at most one per
+// work item).
 template <class T, int NC, int TB>
 static hipError_t bsgs_mode(int mode, const BatchLevel *lv, WorkRange w, const int *active,
-                            int color, hipStream_t s)
+                            int color, int persist, hipStream_t s)
 {
     if (w.n <= 0) return hipSuccess;
+    if (persist > 0) {
+        const dim3 g(std::min(w.n, persist));
+        switch (mode) {
+        case MODE_NORMAL:
+            hipLaunchKernelGGL((kb_sgs_half_loop<T, NC, MODE_NORMAL, TB>), g, dim3(TB), 0, s, lv, w, active, color);
+            break;
+        case MODE_ZERO:
+            hipLaunchKernelGGL((kb_sgs_half_loop<T, NC, MODE_ZERO, TB>), g, dim3(TB), 0, s, lv, w, active, color);
+            break;
+        case MODE_PROLONG:
+            hipLaunchKernelGGL((kb_sgs_half_loop<T, NC, MODE_PROLONG, TB>), g, dim3(TB), 0, s, lv, w, active, color);
+            break;
+        default:
+            hipLaunchKernelGGL((kb_sgs_half_loop<T, NC, MODE_PROLONG_ZERO, TB>), g, dim3(TB), 0, s, lv, w, active, color);
+            break;
+        }
+        return hipGetLastError();
+    }
     switch (mode) {
     case MODE_NORMAL:
         hipLaunchKernelGGL((kb_sgs_half<T, NC, MODE_NORMAL, TB>), dim3(w.n), dim3(TB), 0, s, lv, w, active, color);
@@ -3255,26 +3295,27 @@ static hipError_t bsgs_mode(int mode, const BatchLevel *lv, WorkRange w, const i
 
 template <class T, int NC>
 static hipError_t bsgs_tile(int mode, int tile, const BatchLevel *lv, WorkRange w,
-                            const int *active, int color, hipStream_t s)
+                            const int *active, int color, int persist, hipStream_t s)
 {
     switch (tile) {
-    case 64: return bsgs_mode<T, NC, 64>(mode, lv, w, active, color, s);
-    case 128: return bsgs_mode<T, NC, 128>(mode, lv, w, active, color, s);
-    case 256: return bsgs_mode<T, NC, 256>(mode, lv, w, active, color, s);
-    case 512: return bsgs_mode<T, NC, 512>(mode, lv, w, active, color, s);
+    case 64: return bsgs_mode<T, NC, 64>(mode, lv, w, active, color, persist, s);
+    case 128: return bsgs_mode<T, NC, 128>(mode, lv, w, active, color, persist, s);
+    case 256: return bsgs_mode<T, NC, 256>(mode, lv, w, active, color, persist, s);
+    case 512: return bsgs_mode<T, NC, 512>(mode, lv, w, active, color, persist, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_b_sgs_half(int dim, bool f32, int mode, int tile, const BatchLevel *lv,
-                             WorkRange w, const int *active, int color, hipStream_t s)
+                             WorkRange w, const int *active, int color, int persist,
+                             hipStream_t s)
 {
     if (f32) {
-        if (dim == 1) return bsgs_tile<float, 2>(mode, tile, lv, w, active, color, s);
-        return bsgs_tile<float, 3>(mode, tile, lv, w, active, color, s);
+        if (dim == 1) return bsgs_tile<float, 2>(mode, tile, lv, w, active, color, persist, s);
+        return bsgs_tile<float, 3>(mode, tile, lv, w, active, color, persist, s);
     }
-    if (dim == 1) return bsgs_tile<double, 2>(mode, tile, lv, w, active, color, s);
-    return bsgs_tile<double, 3>(mode, tile, lv, w, active, color, s);
+    if (dim == 1) return bsgs_tile<double, 2>(mode, tile, lv, w, active, color, persist, s);
+    return bsgs_tile<double, 3>(mode, tile, lv, w, active, color, persist, s);
 }
 
 template <class T>

@@ -106,6 +106,10 @@ CASES = {
     # a step limit that stops some instances before others converge
     "step_limit": (lambda: W.batch_channels(4, sizes=(32, 64), seed=14, n_levels=3,
                                             max_newton=9), 1e-10, "1024"),
+    # the half sweeps on a persistent grid (one block per compute unit) looping
+    # over the work list, every level launched with one half sweep per launch
+    "persistent": (lambda: W.batch_channels(4, sizes=(32, 64, 96), seed=15, n_levels=3,
+                                            gamma=2, max_newton=40), 1e-10, "0", "1", "1"),
 }
 
 
@@ -114,6 +118,7 @@ def test_batch_matches_oracle_and_single(nmg, case, monkeypatch):
     mk, tol, cc = CASES[case][:3]
     monkeypatch.setenv("NMG_COARSE_CELLS", cc)
     monkeypatch.setenv("NMG_FUSE", CASES[case][3] if len(CASES[case]) > 3 else "3")
+    monkeypatch.setenv("NMG_BATCH_PERSISTENT", CASES[case][4] if len(CASES[case]) > 4 else "0")
     probs = mk()
     say(case, [p.name for p in probs])
     Ub, rb = run_batch(nmg, probs, tol)
