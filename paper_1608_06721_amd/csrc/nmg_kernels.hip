@@ -248,12 +248,15 @@ __device__ __forceinline__ double quad_bcast(double v)
 // Residual and forward-difference blocks of one cell.  D receives
 // sum_e |e| dT/dU_i, Off[f] receives |e| dT/dU_j for interior faces.
 // Off-diagonal blocks are handed to `off(f, r, k, value)` as soon as face f
-// is done (value 0 on boundary faces), so no per-face array is kept.
+// is done (value 0 on boundary faces), so no per-face array is kept.  With
+// UNROLL the face loop is unrolled, so that each face's orientation (which
+// side is left, which momentum is normal) is fixed at compile time instead
+// of being selected per evaluation: about 30 % fewer instructions.
 struct NoOff {
     __device__ void operator()(int, int, int, double) const {}
 };
 
-template <int NC, bool WANT_OFF, class OffSink>
+template <int NC, bool WANT_OFF, bool UNROLL, class OffSink>
 __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, const double *U, int i,
                                               int j, double *Rc, double (*D)[NC], const OffSink &off)
 {
@@ -279,16 +282,37 @@ __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, co
 #pragma unroll
         for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
     }
-    for (int f = 0; f < NF; ++f) {
+    // Without the off-diagonal blocks, the neighbours' states are all loaded
+    // before any face is evaluated so that their latencies overlap (a
+    // boundary face loads the cell itself, unused); with them, that would
+    // take the kernel past 256 registers, so each face loads its own.
+    double qn[NF][NC], zn[NF];
+    bool inner_f[NF];
+    if constexpr (!WANT_OFF) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            int ni, nj;
+            inner_f[f] = neighbour(P, i, j, f, ni, nj);
+            const long nidx = inner_f[f] ? (long)nj * P.nx + ni : idx;
+            load_state<NC>(P, U, nidx, qn[f]);
+            zn[f] = z[nidx];
+        }
+    }
+    auto face = [&](int f) {
         const double e = P.elen[f];
-        int ni, nj;
-        bool inner = neighbour(P, i, j, f, ni, nj);
         double T0[NC], Tk[NC];
-        if (inner) {
-            long nidx = (long)nj * P.nx + ni;
-            double qj[NC];
-            load_state<NC>(P, U, nidx, qj);
-            double zj = z[nidx];
+        if constexpr (WANT_OFF) {
+            int ni, nj;
+            inner_f[f] = neighbour(P, i, j, f, ni, nj);
+            if (inner_f[f]) {
+                const long nidx = (long)nj * P.nx + ni;
+                load_state<NC>(P, U, nidx, qn[f]);
+                zn[f] = z[nidx];
+            }
+        }
+        if (inner_f[f]) {
+            const double *qj = qn[f];
+            const double zj = zn[f];
             Side oth = cell_side<NC>(P, qj, zj);
             edge_term<NC>(P, f, own, oth, T0);
 #pragma unroll
@@ -331,6 +355,13 @@ __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, co
                     for (int c = 0; c < NC; ++c) off(f, r, c, 0.0);
             }
         }
+    };
+    if constexpr (UNROLL) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) face(f);
+    } else {
+#pragma unroll 1
+        for (int f = 0; f < NF; ++f) face(f);
     }
 }
 
@@ -358,6 +389,7 @@ __device__ __forceinline__ void isolated_cell(const Phys &P, const double *__res
     load_state<NC>(P, U, idx, qi);
     Side own = cell_side<NC>(P, qi, z[idx]);
     unsigned char res = 1;
+#pragma unroll
     for (int f = 0; f < NF; ++f) {
         int ni, nj;
         Side oth;
@@ -431,7 +463,7 @@ __device__ __forceinline__ double assemble_cell(const Phys &P, const LevelGeom &
             st.nb_iso[f] = f < NF && neighbour(P, i, j, f, ni, nj) && iso[(long)nj * P.nx + ni];
         }
         double Rc[NC], D[NC][NC];
-        cell_jacobian<NC, true>(P, z, U, i, j, Rc, D, st);
+        cell_jacobian<NC, true, sizeof(T) == 8>(P, z, U, i, j, Rc, D, st);
         if (R_out) {
 #pragma unroll
             for (int r = 0; r < NC; ++r) R_out[r * N + idx] = Rc[r];
@@ -465,7 +497,7 @@ __device__ __forceinline__ double assemble_cell(const Phys &P, const LevelGeom &
 }
 
 template <int NC, class T>
-__global__ void __launch_bounds__(kBlock) k_assemble(Phys P, LevelGeom G,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) k_assemble(Phys P, LevelGeom G,
                                                      const double *__restrict__ z,
                                                      const double *__restrict__ U,
                                                      const unsigned char *__restrict__ iso,
@@ -499,14 +531,23 @@ __device__ __forceinline__ double residual_cell(const Phys &P, const double *__r
         double Rc[NC];
 #pragma unroll
         for (int r = 0; r < NC; ++r) Rc[r] = 0.0;
+        // neighbour states loaded up front (a boundary face loads the cell
+        // itself, unused)
+        double qn[NF][NC], zn[NF];
+        bool inner_f[NF];
+#pragma unroll
         for (int f = 0; f < NF; ++f) {
             int ni, nj;
+            inner_f[f] = neighbour(P, i, j, f, ni, nj);
+            const long nidx = inner_f[f] ? (long)nj * P.nx + ni : idx;
+            load_state<NC>(P, U, nidx, qn[f]);
+            zn[f] = z[nidx];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
             Side oth;
-            if (neighbour(P, i, j, f, ni, nj)) {
-                long nidx = (long)nj * P.nx + ni;
-                double qj[NC];
-                load_state<NC>(P, U, nidx, qj);
-                oth = cell_side<NC>(P, qj, z[nidx]);
+            if (inner_f[f]) {
+                oth = cell_side<NC>(P, qn[f], zn[f]);
             } else {
                 oth = ghost(P, f, own);
             }
@@ -601,7 +642,7 @@ __device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict
     const long N = (long)P.nx * P.ny;
     const long idx = (long)j * P.nx + i;
     double Rc[NC], D[NC][NC];
-    cell_jacobian<NC, false>(P, z, U, i, j, Rc, D, NoOff());
+    cell_jacobian<NC, false, true>(P, z, U, i, j, Rc, D, NoOff());
     double nrm = l1norm<NC>(Rc);
 #pragma unroll
     for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
@@ -686,6 +727,7 @@ __device__ __forceinline__ void blu_cell_quad(const Phys &P, const double *__res
     double acc[NC];     // lane 0: R_i; lane k: column k-1 of sum_e |e| dT/dU_i
 #pragma unroll
     for (int r = 0; r < NC; ++r) acc[r] = 0.0;
+#pragma unroll
     for (int f = 0; f < NF; ++f) {
         const double e = P.elen[f];
         int ni, nj;
@@ -2519,7 +2561,7 @@ __global__ void __launch_bounds__(kBlock) kb_isolated(const BatchInst *__restric
 }
 
 template <int NC, class T>
-__global__ void __launch_bounds__(kBlock) kb_assemble(const BatchInst *__restrict__ bi,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) kb_assemble(const BatchInst *__restrict__ bi,
                                                       WorkRange w, const int *__restrict__ active,
                                                       double *__restrict__ partial)
 {
