@@ -966,7 +966,6 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
     // ahead (2, 4, ... up to kStep1Ahead) and the host reads the flag once per
     // run; launches after the stop do nothing.  The sweeps performed are
     // those of the loop with the test on the host.
-    const int order[4] = {0, 1, 1, 0};
     int *ctrl = reinterpret_cast<int *>(c->scal + 1);
     int *h_ctrl = reinterpret_cast<int *>(c->h_scal + 1);
     for (int l = NL; l >= 1; --l) {
@@ -981,9 +980,8 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
                                           c->stream));
                 HIPCHK(c, launch_step1_test(c->partial, nparts, thr, c->prm.init_max_sweeps, ctrl,
                                             c->stream));
-                for (int q = 0; q < 4; ++q)
-                    HIPCHK(c, launch_blu_half(P, c->zl[l], c->Ul[l], order[q], c->blu_lanes,
-                                              c->stream, ctrl));
+                HIPCHK(c, launch_blu_sweeps(P, c->zl[l], c->Ul[l], 1, c->blu_lanes, c->stream,
+                                            ctrl));
             }
             HIPCHK(c, hipMemcpyAsync(h_ctrl, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                      c->stream));
@@ -1233,9 +1231,7 @@ int nmg_blu_sweep(nmg_ctx *c, const double *z, double *U)
 {
     if (!c) return NMG_EINVAL;
     if (!z || !U) return fail(c, NMG_EINVAL, "null z or U");
-    const int order[4] = {0, 1, 1, 0};
-    for (int k = 0; k < 4; ++k)
-        HIPCHK(c, launch_blu_half(c->P, z, U, order[k], c->blu_lanes, c->stream));
+    HIPCHK(c, launch_blu_sweeps(c->P, z, U, 1, c->blu_lanes, c->stream));
     return NMG_OK;
 }
 
@@ -1277,8 +1273,7 @@ int nmg_newton_mg_solve(nmg_ctx *c, const double *z, double *U, double tol, nmg_
     if ((rc = phase_mark(c, NMG_PHASE_STEP1))) return rc;
     for (n = 0; n < p.max_newton; ++n) {
         HIPCHK(c, hipMemcpyAsync(c->Ulast, U, vbytes, hipMemcpyDeviceToDevice, c->stream));
-        for (int s = 0; s < p.blu_sweeps; ++s)
-            if ((rc = nmg_blu_sweep(c, z, U))) return rc;
+        HIPCHK(c, launch_blu_sweeps(c->P, z, U, p.blu_sweeps, c->blu_lanes, c->stream));
         if ((rc = phase_mark(c, NMG_PHASE_BLU))) return rc;
         if ((rc = assemble(c, z, U, nullptr, &res))) return rc;
         if (st && st->res_hist && n < st->hist_cap) st->res_hist[n] = res;

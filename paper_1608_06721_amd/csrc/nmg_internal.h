@@ -149,8 +149,14 @@ constexpr long kBluQuadMaxCells = 1L << 16;
 // 2D meshes of at most kBluX16MaxCells cells per colour run the half sweep
 // with sixteen lanes per cell (k_blu_half_x16: one per face and evaluation).
 constexpr long kBluX16MaxCells = 1L << 14;
-hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int lanes,
-                           hipStream_t s, const int *gate = nullptr);
+// reps consecutive half sweeps of one colour in one launch (each cell
+// updated reps times from its neighbours' unchanged states).
+hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int reps,
+                           int lanes, hipStream_t s, const int *gate = nullptr);
+// n symmetric BLU-SGS sweeps (half sweeps of colours 0, 1, 1, 0 each), runs
+// of one colour merged into single launches: 0, 1 x2, 0 for one sweep.
+hipError_t launch_blu_sweeps(const Phys &P, const double *z, double *U, int n, int lanes,
+                             hipStream_t s, const int *gate = nullptr);
 hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool f32, double *U,
                          hipStream_t s);
 hipError_t launch_threshold(const Phys &P, double *U, hipStream_t s);

@@ -69,7 +69,11 @@ __device__ __forceinline__ void num_flux(const Phys &P, int axis, double hL, dou
     double unR = (axis == 0) ? uR : vR;
     double cL = dsqrt(g * hL), cR = dsqrt(g * hR);
     if (P.flux == 1) {
-        double s = dmax(dabs(unL) + cL, dabs(unR) + cR) + P.eps_r * dsqrt(g * dmax(hL, hR));
+        // sqrt(g max(hL, hR)) is max(cL, cR) bit for bit: with g > 0 the
+        // rounded product and the correctly rounded square root are monotone
+        // and keep the sign of zero, and dmax returns its second operand on
+        // ties, so both forms pick the same operand's value.
+        double s = dmax(dabs(unL) + cL, dabs(unR) + cR) + P.eps_r * dmax(cL, cR);
 #pragma unroll
         for (int k = 0; k < NC; ++k) out[k] = 0.5 * ((FL[k] + FR[k]) - s * (UR[k] - UL[k]));
         return;
@@ -256,16 +260,57 @@ struct NoOff {
     __device__ void operator()(int, int, int, double) const {}
 };
 
-template <int NC, bool WANT_OFF, bool UNROLL, class OffSink>
-__device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, const double *U, int i,
-                                              int j, double *Rc, double (*D)[NC], const OffSink &off)
+// The states and beds of a cell's face neighbours, loaded together so that
+// their latencies overlap (a boundary face holds the cell itself, unused).
+template <int NC>
+struct Nbrs {
+    double q[4][NC], z[4];
+    bool inner[4];
+};
+
+// An empty register constraint on the neighbours' values: the compiler must
+// take them as changed here, so arithmetic on them stays inside a loop of
+// cell updates instead of being hoisted out of it and kept live in extra
+// registers across the loop.
+template <int NC>
+__device__ __forceinline__ void opaque_nbrs(Nbrs<NC> &nb)
+{
+    const int NF = (NC == 2) ? 2 : 4;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) asm volatile("" : "+v"(nb.q[f][c]));
+        asm volatile("" : "+v"(nb.z[f]));
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ void load_nbrs(const Phys &P, const double *z, const double *U, int i,
+                                          int j, Nbrs<NC> &nb)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const long idx = (long)j * P.nx + i;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        int ni, nj;
+        nb.inner[f] = neighbour(P, i, j, f, ni, nj);
+        const long nidx = nb.inner[f] ? (long)nj * P.nx + ni : idx;
+        load_state<NC>(P, U, nidx, nb.q[f]);
+        nb.z[f] = z[nidx];
+    }
+}
+
+// cell_jacobian at the cell state qi (bed zi).  With PRE the neighbours come
+// from nb; otherwise each face loads its own (with the off-diagonal blocks,
+// loading them all first would take the kernel past 256 registers).
+template <int NC, bool WANT_OFF, bool UNROLL, bool PRE, class OffSink>
+__device__ __forceinline__ void cell_jacobian_at(const Phys &P, const double *z, const double *U,
+                                                 int i, int j, const double *qi, double zi,
+                                                 const Nbrs<NC> &nb, double *Rc, double (*D)[NC],
+                                                 const OffSink &off)
+{
+    const int NF = (NC == 2) ? 2 : 4;
     const double eps = P.eps;
-    double qi[NC];
-    load_state<NC>(P, U, idx, qi);
-    const double zi = z[idx];
     Side own = cell_side<NC>(P, qi, zi);
     Side ownp[NC];
 #pragma unroll
@@ -282,37 +327,26 @@ __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, co
 #pragma unroll
         for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
     }
-    // Without the off-diagonal blocks, the neighbours' states are all loaded
-    // before any face is evaluated so that their latencies overlap (a
-    // boundary face loads the cell itself, unused); with them, that would
-    // take the kernel past 256 registers, so each face loads its own.
-    double qn[NF][NC], zn[NF];
-    bool inner_f[NF];
-    if constexpr (!WANT_OFF) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            int ni, nj;
-            inner_f[f] = neighbour(P, i, j, f, ni, nj);
-            const long nidx = inner_f[f] ? (long)nj * P.nx + ni : idx;
-            load_state<NC>(P, U, nidx, qn[f]);
-            zn[f] = z[nidx];
-        }
-    }
     auto face = [&](int f) {
         const double e = P.elen[f];
         double T0[NC], Tk[NC];
-        if constexpr (WANT_OFF) {
+        bool inner;
+        double qj[NC], zj;
+        if constexpr (PRE) {
+            inner = nb.inner[f];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) qj[c] = nb.q[f][c];
+            zj = nb.z[f];
+        } else {
             int ni, nj;
-            inner_f[f] = neighbour(P, i, j, f, ni, nj);
-            if (inner_f[f]) {
+            inner = neighbour(P, i, j, f, ni, nj);
+            if (inner) {
                 const long nidx = (long)nj * P.nx + ni;
-                load_state<NC>(P, U, nidx, qn[f]);
-                zn[f] = z[nidx];
+                load_state<NC>(P, U, nidx, qj);
+                zj = z[nidx];
             }
         }
-        if (inner_f[f]) {
-            const double *qj = qn[f];
-            const double zj = zn[f];
+        if (inner) {
             Side oth = cell_side<NC>(P, qj, zj);
             edge_term<NC>(P, f, own, oth, T0);
 #pragma unroll
@@ -363,6 +397,17 @@ __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, co
 #pragma unroll 1
         for (int f = 0; f < NF; ++f) face(f);
     }
+}
+
+template <int NC, bool WANT_OFF, bool UNROLL, class OffSink>
+__device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, const double *U, int i,
+                                              int j, double *Rc, double (*D)[NC], const OffSink &off)
+{
+    const long idx = (long)j * P.nx + i;
+    double qi[NC];
+    load_state<NC>(P, U, idx, qi);
+    Nbrs<NC> none;
+    cell_jacobian_at<NC, WANT_OFF, UNROLL, false>(P, z, U, i, j, qi, z[idx], none, Rc, D, off);
 }
 
 template <int NC>
@@ -531,23 +576,13 @@ __device__ __forceinline__ double residual_cell(const Phys &P, const double *__r
         double Rc[NC];
 #pragma unroll
         for (int r = 0; r < NC; ++r) Rc[r] = 0.0;
-        // neighbour states loaded up front (a boundary face loads the cell
-        // itself, unused)
-        double qn[NF][NC], zn[NF];
-        bool inner_f[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            int ni, nj;
-            inner_f[f] = neighbour(P, i, j, f, ni, nj);
-            const long nidx = inner_f[f] ? (long)nj * P.nx + ni : idx;
-            load_state<NC>(P, U, nidx, qn[f]);
-            zn[f] = z[nidx];
-        }
+        Nbrs<NC> nb;
+        load_nbrs<NC>(P, z, U, i, j, nb);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             Side oth;
-            if (inner_f[f]) {
-                oth = cell_side<NC>(P, qn[f], zn[f]);
+            if (nb.inner[f]) {
+                oth = cell_side<NC>(P, nb.q[f], nb.z[f]);
             } else {
                 oth = ghost(P, f, own);
             }
@@ -627,26 +662,17 @@ __global__ void __launch_bounds__(kBlock) k_count_u8(const unsigned char *__rest
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// One BLU-SGS cell update for every cell of one colour (Algorithm 1,
-// Step 2.1): U_i -= (alpha ||R_i||_1 I + dR_i/dU_i)^-1 R_i, then the dry
-// threshold.  Cells of one colour only read the other colour.
+// The regularized block of one BLU-SGS update and its solution: D gets
+// alpha ||R_i||_1 on its diagonal, a dry cell under the dry-cell pin (h = 0)
+// keeps only its depth row, and d solves D d = R_i; then the new state
+// q - d, with the dry threshold (every component 0 below h_eps).
 template <int NC>
-__device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict__ z,
-                                         double *__restrict__ U, int color, long t,
-                                         const int *__restrict__ gate = nullptr)
+__device__ __forceinline__ void blu_solve(const Phys &P, double *Rc, double (*D)[NC], double *q)
 {
-    const int W = (P.nx + 1) / 2;
-    int j = (int)(t / W), k = (int)(t % W);
-    int i = 2 * k + ((j + color) & 1);
-    if (i >= P.nx) return;
-    const long N = (long)P.nx * P.ny;
-    const long idx = (long)j * P.nx + i;
-    double Rc[NC], D[NC][NC];
-    cell_jacobian<NC, false, true>(P, z, U, i, j, Rc, D, NoOff());
     double nrm = l1norm<NC>(Rc);
 #pragma unroll
     for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
-    if (P.dry_pin && U[idx] == 0.0) {
+    if (P.dry_pin && q[0] == 0.0) {
 #pragma unroll
         for (int r = 1; r < NC; ++r) {
 #pragma unroll
@@ -661,12 +687,41 @@ __device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict
 #pragma unroll
         for (int c = 0; c < NC; ++c) M[r * NC + c] = D[r][c];
     solve_block<double, NC>(M, Rc, d);
-    double q[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) q[c] = U[c * N + idx] - d[c];
+    for (int c = 0; c < NC; ++c) q[c] = q[c] - d[c];
     if (q[0] < P.h_eps) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = 0.0;
+    }
+}
+
+// One BLU-SGS cell update for every cell of one colour (Algorithm 1,
+// Step 2.1): U_i -= (alpha ||R_i||_1 I + dR_i/dU_i)^-1 R_i, then the dry
+// threshold.  Cells of one colour only read the other colour, so `reps`
+// consecutive half sweeps of the same colour are `reps` updates of each cell
+// from its neighbours' unchanged states: one launch does them with the
+// state kept in registers, the same arithmetic as `reps` launches.
+template <int NC>
+__device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict__ z,
+                                         double *__restrict__ U, int color, long t, int reps = 1,
+                                         const int *__restrict__ gate = nullptr)
+{
+    const int W = (P.nx + 1) / 2;
+    int j = (int)(t / W), k = (int)(t % W);
+    int i = 2 * k + ((j + color) & 1);
+    if (i >= P.nx) return;
+    const long N = (long)P.nx * P.ny;
+    const long idx = (long)j * P.nx + i;
+    double q[NC];
+    load_state<NC>(P, U, idx, q);
+    const double zi = z[idx];
+    Nbrs<NC> nb;
+    load_nbrs<NC>(P, z, U, i, j, nb);
+    for (int rep = 0; rep < reps; ++rep) {
+        opaque_nbrs<NC>(nb);
+        double Rc[NC], D[NC][NC];
+        cell_jacobian_at<NC, false, true, true>(P, z, U, i, j, q, zi, nb, Rc, D, NoOff());
+        blu_solve<NC>(P, Rc, D, q);
     }
     if (gate && *gate) return;
 #pragma unroll
@@ -678,14 +733,14 @@ __device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict
 // before the store, so its latency overlaps the arithmetic.
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__restrict__ z,
-                                                     double *__restrict__ U, int color,
+                                                     double *__restrict__ U, int color, int reps,
                                                      const int *__restrict__ gate)
 {
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     long t = (long)xb * kBlock + threadIdx.x;
     if (t >= (long)W * P.ny) return;
-    blu_cell<NC>(P, z, U, color, t, gate);
+    blu_cell<NC>(P, z, U, color, t, reps, gate);
 }
 
 // blu_cell with four lanes per cell, lane k of the cell's aligned quad
@@ -703,7 +758,7 @@ __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__res
 template <int NC>
 __device__ __forceinline__ void blu_cell_quad(const Phys &P, const double *__restrict__ z,
                                               double *__restrict__ U, int color, long t, int k,
-                                              const int *__restrict__ gate)
+                                              int reps, const int *__restrict__ gate)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const int W = (P.nx + 1) / 2;
@@ -716,92 +771,69 @@ __device__ __forceinline__ void blu_cell_quad(const Phys &P, const double *__res
     double qi[NC];
     load_state<NC>(P, U, idx, qi);
     const double zi = z[idx];
-    // this lane's own side: unperturbed (k = 0) or component k-1 + eps
-    double qk[NC];
+    Nbrs<NC> nb;
+    load_nbrs<NC>(P, z, U, i, j, nb);
+    for (int rep = 0; rep < reps; ++rep) {
+        opaque_nbrs<NC>(nb);
+        // this lane's own side: unperturbed (k = 0) or component k-1 + eps
+        double qk[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) qk[c] = qi[c];
+        for (int c = 0; c < NC; ++c) qk[c] = qi[c];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-        if (k == c + 1) qk[c] = qk[c] + eps;
-    const Side mine = cell_side<NC>(P, qk, zi);
-    double acc[NC];     // lane 0: R_i; lane k: column k-1 of sum_e |e| dT/dU_i
+        for (int c = 0; c < NC; ++c)
+            if (k == c + 1) qk[c] = qk[c] + eps;
+        const Side mine = cell_side<NC>(P, qk, zi);
+        double acc[NC];     // lane 0: R_i; lane k: column k-1 of sum_e |e| dT/dU_i
 #pragma unroll
-    for (int r = 0; r < NC; ++r) acc[r] = 0.0;
+        for (int r = 0; r < NC; ++r) acc[r] = 0.0;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        const double e = P.elen[f];
-        int ni, nj;
-        double T[NC], T0[NC];
-        if (neighbour(P, i, j, f, ni, nj)) {
-            long nidx = (long)nj * P.nx + ni;
-            double qj[NC];
-            load_state<NC>(P, U, nidx, qj);
-            Side oth = cell_side<NC>(P, qj, z[nidx]);
-            edge_term<NC>(P, f, mine, oth, T);
-        } else {
-            Side gh = ghost(P, f, mine);
-            edge_term<NC>(P, f, mine, gh, T);
+        for (int f = 0; f < NF; ++f) {
+            const double e = P.elen[f];
+            double T[NC], T0[NC];
+            if (nb.inner[f]) {
+                Side oth = cell_side<NC>(P, nb.q[f], nb.z[f]);
+                edge_term<NC>(P, f, mine, oth, T);
+            } else {
+                Side gh = ghost(P, f, mine);
+                edge_term<NC>(P, f, mine, gh, T);
+            }
+#pragma unroll
+            for (int r = 0; r < NC; ++r) T0[r] = quad_bcast<0>(T[r]);
+            if (k == 0) {
+#pragma unroll
+                for (int r = 0; r < NC; ++r) acc[r] = acc[r] + e * T[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < NC; ++r) acc[r] = acc[r] + e * ((T[r] - T0[r]) / eps);
+            }
         }
+        double Rc[NC], D[NC][NC];
 #pragma unroll
-        for (int r = 0; r < NC; ++r) T0[r] = quad_bcast<0>(T[r]);
-        if (k == 0) {
-#pragma unroll
-            for (int r = 0; r < NC; ++r) acc[r] = acc[r] + e * T[r];
-        } else {
-#pragma unroll
-            for (int r = 0; r < NC; ++r) acc[r] = acc[r] + e * ((T[r] - T0[r]) / eps);
+        for (int r = 0; r < NC; ++r) {
+            Rc[r] = quad_bcast<0>(acc[r]);
+            D[r][0] = quad_bcast<1>(acc[r]);
+            D[r][1] = quad_bcast<2>(acc[r]);
+            if (NC == 3) D[r][NC - 1] = quad_bcast<3>(acc[r]);
         }
-    }
-    double Rc[NC], D[NC][NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r) {
-        Rc[r] = quad_bcast<0>(acc[r]);
-        D[r][0] = quad_bcast<1>(acc[r]);
-        D[r][1] = quad_bcast<2>(acc[r]);
-        if (NC == 3) D[r][NC - 1] = quad_bcast<3>(acc[r]);
-    }
-    double nrm = l1norm<NC>(Rc);
-#pragma unroll
-    for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
-    if (P.dry_pin && qi[0] == 0.0) {
-#pragma unroll
-        for (int r = 1; r < NC; ++r) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
-            D[r][r] = D[0][0];
-            Rc[r] = 0.0;
-        }
-    }
-    double M[NC * NC], d[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) M[r * NC + c] = D[r][c];
-    solve_block<double, NC>(M, Rc, d);
-    double q[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) q[c] = qi[c] - d[c];
-    if (q[0] < P.h_eps) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) q[c] = 0.0;
+        blu_solve<NC>(P, Rc, D, qi);
     }
     if (k == 0 && !(gate && *gate)) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
+        for (int c = 0; c < NC; ++c) U[c * N + idx] = qi[c];
     }
 }
 
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_blu_half_quad(Phys P, const double *__restrict__ z,
                                                           double *__restrict__ U, int color,
-                                                          const int *__restrict__ gate)
+                                                          int reps, const int *__restrict__ gate)
 {
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     const long g = (long)xb * kBlock + threadIdx.x;
     const long t = g >> 2;
     if (t >= (long)W * P.ny) return;
-    blu_cell_quad<NC>(P, z, U, color, t, (int)(g & 3), gate);
+    blu_cell_quad<NC>(P, z, U, color, t, (int)(g & 3), reps, gate);
 }
 
 // Value of lane i + S of the 16-lane row (DPP row_shl:S; lanes whose source
@@ -837,12 +869,13 @@ __device__ __forceinline__ double faces_sum(double v)
 // column k-1 of the diagonal block, |e| ((T_k - T_0) / eps), with T_0 taken
 // from lane 4 f; lane 0 of the cell then sums the four faces' terms in the
 // order W, E, S, N, and does the regularization, the pin, the block solve,
-// the threshold and the store.  Every operation is blu_cell's in its order,
-// so the result is the same bit for bit; a cell's chain of dependent
-// arithmetic is one edge term and one ghost state.
+// the threshold and the store (with reps > 1 it hands the new state to the
+// cell's other lanes for the next update).  Every operation is blu_cell's in
+// its order, so the result is the same bit for bit; a cell's chain of
+// dependent arithmetic is one edge term and one ghost state per update.
 __device__ __forceinline__ void blu_cell_x16(const Phys &P, const double *__restrict__ z,
                                              double *__restrict__ U, int color, long t, int lane,
-                                             const int *__restrict__ gate)
+                                             int reps, const int *__restrict__ gate)
 {
     constexpr int NC = 3;
     const int W = (P.nx + 1) / 2;
@@ -856,80 +889,65 @@ __device__ __forceinline__ void blu_cell_x16(const Phys &P, const double *__rest
     double qi[NC];
     load_state<NC>(P, U, idx, qi);
     const double zi = z[idx];
-    double qk[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) qk[c] = qi[c];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-        if (k == c + 1) qk[c] = qk[c] + eps;
-    const Side mine = cell_side<NC>(P, qk, zi);
     const double e = P.elen[f];
-    double T[NC];
     int ni, nj;
-    if (neighbour(P, i, j, f, ni, nj)) {
-        long nidx = (long)nj * P.nx + ni;
-        double qj[NC];
-        load_state<NC>(P, U, nidx, qj);
-        Side oth = cell_side<NC>(P, qj, z[nidx]);
-        edge_term<NC>(P, f, mine, oth, T);
-    } else {
-        Side gh = ghost(P, f, mine);
-        edge_term<NC>(P, f, mine, gh, T);
-    }
-    double term[NC];    // lane k = 0: |e| T_0; lane k > 0: |e| (T_k - T_0) / eps
+    const bool inner = neighbour(P, i, j, f, ni, nj);
+    const long nidx = inner ? (long)nj * P.nx + ni : idx;
+    double qj[NC];
+    load_state<NC>(P, U, nidx, qj);
+    const double zj = z[nidx];
+    for (int rep = 0; rep < reps; ++rep) {
+        if (rep > 0) {
 #pragma unroll
-    for (int r = 0; r < NC; ++r) {
-        const double T0 = quad_bcast<0>(T[r]);
-        term[r] = (k == 0) ? e * T[r] : e * ((T[r] - T0) / eps);
-    }
-    double Rc[NC], D[NC][NC];
+            for (int c = 0; c < NC; ++c) qi[c] = __shfl(qi[c], 0, 16);
+        }
+        double qk[NC];
 #pragma unroll
-    for (int r = 0; r < NC; ++r) {
-        Rc[r] = faces_sum<0>(term[r]);
-        D[r][0] = faces_sum<1>(term[r]);
-        D[r][1] = faces_sum<2>(term[r]);
-        D[r][2] = faces_sum<3>(term[r]);
+        for (int c = 0; c < NC; ++c) qk[c] = qi[c];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (k == c + 1) qk[c] = qk[c] + eps;
+        const Side mine = cell_side<NC>(P, qk, zi);
+        double T[NC];
+        if (inner) {
+            Side oth = cell_side<NC>(P, qj, zj);
+            edge_term<NC>(P, f, mine, oth, T);
+        } else {
+            Side gh = ghost(P, f, mine);
+            edge_term<NC>(P, f, mine, gh, T);
+        }
+        double term[NC];    // lane k = 0: |e| T_0; lane k > 0: |e| (T_k - T_0) / eps
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            const double T0 = quad_bcast<0>(T[r]);
+            term[r] = (k == 0) ? e * T[r] : e * ((T[r] - T0) / eps);
+        }
+        double Rc[NC], D[NC][NC];
+#pragma unroll
+        for (int r = 0; r < NC; ++r) {
+            Rc[r] = faces_sum<0>(term[r]);
+            D[r][0] = faces_sum<1>(term[r]);
+            D[r][1] = faces_sum<2>(term[r]);
+            D[r][2] = faces_sum<3>(term[r]);
+        }
+        // valid in lane 0 only; the other lanes' results are replaced above
+        blu_solve<NC>(P, Rc, D, qi);
     }
     if (lane != 0 || (gate && *gate)) return;
-    double nrm = l1norm<NC>(Rc);
 #pragma unroll
-    for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
-    if (P.dry_pin && qi[0] == 0.0) {
-#pragma unroll
-        for (int r = 1; r < NC; ++r) {
-#pragma unroll
-            for (int c = 0; c < NC; ++c) D[r][c] = 0.0;
-            D[r][r] = D[0][0];
-            Rc[r] = 0.0;
-        }
-    }
-    double M[NC * NC], d[NC];
-#pragma unroll
-    for (int r = 0; r < NC; ++r)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) M[r * NC + c] = D[r][c];
-    solve_block<double, NC>(M, Rc, d);
-    double q[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) q[c] = qi[c] - d[c];
-    if (q[0] < P.h_eps) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) q[c] = 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
+    for (int c = 0; c < NC; ++c) U[c * N + idx] = qi[c];
 }
 
 __global__ void __launch_bounds__(kBlock) k_blu_half_x16(Phys P, const double *__restrict__ z,
                                                          double *__restrict__ U, int color,
-                                                         const int *__restrict__ gate)
+                                                         int reps, const int *__restrict__ gate)
 {
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     const long g = (long)xb * kBlock + threadIdx.x;
     const long t = g >> 4;
     if (t >= (long)W * P.ny) return;
-    blu_cell_x16(P, z, U, color, t, (int)(g & 15), gate);
+    blu_cell_x16(P, z, U, color, t, (int)(g & 15), reps, gate);
 }
 
 // Relaxed update U += tau_i dU (positivity-limited tau_i) and dry threshold.
@@ -2871,23 +2889,43 @@ hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipS
     NMG_LAUNCH(k_count_u8, nblocks(n), v, n, partial);
 }
 
-hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int lanes,
-                           hipStream_t s, const int *gate)
+hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int reps,
+                           int lanes, hipStream_t s, const int *gate)
 {
     const long cells = (long)((P.nx + 1) / 2) * P.ny;
+    if (reps < 1) return hipSuccess;
     if (lanes < 0) lanes = (cells <= kBluX16MaxCells) ? 16 : (cells <= kBluQuadMaxCells) ? 4 : 1;
     if (lanes == 16 && P.dim == 2) {
         int g = nblocks(16 * cells);
-        NMG_LAUNCH(k_blu_half_x16, g, P, z, U, color, gate);
+        NMG_LAUNCH(k_blu_half_x16, g, P, z, U, color, reps, gate);
     }
     if (lanes >= 4) {
         int g = nblocks(4 * cells);
-        if (P.dim == 1) NMG_LAUNCH(k_blu_half_quad<2>, g, P, z, U, color, gate);
-        NMG_LAUNCH(k_blu_half_quad<3>, g, P, z, U, color, gate);
+        if (P.dim == 1) NMG_LAUNCH(k_blu_half_quad<2>, g, P, z, U, color, reps, gate);
+        NMG_LAUNCH(k_blu_half_quad<3>, g, P, z, U, color, reps, gate);
     }
     int g = nblocks(cells);
-    if (P.dim == 1) NMG_LAUNCH(k_blu_half<2>, g, P, z, U, color, gate);
-    NMG_LAUNCH(k_blu_half<3>, g, P, z, U, color, gate);
+    if (P.dim == 1) NMG_LAUNCH(k_blu_half<2>, g, P, z, U, color, reps, gate);
+    NMG_LAUNCH(k_blu_half<3>, g, P, z, U, color, reps, gate);
+}
+
+hipError_t launch_blu_sweeps(const Phys &P, const double *z, double *U, int n, int lanes,
+                             hipStream_t s, const int *gate)
+{
+    const int order[4] = {0, 1, 1, 0};
+    int color = -1, reps = 0;
+    for (int h = 0; h < 4 * n; ++h) {
+        const int c = order[h & 3];
+        if (c == color) {
+            ++reps;
+            continue;
+        }
+        hipError_t e = launch_blu_half(P, z, U, color, reps, lanes, s, gate);
+        if (e != hipSuccess) return e;
+        color = c;
+        reps = 1;
+    }
+    return launch_blu_half(P, z, U, color, reps, lanes, s, gate);
 }
 
 hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool f32, double *U,
