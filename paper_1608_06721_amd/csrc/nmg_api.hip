@@ -962,10 +962,11 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
     }
     // On each level: residual, stop test (sum ||R_i||_1 < eps_p 2^-l or the
     // sweep cap), symmetric BLU-SGS sweep, repeated.  The test runs on the
-    // device and gates the launches behind it, so runs of sweeps are enqueued
-    // ahead (2, 4, ... up to kStep1Ahead) and the host reads the flag once per
-    // run; launches after the stop do nothing.  The sweeps performed are
-    // those of the loop with the test on the host.
+    // device, in the sweep's first launch before its stores, and sets a flag
+    // that gates the launches behind it, so runs of sweeps are enqueued ahead
+    // (2, 4, ... up to kStep1Ahead) and the host reads the flag once per run;
+    // launches after the stop do nothing.  The sweeps performed are those of
+    // the loop with the test on the host.
     int *ctrl = reinterpret_cast<int *>(c->scal + 1);
     int *h_ctrl = reinterpret_cast<int *>(c->h_scal + 1);
     for (int l = NL; l >= 1; --l) {
@@ -973,15 +974,20 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
         const double thr = std::ldexp(c->prm.eps_p, -l);
         const int nparts = nblocks(cells(c->L[l].G));
         HIPCHK(c, launch_step1_reset(ctrl, c->stream));
-        int cnt = 0;
+        int cnt = 0, sweep = 0;
         for (int ahead = 2;; ahead = std::min(2 * ahead, kStep1Ahead)) {
-            for (int k = 0; k < ahead; ++k) {
+            for (int k = 0; k < ahead; ++k, ++sweep) {
                 HIPCHK(c, launch_residual(P, c->zl[l], c->Ul[l], nullptr, c->partial,
                                           c->stream));
-                HIPCHK(c, launch_step1_test(c->partial, nparts, thr, c->prm.init_max_sweeps, ctrl,
-                                            c->stream));
+                StopTest test;
+                test.partial = c->partial;
+                test.n = nparts;
+                test.sweep = sweep;
+                test.max_sweeps = c->prm.init_max_sweeps;
+                test.thr = thr;
+                test.ctrl = ctrl;
                 HIPCHK(c, launch_blu_sweeps(P, c->zl[l], c->Ul[l], 1, c->blu_lanes, c->stream,
-                                            ctrl));
+                                            ctrl, test));
             }
             HIPCHK(c, hipMemcpyAsync(h_ctrl, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                      c->stream));

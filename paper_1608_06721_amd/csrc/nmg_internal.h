@@ -130,10 +130,7 @@ hipError_t launch_assemble(const Phys &P, const LevelGeom &G, const double *z, c
 hipError_t launch_residual(const Phys &P, const double *z, const double *U, double *R_out,
                            double *partial, hipStream_t s);
 
-// Step 1 stop test on the device over n partials (k_step1_test) and the
-// reset of its control words {stop flag, sweeps done}.
-hipError_t launch_step1_test(const double *partial, int n, double thr, int max_sweeps, int *ctrl,
-                             hipStream_t s);
+// Reset of the Step 1 stop test's control words {stop flag, sweeps done}.
 hipError_t launch_step1_reset(int *ctrl, hipStream_t s);
 hipError_t launch_reduce(const double *partial, int n, double *out, hipStream_t s);
 hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipStream_t s);
@@ -149,14 +146,31 @@ constexpr long kBluQuadMaxCells = 1L << 16;
 // 2D meshes of at most kBluX16MaxCells cells per colour run the half sweep
 // with sixteen lanes per cell (k_blu_half_x16: one per face and evaluation).
 constexpr long kBluX16MaxCells = 1L << 14;
+// Step 1 stop test done by a BLU-SGS launch before its stores (no launch of
+// its own): every block sums the n partials of the level's residual norm
+// (written by the residual launch before it) in sum_partials' order, as
+// k_reduce does, and the sweep stops if ctrl[0] is already set, the sum is
+// below thr (or not a number), or `sweep` sweeps are done on the level and
+// that is max_sweeps.  Block 0 records a new stop: ctrl[0] = 1,
+// ctrl[1] = sweep.  partial == nullptr: no test.
+struct StopTest {
+    const double *partial = nullptr;
+    int n = 0, sweep = 0, max_sweeps = 0;
+    double thr = 0.0;
+    int *ctrl = nullptr;
+};
 // reps consecutive half sweeps of one colour in one launch (each cell
-// updated reps times from its neighbours' unchanged states).
+// updated reps times from its neighbours' unchanged states); gate: a stop
+// flag set by an earlier launch, test: the stop test of this launch.
 hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int reps,
-                           int lanes, hipStream_t s, const int *gate = nullptr);
+                           int lanes, hipStream_t s, const int *gate = nullptr,
+                           const StopTest &test = StopTest());
 // n symmetric BLU-SGS sweeps (half sweeps of colours 0, 1, 1, 0 each), runs
-// of one colour merged into single launches: 0, 1 x2, 0 for one sweep.
+// of one colour merged into single launches: 0, 1 x2, 0 for one sweep.  The
+// stop test, if any, is done by the first launch.
 hipError_t launch_blu_sweeps(const Phys &P, const double *z, double *U, int n, int lanes,
-                             hipStream_t s, const int *gate = nullptr);
+                             hipStream_t s, const int *gate = nullptr,
+                             const StopTest &test = StopTest());
 hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool f32, double *U,
                          hipStream_t s);
 hipError_t launch_threshold(const Phys &P, double *U, hipStream_t s);

@@ -630,23 +630,6 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ pa
     if (threadIdx.x == 0) out[0] = s;
 }
 
-// Stop test of Step 1 on one level, on the device: ctrl[0] is the stop
-// flag, ctrl[1] the sweeps done.  Unless stopped, the level's residual norm
-// (the partials of the preceding residual launch, summed as k_reduce does)
-// below thr, or max_sweeps sweeps done, sets the flag; otherwise the sweep
-// that follows is counted.
-__global__ void __launch_bounds__(kBlock) k_step1_test(const double *__restrict__ partial, int n,
-                                                       double thr, int max_sweeps,
-                                                       int *__restrict__ ctrl)
-{
-    if (ctrl[0]) return;
-    double s = sum_partials(partial, n);
-    if (threadIdx.x == 0) {
-        if (!(s >= thr) || ctrl[1] >= max_sweeps) ctrl[0] = 1;
-        else ctrl[1] = ctrl[1] + 1;
-    }
-}
-
 __global__ void k_step1_reset(int *__restrict__ ctrl)
 {
     ctrl[0] = 0;
@@ -701,18 +684,18 @@ __device__ __forceinline__ void blu_solve(const Phys &P, double *Rc, double (*D)
 // consecutive half sweeps of the same colour are `reps` updates of each cell
 // from its neighbours' unchanged states: one launch does them with the
 // state kept in registers, the same arithmetic as `reps` launches.
+// blu_cell_update leaves the new state in q and the cell's index in idx;
+// false if slot t of the colour holds no cell.
 template <int NC>
-__device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict__ z,
-                                         double *__restrict__ U, int color, long t, int reps = 1,
-                                         const int *__restrict__ gate = nullptr)
+__device__ __forceinline__ bool blu_cell_update(const Phys &P, const double *__restrict__ z,
+                                                const double *__restrict__ U, int color, long t,
+                                                int reps, double *q, long &idx)
 {
     const int W = (P.nx + 1) / 2;
     int j = (int)(t / W), k = (int)(t % W);
     int i = 2 * k + ((j + color) & 1);
-    if (i >= P.nx) return;
-    const long N = (long)P.nx * P.ny;
-    const long idx = (long)j * P.nx + i;
-    double q[NC];
+    if (i >= P.nx) return false;
+    idx = (long)j * P.nx + i;
     load_state<NC>(P, U, idx, q);
     const double zi = z[idx];
     Nbrs<NC> nb;
@@ -723,24 +706,68 @@ __device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict
         cell_jacobian_at<NC, false, true, true>(P, z, U, i, j, q, zi, nb, Rc, D, NoOff());
         blu_solve<NC>(P, Rc, D, q);
     }
-    if (gate && *gate) return;
+    return true;
+}
+
+template <int NC>
+__device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict__ z,
+                                         double *__restrict__ U, int color, long t)
+{
+    const long N = (long)P.nx * P.ny;
+    double q[NC];
+    long idx;
+    if (!blu_cell_update<NC>(P, z, U, color, t, 1, q, idx)) return;
 #pragma unroll
     for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
 }
 
-// gate (nullable): a flag set by the Step 1 stop test; once it is set the
-// launch stores nothing.  It is read with the cell's data and tested only
-// before the store, so its latency overlaps the arithmetic.
+// This thread's share of the stop test's partials (the first stage of
+// sum_partials), loaded before the cell's arithmetic so their latency
+// overlaps it.
+__device__ __forceinline__ double stop_share(const StopTest &st)
+{
+    double v = 0.0;
+    if (st.partial)
+        for (int k = threadIdx.x; k < st.n; k += kBlock) v = v + st.partial[k];
+    return v;
+}
+
+// The stop decision of a launch with a stop test; every thread of the block
+// takes part (block_sum synchronizes) and gets the same answer.
+__device__ __forceinline__ bool stop_decision(const StopTest &st, double share)
+{
+    if (!st.partial) return false;
+    const bool stopped = st.ctrl[0] != 0;
+    const double s = block_sum(share);
+    const bool stop = stopped || !(s >= st.thr) || st.sweep >= st.max_sweeps;
+    if (stop && !stopped && blockIdx.x == 0 && threadIdx.x == 0) {
+        st.ctrl[0] = 1;
+        st.ctrl[1] = st.sweep;
+    }
+    return stop;
+}
+
+// gate (nullable): a flag set by the Step 1 stop test of an earlier launch;
+// once it is set the launch stores nothing.  It is read with the cell's
+// data and tested only before the store, so its latency overlaps the
+// arithmetic; so is this launch's own stop test (st).
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__restrict__ z,
                                                      double *__restrict__ U, int color, int reps,
-                                                     const int *__restrict__ gate)
+                                                     const int *__restrict__ gate, StopTest st)
 {
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
-    long t = (long)xb * kBlock + threadIdx.x;
-    if (t >= (long)W * P.ny) return;
-    blu_cell<NC>(P, z, U, color, t, reps, gate);
+    const long t = (long)xb * kBlock + threadIdx.x;
+    const long N = (long)P.nx * P.ny;
+    const double share = stop_share(st);
+    double q[NC];
+    long idx = 0;
+    const bool cell = t < (long)W * P.ny && blu_cell_update<NC>(P, z, U, color, t, reps, q, idx);
+    const bool stop = stop_decision(st, share);
+    if (!cell || stop || (gate && *gate)) return;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
 }
 
 // blu_cell with four lanes per cell, lane k of the cell's aligned quad
@@ -756,19 +783,17 @@ __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__res
 // is the same bit for bit; a cell's longest chain of dependent arithmetic is
 // one edge term (and ghost) per face instead of NC + 1.
 template <int NC>
-__device__ __forceinline__ void blu_cell_quad(const Phys &P, const double *__restrict__ z,
-                                              double *__restrict__ U, int color, long t, int k,
-                                              int reps, const int *__restrict__ gate)
+__device__ __forceinline__ bool blu_cell_quad(const Phys &P, const double *__restrict__ z,
+                                              const double *__restrict__ U, int color, long t,
+                                              int k, int reps, double *qi, long &idx)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const int W = (P.nx + 1) / 2;
     int j = (int)(t / W), kk = (int)(t % W);
     int i = 2 * kk + ((j + color) & 1);
-    if (i >= P.nx) return;
-    const long N = (long)P.nx * P.ny;
-    const long idx = (long)j * P.nx + i;
+    if (i >= P.nx) return false;
+    idx = (long)j * P.nx + i;
     const double eps = P.eps;
-    double qi[NC];
     load_state<NC>(P, U, idx, qi);
     const double zi = z[idx];
     Nbrs<NC> nb;
@@ -817,23 +842,30 @@ __device__ __forceinline__ void blu_cell_quad(const Phys &P, const double *__res
         }
         blu_solve<NC>(P, Rc, D, qi);
     }
-    if (k == 0 && !(gate && *gate)) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) U[c * N + idx] = qi[c];
-    }
+    return true;
 }
 
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_blu_half_quad(Phys P, const double *__restrict__ z,
                                                           double *__restrict__ U, int color,
-                                                          int reps, const int *__restrict__ gate)
+                                                          int reps, const int *__restrict__ gate,
+                                                          StopTest st)
 {
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     const long g = (long)xb * kBlock + threadIdx.x;
     const long t = g >> 2;
-    if (t >= (long)W * P.ny) return;
-    blu_cell_quad<NC>(P, z, U, color, t, (int)(g & 3), reps, gate);
+    const long N = (long)P.nx * P.ny;
+    const double share = stop_share(st);
+    double q[NC];
+    long idx = 0;
+    // the four lanes of a cell share t, so whole quads are active or not
+    const bool cell =
+        t < (long)W * P.ny && blu_cell_quad<NC>(P, z, U, color, t, (int)(g & 3), reps, q, idx);
+    const bool stop = stop_decision(st, share);
+    if (!cell || (g & 3) != 0 || stop || (gate && *gate)) return;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
 }
 
 // Value of lane i + S of the 16-lane row (DPP row_shl:S; lanes whose source
@@ -873,20 +905,18 @@ __device__ __forceinline__ double faces_sum(double v)
 // cell's other lanes for the next update).  Every operation is blu_cell's in
 // its order, so the result is the same bit for bit; a cell's chain of
 // dependent arithmetic is one edge term and one ghost state per update.
-__device__ __forceinline__ void blu_cell_x16(const Phys &P, const double *__restrict__ z,
-                                             double *__restrict__ U, int color, long t, int lane,
-                                             int reps, const int *__restrict__ gate)
+__device__ __forceinline__ bool blu_cell_x16(const Phys &P, const double *__restrict__ z,
+                                             const double *__restrict__ U, int color, long t,
+                                             int lane, int reps, double *qi, long &idx)
 {
     constexpr int NC = 3;
     const int W = (P.nx + 1) / 2;
     int j = (int)(t / W), kk = (int)(t % W);
     int i = 2 * kk + ((j + color) & 1);
-    if (i >= P.nx) return;
+    if (i >= P.nx) return false;
     const int f = lane >> 2, k = lane & 3;
-    const long N = (long)P.nx * P.ny;
-    const long idx = (long)j * P.nx + i;
+    idx = (long)j * P.nx + i;
     const double eps = P.eps;
-    double qi[NC];
     load_state<NC>(P, U, idx, qi);
     const double zi = z[idx];
     const double e = P.elen[f];
@@ -933,21 +963,29 @@ __device__ __forceinline__ void blu_cell_x16(const Phys &P, const double *__rest
         // valid in lane 0 only; the other lanes' results are replaced above
         blu_solve<NC>(P, Rc, D, qi);
     }
-    if (lane != 0 || (gate && *gate)) return;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) U[c * N + idx] = qi[c];
+    return true;
 }
 
 __global__ void __launch_bounds__(kBlock) k_blu_half_x16(Phys P, const double *__restrict__ z,
                                                          double *__restrict__ U, int color,
-                                                         int reps, const int *__restrict__ gate)
+                                                         int reps, const int *__restrict__ gate,
+                                                         StopTest st)
 {
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     const long g = (long)xb * kBlock + threadIdx.x;
     const long t = g >> 4;
-    if (t >= (long)W * P.ny) return;
-    blu_cell_x16(P, z, U, color, t, (int)(g & 15), reps, gate);
+    const long N = (long)P.nx * P.ny;
+    const double share = stop_share(st);
+    double q[3];
+    long idx = 0;
+    // the sixteen lanes of a cell share t, so whole rows are active or not
+    const bool cell =
+        t < (long)W * P.ny && blu_cell_x16(P, z, U, color, t, (int)(g & 15), reps, q, idx);
+    const bool stop = stop_decision(st, share);
+    if (!cell || (g & 15) != 0 || stop || (gate && *gate)) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) U[c * N + idx] = q[c];
 }
 
 // Relaxed update U += tau_i dU (positivity-limited tau_i) and dry threshold.
@@ -2867,12 +2905,6 @@ hipError_t launch_residual(const Phys &P, const double *z, const double *U, doub
     NMG_LAUNCH(k_residual<3>, g, P, z, U, R_out, partial);
 }
 
-hipError_t launch_step1_test(const double *partial, int n, double thr, int max_sweeps, int *ctrl,
-                             hipStream_t s)
-{
-    NMG_LAUNCH(k_step1_test, 1, partial, n, thr, max_sweeps, ctrl);
-}
-
 hipError_t launch_step1_reset(int *ctrl, hipStream_t s)
 {
     hipLaunchKernelGGL(k_step1_reset, dim3(1), dim3(1), 0, s, ctrl);
@@ -2890,42 +2922,46 @@ hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipS
 }
 
 hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int reps,
-                           int lanes, hipStream_t s, const int *gate)
+                           int lanes, hipStream_t s, const int *gate, const StopTest &test)
 {
     const long cells = (long)((P.nx + 1) / 2) * P.ny;
     if (reps < 1) return hipSuccess;
     if (lanes < 0) lanes = (cells <= kBluX16MaxCells) ? 16 : (cells <= kBluQuadMaxCells) ? 4 : 1;
     if (lanes == 16 && P.dim == 2) {
         int g = nblocks(16 * cells);
-        NMG_LAUNCH(k_blu_half_x16, g, P, z, U, color, reps, gate);
+        NMG_LAUNCH(k_blu_half_x16, g, P, z, U, color, reps, gate, test);
     }
     if (lanes >= 4) {
         int g = nblocks(4 * cells);
-        if (P.dim == 1) NMG_LAUNCH(k_blu_half_quad<2>, g, P, z, U, color, reps, gate);
-        NMG_LAUNCH(k_blu_half_quad<3>, g, P, z, U, color, reps, gate);
+        if (P.dim == 1) NMG_LAUNCH(k_blu_half_quad<2>, g, P, z, U, color, reps, gate, test);
+        NMG_LAUNCH(k_blu_half_quad<3>, g, P, z, U, color, reps, gate, test);
     }
     int g = nblocks(cells);
-    if (P.dim == 1) NMG_LAUNCH(k_blu_half<2>, g, P, z, U, color, reps, gate);
-    NMG_LAUNCH(k_blu_half<3>, g, P, z, U, color, reps, gate);
+    if (P.dim == 1) NMG_LAUNCH(k_blu_half<2>, g, P, z, U, color, reps, gate, test);
+    NMG_LAUNCH(k_blu_half<3>, g, P, z, U, color, reps, gate, test);
 }
 
 hipError_t launch_blu_sweeps(const Phys &P, const double *z, double *U, int n, int lanes,
-                             hipStream_t s, const int *gate)
+                             hipStream_t s, const int *gate, const StopTest &test)
 {
     const int order[4] = {0, 1, 1, 0};
-    int color = -1, reps = 0;
-    for (int h = 0; h < 4 * n; ++h) {
-        const int c = order[h & 3];
+    int color = -1, reps = 0, launched = 0;
+    for (int h = 0; h <= 4 * n; ++h) {
+        const int c = (h < 4 * n) ? order[h & 3] : -1;
         if (c == color) {
             ++reps;
             continue;
         }
-        hipError_t e = launch_blu_half(P, z, U, color, reps, lanes, s, gate);
-        if (e != hipSuccess) return e;
+        if (reps > 0) {
+            hipError_t e = launch_blu_half(P, z, U, color, reps, lanes, s, gate,
+                                           launched == 0 ? test : StopTest());
+            if (e != hipSuccess) return e;
+            ++launched;
+        }
         color = c;
         reps = 1;
     }
-    return launch_blu_half(P, z, U, color, reps, lanes, s, gate);
+    return hipSuccess;
 }
 
 hipError_t launch_update(const Phys &P, const LevelGeom &G, const void *x, bool f32, double *U,
