@@ -152,6 +152,31 @@ def test_phase_timing_and_step1_levels(nmg):
     assert lv == so
 
 
+@pytest.mark.parametrize("lanes", ["default", "1", "4", "16"])
+@pytest.mark.parametrize("cap", [0, 1, 2, 3, 6, 7, 17])
+def test_step1_sweep_cap_and_merged_sweeps(nmg, monkeypatch, lanes, cap):
+    """Step 1 with its sweep cap binding on every level (eps_p far below the
+    coarse residuals), caps crossing the runs of sweeps the host enqueues
+    ahead of its flag read (2, 4, 8, 16): the per-level counts equal the cap
+    and the state handed to Newton matches the oracle bit for bit, with one,
+    four or sixteen lanes per cell.  Then two Newton steps with two BLU-SGS
+    sweeps each, whose same-colour half sweeps run merged in one launch
+    (colours 0, 1 x2, 0 x2, 1 x2, 0)."""
+    if lanes == "default":
+        monkeypatch.delenv("NMG_BLU_LANES", raising=False)
+    else:
+        monkeypatch.setenv("NMG_BLU_LANES", lanes)
+    base = W.channel(64, 32, n_levels=3, mound_amp=0.3, gamma=2)
+    prob = base.with_params(eps_p=1e-300, init_max_sweeps=cap, max_newton=0)
+    say("step1 cap", cap, "lanes", lanes)
+    st = solve_both(nmg, prob, 0.0)
+    assert st["init_level_sweeps"][:4] == [0, cap, cap, cap]
+    assert oracle.nested_init(prob)[1] == [0, cap, cap, cap]
+    prob2 = base.with_params(eps_p=1e-300, init_max_sweeps=cap, max_newton=2, blu_sweeps=2)
+    st2 = solve_both(nmg, prob2, 0.0)
+    assert st2["newton_steps"] == 2
+
+
 def test_full_size_step1(nmg):
     """Step 1 of the benchmark solve at full size (1024 x 1024 channel with
     two emergent mounds, eps_p = 0.2, five coarse levels, the sweep cap
