@@ -69,6 +69,8 @@ struct nmg_ctx {
     // Algorithm 1, Step 1 (allocated on first use): coarse beds and states
     double *init_pool = nullptr;
     double *zl[kMaxLevels] = {}, *Ul[kMaxLevels] = {};
+    double *init_red = nullptr;     // Step 1: first half sweep's red states
+    double *init_part = nullptr;    // Step 1: residual partials of that launch
     // Krylov acceleration of the adjoint solve (allocated on first use)
     int km = 0;                       // restart length the buffers were sized for
     double *kV = nullptr, *kg = nullptr, *kx = nullptr, *kw = nullptr;
@@ -928,7 +930,11 @@ Phys level_phys(const nmg_ctx *c, int l)
 int alloc_step1(nmg_ctx *c)
 {
     const int NL = c->NL, nc = c->nc;
-    size_t tot = 0;
+    // level 1 is the largest coarse level; a half sweep launches at most 16
+    // lanes per cell of one colour
+    const size_t c1 = cells(c->L[1].G);
+    const size_t nparts = (size_t)nblocks(16 * (long)c1);
+    size_t tot = nc * c1 + nparts;
     for (int l = 1; l <= NL; ++l) tot += (size_t)(1 + nc) * cells(c->L[l].G);
     if (hipMalloc(&c->init_pool, sizeof(double) * tot) != hipSuccess)
         return fail(c, NMG_ENOMEM, "Step 1 levels");
@@ -937,6 +943,8 @@ int alloc_step1(nmg_ctx *c)
         c->zl[l] = c->init_pool + off; off += cells(c->L[l].G);
         c->Ul[l] = c->init_pool + off; off += (size_t)nc * cells(c->L[l].G);
     }
+    c->init_red = c->init_pool + off; off += nc * c1;
+    c->init_part = c->init_pool + off;
     return NMG_OK;
 }
 
@@ -961,33 +969,42 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
         Up = c->Ul[l];
     }
     // On each level: residual, stop test (sum ||R_i||_1 < eps_p 2^-l or the
-    // sweep cap), symmetric BLU-SGS sweep, repeated.  The test runs on the
-    // device, in the sweep's first launch before its stores, and sets a flag
+    // sweep cap), symmetric BLU-SGS sweep, repeated, in three launches per
+    // sweep.  The first computes the residual norms of both colours at the
+    // level's state (block partials) and the red half sweep from it, stored
+    // to init_red so that the state stays as it was; the second does the
+    // stop test on those partials before its stores and the two black half
+    // sweeps, reading the red states from init_red; the third the last red
+    // half sweep from init_red into the level's state.  The test sets a flag
     // that gates the launches behind it, so runs of sweeps are enqueued ahead
     // (2, 4, ... up to kStep1Ahead) and the host reads the flag once per run;
-    // launches after the stop do nothing.  The sweeps performed are those of
+    // after the stop nothing is stored.  The sweeps performed are those of
     // the loop with the test on the host.
     int *ctrl = reinterpret_cast<int *>(c->scal + 1);
     int *h_ctrl = reinterpret_cast<int *>(c->h_scal + 1);
     for (int l = NL; l >= 1; --l) {
         const Phys P = level_phys(c, l);
         const double thr = std::ldexp(c->prm.eps_p, -l);
-        const int nparts = nblocks(cells(c->L[l].G));
+        const int lanes = c->blu_lanes;
+        const double *zl = c->zl[l];
+        double *Ul = c->Ul[l], *red = c->init_red;
         HIPCHK(c, launch_step1_reset(ctrl, c->stream));
         int cnt = 0, sweep = 0;
         for (int ahead = 2;; ahead = std::min(2 * ahead, kStep1Ahead)) {
             for (int k = 0; k < ahead; ++k, ++sweep) {
-                HIPCHK(c, launch_residual(P, c->zl[l], c->Ul[l], nullptr, c->partial,
-                                          c->stream));
                 StopTest test;
-                test.partial = c->partial;
-                test.n = nparts;
+                test.partial = c->init_part;
+                test.n = blu_half_blocks(P, lanes);
                 test.sweep = sweep;
                 test.max_sweeps = c->prm.init_max_sweeps;
                 test.thr = thr;
                 test.ctrl = ctrl;
-                HIPCHK(c, launch_blu_sweeps(P, c->zl[l], c->Ul[l], 1, c->blu_lanes, c->stream,
-                                            ctrl, test));
+                HIPCHK(c, launch_blu_half_io(P, zl, Ul, Ul, red, 0, 1, lanes, c->stream, ctrl,
+                                             StopTest(), c->init_part));
+                HIPCHK(c, launch_blu_half_io(P, zl, Ul, red, Ul, 1, 2, lanes, c->stream, ctrl,
+                                             test, nullptr));
+                HIPCHK(c, launch_blu_half_io(P, zl, red, Ul, Ul, 0, 1, lanes, c->stream, ctrl,
+                                             StopTest(), nullptr));
             }
             HIPCHK(c, hipMemcpyAsync(h_ctrl, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                      c->stream));

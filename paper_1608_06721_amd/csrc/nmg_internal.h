@@ -165,6 +165,15 @@ struct StopTest {
 hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int reps,
                            int lanes, hipStream_t s, const int *gate = nullptr,
                            const StopTest &test = StopTest());
+// The general form: own states read from Uown, the other colour's from
+// Unb, new states stored to Uout; with res_partial (Uown == Unb) the launch
+// also writes per block the sum of ||R_i||_1 at its input state over its
+// slots' cells of both colours, blu_half_blocks(P, lanes) partials.
+hipError_t launch_blu_half_io(const Phys &P, const double *z, const double *Uown,
+                              const double *Unb, double *Uout, int color, int reps, int lanes,
+                              hipStream_t s, const int *gate, const StopTest &test,
+                              double *res_partial);
+int blu_half_blocks(const Phys &P, int lanes);
 // n symmetric BLU-SGS sweeps (half sweeps of colours 0, 1, 1, 0 each), runs
 // of one colour merged into single launches: 0, 1 x2, 0 for one sweep.  The
 // stop test, if any, is done by the first launch.

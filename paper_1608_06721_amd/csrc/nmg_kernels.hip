@@ -650,9 +650,9 @@ __global__ void __launch_bounds__(kBlock) k_count_u8(const unsigned char *__rest
 // keeps only its depth row, and d solves D d = R_i; then the new state
 // q - d, with the dry threshold (every component 0 below h_eps).
 template <int NC>
-__device__ __forceinline__ void blu_solve(const Phys &P, double *Rc, double (*D)[NC], double *q)
+__device__ __forceinline__ double blu_solve(const Phys &P, double *Rc, double (*D)[NC], double *q)
 {
-    double nrm = l1norm<NC>(Rc);
+    const double nrm = l1norm<NC>(Rc);
 #pragma unroll
     for (int r = 0; r < NC; ++r) D[r][r] = D[r][r] + P.alpha * nrm;
     if (P.dry_pin && q[0] == 0.0) {
@@ -676,6 +676,52 @@ __device__ __forceinline__ void blu_solve(const Phys &P, double *Rc, double (*D)
 #pragma unroll
         for (int c = 0; c < NC; ++c) q[c] = 0.0;
     }
+    return nrm;
+}
+
+// Edge term |e_f| T_f of face f of the cell in slot t of `color`, at state
+// U, as residual_cell forms it; false if the slot holds no cell.
+template <int NC>
+__device__ __forceinline__ bool slot_face_term(const Phys &P, const double *__restrict__ z,
+                                               const double *__restrict__ U, int color, long t,
+                                               int f, double *eT)
+{
+    const int W = (P.nx + 1) / 2;
+    int j = (int)(t / W), k = (int)(t % W);
+    int i = 2 * k + ((j + color) & 1);
+    if (i >= P.nx) return false;
+    const long idx = (long)j * P.nx + i;
+    double qi[NC];
+    load_state<NC>(P, U, idx, qi);
+    const Side own = cell_side<NC>(P, qi, z[idx]);
+    int ni, nj;
+    Side oth;
+    if (neighbour(P, i, j, f, ni, nj)) {
+        const long nidx = (long)nj * P.nx + ni;
+        double qj[NC];
+        load_state<NC>(P, U, nidx, qj);
+        oth = cell_side<NC>(P, qj, z[nidx]);
+    } else {
+        oth = ghost(P, f, own);
+    }
+    double T[NC];
+    edge_term<NC>(P, f, own, oth, T);
+#pragma unroll
+    for (int r = 0; r < NC; ++r) eT[r] = P.elen[f] * T[r];
+    return true;
+}
+
+// ||R_i||_1 of the cell in slot t of `color` at state U (0 if none).
+template <int NC>
+__device__ __forceinline__ double slot_residual_norm(const Phys &P, const double *__restrict__ z,
+                                                     const double *__restrict__ U, int color,
+                                                     long t)
+{
+    const int W = (P.nx + 1) / 2;
+    int j = (int)(t / W), k = (int)(t % W);
+    int i = 2 * k + ((j + color) & 1);
+    if (i >= P.nx) return 0.0;
+    return residual_cell<NC>(P, z, U, nullptr, (long)j * P.nx + i);
 }
 
 // One BLU-SGS cell update for every cell of one colour (Algorithm 1,
@@ -684,27 +730,31 @@ __device__ __forceinline__ void blu_solve(const Phys &P, double *Rc, double (*D)
 // consecutive half sweeps of the same colour are `reps` updates of each cell
 // from its neighbours' unchanged states: one launch does them with the
 // state kept in registers, the same arithmetic as `reps` launches.
-// blu_cell_update leaves the new state in q and the cell's index in idx;
-// false if slot t of the colour holds no cell.
+// blu_cell_update reads the cell's own state from Uown and its neighbours'
+// from Unb (the other colour), leaves the new state in q, the cell's index
+// in idx and ||R_i||_1 at the starting state in nrm0; false if slot t of the
+// colour holds no cell.
 template <int NC>
 __device__ __forceinline__ bool blu_cell_update(const Phys &P, const double *__restrict__ z,
-                                                const double *__restrict__ U, int color, long t,
-                                                int reps, double *q, long &idx)
+                                                const double *Uown, const double *Unb,
+                                                int color, long t, int reps, double *q, long &idx,
+                                                double &nrm0)
 {
     const int W = (P.nx + 1) / 2;
     int j = (int)(t / W), k = (int)(t % W);
     int i = 2 * k + ((j + color) & 1);
     if (i >= P.nx) return false;
     idx = (long)j * P.nx + i;
-    load_state<NC>(P, U, idx, q);
+    load_state<NC>(P, Uown, idx, q);
     const double zi = z[idx];
     Nbrs<NC> nb;
-    load_nbrs<NC>(P, z, U, i, j, nb);
+    load_nbrs<NC>(P, z, Unb, i, j, nb);
     for (int rep = 0; rep < reps; ++rep) {
         opaque_nbrs<NC>(nb);
         double Rc[NC], D[NC][NC];
-        cell_jacobian_at<NC, false, true, true>(P, z, U, i, j, q, zi, nb, Rc, D, NoOff());
-        blu_solve<NC>(P, Rc, D, q);
+        cell_jacobian_at<NC, false, true, true>(P, z, Unb, i, j, q, zi, nb, Rc, D, NoOff());
+        const double nrm = blu_solve<NC>(P, Rc, D, q);
+        if (rep == 0) nrm0 = nrm;
     }
     return true;
 }
@@ -714,9 +764,9 @@ __device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict
                                          double *__restrict__ U, int color, long t)
 {
     const long N = (long)P.nx * P.ny;
-    double q[NC];
+    double q[NC], nrm0;
     long idx;
-    if (!blu_cell_update<NC>(P, z, U, color, t, 1, q, idx)) return;
+    if (!blu_cell_update<NC>(P, z, U, U, color, t, 1, q, idx, nrm0)) return;
 #pragma unroll
     for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
 }
@@ -747,27 +797,51 @@ __device__ __forceinline__ bool stop_decision(const StopTest &st, double share)
     return stop;
 }
 
-// gate (nullable): a flag set by the Step 1 stop test of an earlier launch;
-// once it is set the launch stores nothing.  It is read with the cell's
-// data and tested only before the store, so its latency overlaps the
-// arithmetic; so is this launch's own stop test (st).
+// Block partial of a launch's residual output (res_partial[xb]): the sum of
+// its threads' norms.  Followed by a barrier, so that a later block_sum in
+// the same launch cannot overwrite the shared array before every thread
+// has read this one's result.
+__device__ __forceinline__ void residual_partial(double *res_partial, int xb, double nrm)
+{
+    const double s = block_sum(nrm);
+    if (threadIdx.x == 0) res_partial[xb] = s;
+    __syncthreads();
+}
+
+// A BLU-SGS half sweep: the cells of `color` read their own state from Uown
+// and their neighbours' from Unb, and store the new state to Uout (all
+// three the same array for an in-place half sweep).  gate (nullable): a
+// flag set by the Step 1 stop test of an earlier launch; once it is set the
+// launch stores nothing.  It is read with the cell's data and tested only
+// before the store, so its latency overlaps the arithmetic; so is this
+// launch's own stop test (st).  res_partial (nullable, Uown == Unb): the
+// launch also writes, per block, the sum of ||R_i||_1 at the input state of
+// its slots' cells of both colours (the next launch's stop test reads them).
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__restrict__ z,
-                                                     double *__restrict__ U, int color, int reps,
-                                                     const int *__restrict__ gate, StopTest st)
+                                                     const double *Uown, const double *Unb,
+                                                     double *Uout, int color, int reps,
+                                                     const int *__restrict__ gate, StopTest st,
+                                                     double *__restrict__ res_partial)
 {
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     const long t = (long)xb * kBlock + threadIdx.x;
     const long N = (long)P.nx * P.ny;
+    const bool slot = t < (long)W * P.ny;
     const double share = stop_share(st);
-    double q[NC];
+    double q[NC], nrm = 0.0;
     long idx = 0;
-    const bool cell = t < (long)W * P.ny && blu_cell_update<NC>(P, z, U, color, t, reps, q, idx);
+    const bool cell = slot && blu_cell_update<NC>(P, z, Uown, Unb, color, t, reps, q, idx, nrm);
+    if (res_partial) {
+        if (!cell) nrm = 0.0;
+        if (slot) nrm = nrm + slot_residual_norm<NC>(P, z, Uown, color ^ 1, t);
+        residual_partial(res_partial, xb, nrm);
+    }
     const bool stop = stop_decision(st, share);
     if (!cell || stop || (gate && *gate)) return;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
+    for (int c = 0; c < NC; ++c) Uout[c * N + idx] = q[c];
 }
 
 // blu_cell with four lanes per cell, lane k of the cell's aligned quad
@@ -784,8 +858,9 @@ __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__res
 // one edge term (and ghost) per face instead of NC + 1.
 template <int NC>
 __device__ __forceinline__ bool blu_cell_quad(const Phys &P, const double *__restrict__ z,
-                                              const double *__restrict__ U, int color, long t,
-                                              int k, int reps, double *qi, long &idx)
+                                              const double *Uown, const double *Unb, int color,
+                                              long t, int k, int reps, double *qi, long &idx,
+                                              double &nrm0)
 {
     const int NF = (NC == 2) ? 2 : 4;
     const int W = (P.nx + 1) / 2;
@@ -794,10 +869,10 @@ __device__ __forceinline__ bool blu_cell_quad(const Phys &P, const double *__res
     if (i >= P.nx) return false;
     idx = (long)j * P.nx + i;
     const double eps = P.eps;
-    load_state<NC>(P, U, idx, qi);
+    load_state<NC>(P, Uown, idx, qi);
     const double zi = z[idx];
     Nbrs<NC> nb;
-    load_nbrs<NC>(P, z, U, i, j, nb);
+    load_nbrs<NC>(P, z, Unb, i, j, nb);
     for (int rep = 0; rep < reps; ++rep) {
         opaque_nbrs<NC>(nb);
         // this lane's own side: unperturbed (k = 0) or component k-1 + eps
@@ -840,32 +915,78 @@ __device__ __forceinline__ bool blu_cell_quad(const Phys &P, const double *__res
             D[r][1] = quad_bcast<2>(acc[r]);
             if (NC == 3) D[r][NC - 1] = quad_bcast<3>(acc[r]);
         }
-        blu_solve<NC>(P, Rc, D, qi);
+        const double nrm = blu_solve<NC>(P, Rc, D, qi);
+        if (rep == 0) nrm0 = nrm;
     }
     return true;
 }
 
+// ||R_i||_1 of the cell in slot t of `color` at U with four lanes per cell:
+// lane k forms face k's term, lane 0 gets the sum over the faces in the
+// order W, E, S, N (residual_cell's), the other lanes 0.  Every lane of the
+// quad must take part.
+template <int NC>
+__device__ __forceinline__ double slot_residual_norm_quad(const Phys &P,
+                                                          const double *__restrict__ z,
+                                                          const double *__restrict__ U,
+                                                          int color, long t, int k)
+{
+    const int NF = (NC == 2) ? 2 : 4;
+    double eT[NC];
+    // (in 1D lanes 2 and 3 repeat face 0 and contribute nothing)
+    const bool cell = slot_face_term<NC>(P, z, U, color, t, k < NF ? k : 0, eT);
+    if (!cell || k >= NF) {
+#pragma unroll
+        for (int r = 0; r < NC; ++r) eT[r] = 0.0;
+    }
+    double R[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) {
+        double v = 0.0;
+        v = v + quad_bcast<0>(eT[r]);
+        v = v + quad_bcast<1>(eT[r]);
+        if (NC == 3) {
+            v = v + quad_bcast<2>(eT[r]);
+            v = v + quad_bcast<3>(eT[r]);
+        }
+        R[r] = v;
+    }
+    return (cell && k == 0) ? l1norm<NC>(R) : 0.0;
+}
+
+// k_blu_half with four lanes per cell (the arguments are k_blu_half's).
 template <int NC>
 __global__ void __launch_bounds__(kBlock) k_blu_half_quad(Phys P, const double *__restrict__ z,
-                                                          double *__restrict__ U, int color,
-                                                          int reps, const int *__restrict__ gate,
-                                                          StopTest st)
+                                                          const double *Uown, const double *Unb,
+                                                          double *Uout, int color, int reps,
+                                                          const int *__restrict__ gate,
+                                                          StopTest st,
+                                                          double *__restrict__ res_partial)
 {
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     const long g = (long)xb * kBlock + threadIdx.x;
     const long t = g >> 2;
+    const int k = (int)(g & 3);
     const long N = (long)P.nx * P.ny;
-    const double share = stop_share(st);
-    double q[NC];
-    long idx = 0;
     // the four lanes of a cell share t, so whole quads are active or not
+    const bool slot = t < (long)W * P.ny;
+    const double share = stop_share(st);
+    // the other colour's residual norm first (lane 0; 0 without output)
+    const double nrm1 = (res_partial && slot)
+                            ? slot_residual_norm_quad<NC>(P, z, Uown, color ^ 1, t, k) : 0.0;
+    double q[NC], nrm = 0.0;
+    long idx = 0;
     const bool cell =
-        t < (long)W * P.ny && blu_cell_quad<NC>(P, z, U, color, t, (int)(g & 3), reps, q, idx);
+        slot && blu_cell_quad<NC>(P, z, Uown, Unb, color, t, k, reps, q, idx, nrm);
+    if (res_partial) {
+        if (!cell || k != 0) nrm = 0.0;
+        residual_partial(res_partial, xb, nrm + nrm1);
+    }
     const bool stop = stop_decision(st, share);
-    if (!cell || (g & 3) != 0 || stop || (gate && *gate)) return;
+    if (!cell || k != 0 || stop || (gate && *gate)) return;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
+    for (int c = 0; c < NC; ++c) Uout[c * N + idx] = q[c];
 }
 
 // Value of lane i + S of the 16-lane row (DPP row_shl:S; lanes whose source
@@ -906,8 +1027,9 @@ __device__ __forceinline__ double faces_sum(double v)
 // its order, so the result is the same bit for bit; a cell's chain of
 // dependent arithmetic is one edge term and one ghost state per update.
 __device__ __forceinline__ bool blu_cell_x16(const Phys &P, const double *__restrict__ z,
-                                             const double *__restrict__ U, int color, long t,
-                                             int lane, int reps, double *qi, long &idx)
+                                             const double *Uown, const double *Unb, int color,
+                                             long t, int lane, int reps, double *qi, long &idx,
+                                             double &nrm0)
 {
     constexpr int NC = 3;
     const int W = (P.nx + 1) / 2;
@@ -917,14 +1039,14 @@ __device__ __forceinline__ bool blu_cell_x16(const Phys &P, const double *__rest
     const int f = lane >> 2, k = lane & 3;
     idx = (long)j * P.nx + i;
     const double eps = P.eps;
-    load_state<NC>(P, U, idx, qi);
+    load_state<NC>(P, Uown, idx, qi);
     const double zi = z[idx];
     const double e = P.elen[f];
     int ni, nj;
     const bool inner = neighbour(P, i, j, f, ni, nj);
     const long nidx = inner ? (long)nj * P.nx + ni : idx;
     double qj[NC];
-    load_state<NC>(P, U, nidx, qj);
+    load_state<NC>(P, inner ? Unb : Uown, nidx, qj);
     const double zj = z[nidx];
     for (int rep = 0; rep < reps; ++rep) {
         if (rep > 0) {
@@ -961,31 +1083,60 @@ __device__ __forceinline__ bool blu_cell_x16(const Phys &P, const double *__rest
             D[r][2] = faces_sum<3>(term[r]);
         }
         // valid in lane 0 only; the other lanes' results are replaced above
-        blu_solve<NC>(P, Rc, D, qi);
+        const double nrm = blu_solve<NC>(P, Rc, D, qi);
+        if (rep == 0) nrm0 = nrm;
     }
     return true;
 }
 
+// ||R_i||_1 of the cell in slot t of `color` at U with sixteen lanes per
+// cell: lane 4 f forms face f's term, lane 0 gets the sum over the faces in
+// the order W, E, S, N (residual_cell's), the other lanes 0.  Every lane of
+// the row must take part.
+__device__ __forceinline__ double slot_residual_norm_x16(const Phys &P,
+                                                         const double *__restrict__ z,
+                                                         const double *__restrict__ U, int color,
+                                                         long t, int lane)
+{
+    constexpr int NC = 3;
+    double eT[NC] = {0.0, 0.0, 0.0};
+    bool cell = true;
+    if ((lane & 3) == 0) cell = slot_face_term<NC>(P, z, U, color, t, lane >> 2, eT);
+    double R[NC];
+#pragma unroll
+    for (int r = 0; r < NC; ++r) R[r] = faces_sum<0>(eT[r]);
+    return (cell && lane == 0) ? l1norm<NC>(R) : 0.0;
+}
+
+// k_blu_half with sixteen lanes per cell (2D; the arguments are k_blu_half's).
 __global__ void __launch_bounds__(kBlock) k_blu_half_x16(Phys P, const double *__restrict__ z,
-                                                         double *__restrict__ U, int color,
-                                                         int reps, const int *__restrict__ gate,
-                                                         StopTest st)
+                                                         const double *Uown, const double *Unb,
+                                                         double *Uout, int color, int reps,
+                                                         const int *__restrict__ gate,
+                                                         StopTest st,
+                                                         double *__restrict__ res_partial)
 {
     const int W = (P.nx + 1) / 2;
     const int xb = xcd_block(blockIdx.x, gridDim.x);
     const long g = (long)xb * kBlock + threadIdx.x;
     const long t = g >> 4;
+    const int lane = (int)(g & 15);
     const long N = (long)P.nx * P.ny;
-    const double share = stop_share(st);
-    double q[3];
-    long idx = 0;
     // the sixteen lanes of a cell share t, so whole rows are active or not
-    const bool cell =
-        t < (long)W * P.ny && blu_cell_x16(P, z, U, color, t, (int)(g & 15), reps, q, idx);
+    const bool slot = t < (long)W * P.ny;
+    const double share = stop_share(st);
+    double q[3], nrm = 0.0;
+    long idx = 0;
+    const bool cell = slot && blu_cell_x16(P, z, Uown, Unb, color, t, lane, reps, q, idx, nrm);
+    if (res_partial) {
+        if (!cell || lane != 0) nrm = 0.0;
+        if (slot) nrm = nrm + slot_residual_norm_x16(P, z, Uown, color ^ 1, t, lane);
+        residual_partial(res_partial, xb, nrm);
+    }
     const bool stop = stop_decision(st, share);
-    if (!cell || (g & 15) != 0 || stop || (gate && *gate)) return;
+    if (!cell || lane != 0 || stop || (gate && *gate)) return;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) U[c * N + idx] = q[c];
+    for (int c = 0; c < 3; ++c) Uout[c * N + idx] = q[c];
 }
 
 // Relaxed update U += tau_i dU (positivity-limited tau_i) and dry threshold.
@@ -2921,24 +3072,48 @@ hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipS
     NMG_LAUNCH(k_count_u8, nblocks(n), v, n, partial);
 }
 
+// Lanes per cell of a BLU-SGS half sweep: the requested count (1, 4 or 16;
+// 16 is 4 in 1D), or by the mesh when negative.
+static int blu_lanes(const Phys &P, int lanes)
+{
+    const long cells = (long)((P.nx + 1) / 2) * P.ny;
+    if (lanes < 0) lanes = (cells <= kBluX16MaxCells) ? 16 : (cells <= kBluQuadMaxCells) ? 4 : 1;
+    if (lanes >= 16) return P.dim == 2 ? 16 : 4;
+    return lanes >= 4 ? 4 : 1;
+}
+
+int blu_half_blocks(const Phys &P, int lanes)
+{
+    const long cells = (long)((P.nx + 1) / 2) * P.ny;
+    return nblocks(blu_lanes(P, lanes) * cells);
+}
+
+hipError_t launch_blu_half_io(const Phys &P, const double *z, const double *Uown,
+                              const double *Unb, double *Uout, int color, int reps, int lanes,
+                              hipStream_t s, const int *gate, const StopTest &test,
+                              double *res_partial)
+{
+    if (reps < 1) return hipSuccess;
+    lanes = blu_lanes(P, lanes);
+    const int g = blu_half_blocks(P, lanes);
+    if (lanes == 16)
+        NMG_LAUNCH(k_blu_half_x16, g, P, z, Uown, Unb, Uout, color, reps, gate, test, res_partial);
+    if (lanes == 4) {
+        if (P.dim == 1)
+            NMG_LAUNCH(k_blu_half_quad<2>, g, P, z, Uown, Unb, Uout, color, reps, gate, test,
+                       res_partial);
+        NMG_LAUNCH(k_blu_half_quad<3>, g, P, z, Uown, Unb, Uout, color, reps, gate, test,
+                   res_partial);
+    }
+    if (P.dim == 1)
+        NMG_LAUNCH(k_blu_half<2>, g, P, z, Uown, Unb, Uout, color, reps, gate, test, res_partial);
+    NMG_LAUNCH(k_blu_half<3>, g, P, z, Uown, Unb, Uout, color, reps, gate, test, res_partial);
+}
+
 hipError_t launch_blu_half(const Phys &P, const double *z, double *U, int color, int reps,
                            int lanes, hipStream_t s, const int *gate, const StopTest &test)
 {
-    const long cells = (long)((P.nx + 1) / 2) * P.ny;
-    if (reps < 1) return hipSuccess;
-    if (lanes < 0) lanes = (cells <= kBluX16MaxCells) ? 16 : (cells <= kBluQuadMaxCells) ? 4 : 1;
-    if (lanes == 16 && P.dim == 2) {
-        int g = nblocks(16 * cells);
-        NMG_LAUNCH(k_blu_half_x16, g, P, z, U, color, reps, gate, test);
-    }
-    if (lanes >= 4) {
-        int g = nblocks(4 * cells);
-        if (P.dim == 1) NMG_LAUNCH(k_blu_half_quad<2>, g, P, z, U, color, reps, gate, test);
-        NMG_LAUNCH(k_blu_half_quad<3>, g, P, z, U, color, reps, gate, test);
-    }
-    int g = nblocks(cells);
-    if (P.dim == 1) NMG_LAUNCH(k_blu_half<2>, g, P, z, U, color, reps, gate, test);
-    NMG_LAUNCH(k_blu_half<3>, g, P, z, U, color, reps, gate, test);
+    return launch_blu_half_io(P, z, U, U, U, color, reps, lanes, s, gate, test, nullptr);
 }
 
 hipError_t launch_blu_sweeps(const Phys &P, const double *z, double *U, int n, int lanes,
