@@ -55,6 +55,7 @@ struct nmg_ctx {
     int fuse = 3;                     // most half sweeps per launch on launched coarse levels
     int split = 1;                    // coarsest-level runs may use two lanes per cell
     int blu_lanes = -1;               // lanes per cell of BLU-SGS half sweeps (-1: by mesh)
+    int step1_graph = 1;              // Step 1 runs of kStep1Ahead sweeps replayed as graphs
     Level L[16];
     void *pool = nullptr;             // the hierarchy's allocation
     // Residuals of colour res_color of level res_level (res_level -1: none
@@ -71,6 +72,8 @@ struct nmg_ctx {
     double *zl[kMaxLevels] = {}, *Ul[kMaxLevels] = {};
     double *init_red = nullptr;     // Step 1: first half sweep's red states
     double *init_part = nullptr;    // Step 1: residual partials of that launch
+    hipStream_t cap_stream = nullptr;                 // Step 1 graph capture
+    hipGraphExec_t init_graph[kMaxLevels] = {};       // Step 1 run of sweeps, per level
     // Krylov acceleration of the adjoint solve (allocated on first use)
     int km = 0;                       // restart length the buffers were sized for
     double *kV = nullptr, *kg = nullptr, *kx = nullptr, *kw = nullptr;
@@ -951,6 +954,59 @@ int alloc_step1(nmg_ctx *c)
 // Most sweeps of Step 1 enqueued between two looks at the stop flag.
 constexpr int kStep1Ahead = 16;
 
+// The three launches of `n` Step 1 sweeps on level l (see nested_init); the
+// first sweep's index on the level is even.
+int step1_sweeps(nmg_ctx *c, int l, int n, hipStream_t s)
+{
+    const Phys P = level_phys(c, l);
+    const int lanes = c->blu_lanes;
+    const double *zl = c->zl[l];
+    double *Ul = c->Ul[l], *red = c->init_red;
+    int *ctrl = reinterpret_cast<int *>(c->scal + 1);
+    for (int k = 0; k < n; ++k) {
+        StopTest test;
+        test.partial = c->init_part;
+        test.n = blu_half_blocks(P, lanes);
+        test.parity = k & 1;
+        test.max_sweeps = c->prm.init_max_sweeps;
+        test.thr = std::ldexp(c->prm.eps_p, -l);
+        test.ctrl = ctrl;
+        HIPCHK(c, launch_blu_half_io(P, zl, Ul, Ul, red, 0, 1, lanes, s, ctrl, StopTest(),
+                                     c->init_part));
+        HIPCHK(c, launch_blu_half_io(P, zl, Ul, red, Ul, 1, 2, lanes, s, ctrl, test, nullptr));
+        HIPCHK(c, launch_blu_half_io(P, zl, red, Ul, Ul, 0, 1, lanes, s, ctrl, StopTest(),
+                                     nullptr));
+    }
+    return NMG_OK;
+}
+
+// A run of kStep1Ahead sweeps on level l as a graph, captured on a stream of
+// its own the first time it is needed (its launches' arguments are the same
+// for every run of the level and every solve of the context).
+int step1_graph(nmg_ctx *c, int l, hipGraphExec_t *out)
+{
+    if (c->init_graph[l]) {
+        *out = c->init_graph[l];
+        return NMG_OK;
+    }
+    if (!c->cap_stream)
+        HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = step1_sweeps(c, l, kStep1Ahead, c->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    HIPCHK(c, e);
+    e = hipGraphInstantiate(&c->init_graph[l], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(c, e);
+    *out = c->init_graph[l];
+    return NMG_OK;
+}
+
 int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_sweeps)
 {
     const int NL = c->NL, nc = c->nc;
@@ -979,32 +1035,23 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
     // that gates the launches behind it, so runs of sweeps are enqueued ahead
     // (2, 4, ... up to kStep1Ahead) and the host reads the flag once per run;
     // after the stop nothing is stored.  The sweeps performed are those of
-    // the loop with the test on the host.
+    // the loop with the test on the host.  Runs of kStep1Ahead sweeps are
+    // replayed from a graph per level (the sweep counter is on the device,
+    // so the launches of every such run are the same), which spares the host
+    // a launch call per kernel: on the small levels those calls took longer
+    // than the kernels.
     int *ctrl = reinterpret_cast<int *>(c->scal + 1);
     int *h_ctrl = reinterpret_cast<int *>(c->h_scal + 1);
     for (int l = NL; l >= 1; --l) {
-        const Phys P = level_phys(c, l);
-        const double thr = std::ldexp(c->prm.eps_p, -l);
-        const int lanes = c->blu_lanes;
-        const double *zl = c->zl[l];
-        double *Ul = c->Ul[l], *red = c->init_red;
         HIPCHK(c, launch_step1_reset(ctrl, c->stream));
-        int cnt = 0, sweep = 0;
+        int cnt = 0, rc;
         for (int ahead = 2;; ahead = std::min(2 * ahead, kStep1Ahead)) {
-            for (int k = 0; k < ahead; ++k, ++sweep) {
-                StopTest test;
-                test.partial = c->init_part;
-                test.n = blu_half_blocks(P, lanes);
-                test.sweep = sweep;
-                test.max_sweeps = c->prm.init_max_sweeps;
-                test.thr = thr;
-                test.ctrl = ctrl;
-                HIPCHK(c, launch_blu_half_io(P, zl, Ul, Ul, red, 0, 1, lanes, c->stream, ctrl,
-                                             StopTest(), c->init_part));
-                HIPCHK(c, launch_blu_half_io(P, zl, Ul, red, Ul, 1, 2, lanes, c->stream, ctrl,
-                                             test, nullptr));
-                HIPCHK(c, launch_blu_half_io(P, zl, red, Ul, Ul, 0, 1, lanes, c->stream, ctrl,
-                                             StopTest(), nullptr));
+            if (ahead == kStep1Ahead && c->step1_graph) {
+                hipGraphExec_t g;
+                if ((rc = step1_graph(c, l, &g))) return rc;
+                HIPCHK(c, hipGraphLaunch(g, c->stream));
+            } else if ((rc = step1_sweeps(c, l, ahead, c->stream))) {
+                return rc;
             }
             HIPCHK(c, hipMemcpyAsync(h_ctrl, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                      c->stream));
@@ -1117,6 +1164,7 @@ int create_ctx(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
         const int v = std::atoi(e);
         c->blu_lanes = (v == 1 || v == 4 || v == 16) ? v : -1;
     }
+    if (const char *e = std::getenv("NMG_STEP1_GRAPH")) c->step1_graph = std::atoi(e) != 0;
     const size_t esz = c->f32 ? sizeof(float) : sizeof(double);
     size_t total = 0;   // elements
     for (int l = 0; l <= c->NL; ++l) {
@@ -1182,6 +1230,9 @@ void nmg_destroy(nmg_ctx *c)
         (void)hipEventDestroy(e.second);
     }
     for (hipEvent_t e : c->pev) (void)hipEventDestroy(e);
+    for (hipGraphExec_t g : c->init_graph)
+        if (g) (void)hipGraphExecDestroy(g);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->pool) (void)hipFree(c->pool);
     if (c->At_alloc) (void)hipFree(c->At_alloc);
     for (double *q : {c->kV, c->kg, c->kx, c->kw, c->kpart, c->kdots, c->kcoef})

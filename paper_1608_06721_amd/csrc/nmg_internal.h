@@ -130,7 +130,8 @@ hipError_t launch_assemble(const Phys &P, const LevelGeom &G, const double *z, c
 hipError_t launch_residual(const Phys &P, const double *z, const double *U, double *R_out,
                            double *partial, hipStream_t s);
 
-// Reset of the Step 1 stop test's control words {stop flag, sweeps done}.
+// Reset of the Step 1 stop test's control words {stop flag, sweeps done,
+// sweep counts by parity}.
 hipError_t launch_step1_reset(int *ctrl, hipStream_t s);
 hipError_t launch_reduce(const double *partial, int n, double *out, hipStream_t s);
 hipError_t launch_count_u8(const unsigned char *v, long n, double *partial, hipStream_t s);
@@ -148,14 +149,16 @@ constexpr long kBluQuadMaxCells = 1L << 16;
 constexpr long kBluX16MaxCells = 1L << 14;
 // Step 1 stop test done by a BLU-SGS launch before its stores (no launch of
 // its own): every block sums the n partials of the level's residual norm
-// (written by the residual launch before it) in sum_partials' order, as
-// k_reduce does, and the sweep stops if ctrl[0] is already set, the sum is
-// below thr (or not a number), or `sweep` sweeps are done on the level and
-// that is max_sweeps.  Block 0 records a new stop: ctrl[0] = 1,
-// ctrl[1] = sweep.  partial == nullptr: no test.
+// (written by the launch before it) in sum_partials' order, as k_reduce
+// does, and the sweep stops if ctrl[0] is already set, the sum is below thr
+// (or not a number), or the sweeps done on the level, ctrl[2 + parity], are
+// max_sweeps.  Block 0 records a new stop (ctrl[0] = 1, ctrl[1] = sweeps
+// done) or counts the sweep in ctrl[2 + (parity ^ 1)], the slot the next
+// sweep reads, so no block reads a word that this launch writes.  parity:
+// the sweep's index on the level mod 2.  partial == nullptr: no test.
 struct StopTest {
     const double *partial = nullptr;
-    int n = 0, sweep = 0, max_sweeps = 0;
+    int n = 0, parity = 0, max_sweeps = 0;
     double thr = 0.0;
     int *ctrl = nullptr;
 };

@@ -634,6 +634,8 @@ __global__ void k_step1_reset(int *__restrict__ ctrl)
 {
     ctrl[0] = 0;
     ctrl[1] = 0;
+    ctrl[2] = 0;
+    ctrl[3] = 0;
 }
 
 __global__ void __launch_bounds__(kBlock) k_count_u8(const unsigned char *__restrict__ v, long n,
@@ -788,11 +790,16 @@ __device__ __forceinline__ bool stop_decision(const StopTest &st, double share)
 {
     if (!st.partial) return false;
     const bool stopped = st.ctrl[0] != 0;
+    const int done = st.ctrl[2 + st.parity];
     const double s = block_sum(share);
-    const bool stop = stopped || !(s >= st.thr) || st.sweep >= st.max_sweeps;
-    if (stop && !stopped && blockIdx.x == 0 && threadIdx.x == 0) {
-        st.ctrl[0] = 1;
-        st.ctrl[1] = st.sweep;
+    const bool stop = stopped || !(s >= st.thr) || done >= st.max_sweeps;
+    if (!stopped && blockIdx.x == 0 && threadIdx.x == 0) {
+        if (stop) {
+            st.ctrl[0] = 1;
+            st.ctrl[1] = done;
+        } else {
+            st.ctrl[2 + (st.parity ^ 1)] = done + 1;
+        }
     }
     return stop;
 }

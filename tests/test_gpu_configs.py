@@ -152,20 +152,23 @@ def test_phase_timing_and_step1_levels(nmg):
     assert lv == so
 
 
+@pytest.mark.parametrize("graph", ["1", "0"])
 @pytest.mark.parametrize("lanes", ["default", "1", "4", "16"])
-@pytest.mark.parametrize("cap", [0, 1, 2, 3, 6, 7, 17])
-def test_step1_sweep_cap_and_merged_sweeps(nmg, monkeypatch, lanes, cap):
+@pytest.mark.parametrize("cap", [0, 1, 2, 3, 6, 7, 17, 50])
+def test_step1_sweep_cap_and_merged_sweeps(nmg, monkeypatch, lanes, cap, graph):
     """Step 1 with its sweep cap binding on every level (eps_p far below the
     coarse residuals), caps crossing the runs of sweeps the host enqueues
-    ahead of its flag read (2, 4, 8, 16): the per-level counts equal the cap
-    and the state handed to Newton matches the oracle bit for bit, with one,
-    four or sixteen lanes per cell.  Then two Newton steps with two BLU-SGS
-    sweeps each, whose same-colour half sweeps run merged in one launch
-    (colours 0, 1 x2, 0 x2, 1 x2, 0)."""
+    ahead of its flag read (2, 4, 8, then 16 replayed from a graph, or
+    enqueued one by one with NMG_STEP1_GRAPH=0): the per-level counts equal
+    the cap and the state handed to Newton matches the oracle bit for bit,
+    with one, four or sixteen lanes per cell.  Then two Newton steps with two
+    BLU-SGS sweeps each, whose same-colour half sweeps run merged in one
+    launch (colours 0, 1 x2, 0 x2, 1 x2, 0)."""
     if lanes == "default":
         monkeypatch.delenv("NMG_BLU_LANES", raising=False)
     else:
         monkeypatch.setenv("NMG_BLU_LANES", lanes)
+    monkeypatch.setenv("NMG_STEP1_GRAPH", graph)
     base = W.channel(64, 32, n_levels=3, mound_amp=0.3, gamma=2)
     prob = base.with_params(eps_p=1e-300, init_max_sweeps=cap, max_newton=0)
     say("step1 cap", cap, "lanes", lanes)
@@ -175,6 +178,29 @@ def test_step1_sweep_cap_and_merged_sweeps(nmg, monkeypatch, lanes, cap):
     prob2 = base.with_params(eps_p=1e-300, init_max_sweeps=cap, max_newton=2, blu_sweeps=2)
     st2 = solve_both(nmg, prob2, 0.0)
     assert st2["newton_steps"] == 2
+
+
+def test_step1_graph_replays_across_solves(nmg):
+    """The Step 1 graphs are captured once per context and replayed by every
+    later solve: three solves on one context, with other GPU work and
+    synchronizations between them, each equal to the oracle bit for bit
+    (sweep counts, Newton steps, state)."""
+    prob = W.channel(64, 32, n_levels=3, mound_amp=0.3, gamma=2).with_params(
+        eps_p=1e-300, init_max_sweeps=45, max_newton=2)
+    Uo, so = oracle.newton_solve(prob, tol=0.0)
+    ctx = nmg.Context.from_problem(prob)
+    z = dev(prob.z)
+    for rep in range(3):
+        U = dev(prob.U0)
+        st = ctx.newton_mg_solve(z, U, 0.0)
+        say("graph replay", rep, st["init_level_sweeps"], st["newton_steps"])
+        assert st["init_level_sweeps"][:4] == [0, 45, 45, 45]
+        assert (st["init_sweeps"], st["newton_steps"]) == (so["init_sweeps"], so["newton_steps"])
+        same(host(U), Uo, "U, solve %d" % rep)
+        x = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        (x * x).sum().item()
+        torch.cuda.synchronize()
+    ctx.close()
 
 
 def test_full_size_step1(nmg):
