@@ -154,7 +154,7 @@ typedef struct {
  *                     4 in 1D); default: 16 in 2D on meshes of at most 2^14
  *                     cells per colour, 4 up to 2^16, else 1.
  *   NMG_STEP1_GRAPH   0: enqueue every Step 1 launch from the host; default
- *                     1: runs of 16 Step 1 sweeps on a level are captured
+ *                     1: runs of 64 Step 1 sweeps on a level are captured
  *                     once per context as a HIP graph (on a stream of the
  *                     context's own) and replayed on the context's stream. */
 int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,

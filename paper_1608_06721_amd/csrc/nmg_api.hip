@@ -951,8 +951,9 @@ int alloc_step1(nmg_ctx *c)
     return NMG_OK;
 }
 
-// Most sweeps of Step 1 enqueued between two looks at the stop flag.
-constexpr int kStep1Ahead = 16;
+// Most sweeps of Step 1 enqueued between two looks at the stop flag (even:
+// every run starts at an even sweep index, see step1_sweeps).
+constexpr int kStep1Ahead = 64;
 
 // The three launches of `n` Step 1 sweeps on level l (see nested_init); the
 // first sweep's index on the level is even.
@@ -1033,7 +1034,9 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
     // sweeps, reading the red states from init_red; the third the last red
     // half sweep from init_red into the level's state.  The test sets a flag
     // that gates the launches behind it, so runs of sweeps are enqueued ahead
-    // (2, 4, ... up to kStep1Ahead) and the host reads the flag once per run;
+    // (2, 4, ... up to kStep1Ahead, the last run before the sweep cap cut to
+    // end at it, rounded up to an even count) and the host reads the flag
+    // once per run;
     // after the stop nothing is stored.  The sweeps performed are those of
     // the loop with the test on the host.  Runs of kStep1Ahead sweeps are
     // replayed from a graph per level (the sweep counter is on the device,
@@ -1045,14 +1048,20 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
     for (int l = NL; l >= 1; --l) {
         HIPCHK(c, launch_step1_reset(ctrl, c->stream));
         int cnt = 0, rc;
+        long queued = 0;    // sweeps enqueued on the level
         for (int ahead = 2;; ahead = std::min(2 * ahead, kStep1Ahead)) {
-            if (ahead == kStep1Ahead && c->step1_graph) {
+            // the test at sweep index init_max_sweeps stops for certain
+            const long need = (long)c->prm.init_max_sweeps + 1 - queued;
+            int n = (int)std::min<long>(ahead, std::max<long>(need, 1));
+            n += n & 1;
+            if (n == kStep1Ahead && c->step1_graph) {
                 hipGraphExec_t g;
                 if ((rc = step1_graph(c, l, &g))) return rc;
                 HIPCHK(c, hipGraphLaunch(g, c->stream));
-            } else if ((rc = step1_sweeps(c, l, ahead, c->stream))) {
+            } else if ((rc = step1_sweeps(c, l, n, c->stream))) {
                 return rc;
             }
+            queued += n;
             HIPCHK(c, hipMemcpyAsync(h_ctrl, ctrl, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                      c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));

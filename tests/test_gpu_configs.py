@@ -154,12 +154,13 @@ def test_phase_timing_and_step1_levels(nmg):
 
 @pytest.mark.parametrize("graph", ["1", "0"])
 @pytest.mark.parametrize("lanes", ["default", "1", "4", "16"])
-@pytest.mark.parametrize("cap", [0, 1, 2, 3, 6, 7, 17, 50])
+@pytest.mark.parametrize("cap", [0, 1, 2, 3, 6, 7, 17, 50, 130])
 def test_step1_sweep_cap_and_merged_sweeps(nmg, monkeypatch, lanes, cap, graph):
     """Step 1 with its sweep cap binding on every level (eps_p far below the
     coarse residuals), caps crossing the runs of sweeps the host enqueues
-    ahead of its flag read (2, 4, 8, then 16 replayed from a graph, or
-    enqueued one by one with NMG_STEP1_GRAPH=0): the per-level counts equal
+    ahead of its flag read (2, 4, ..., 32, then 64 replayed from a graph or,
+    with NMG_STEP1_GRAPH=0, enqueued one by one, the last run cut to end at
+    the cap and rounded up to an even count): the per-level counts equal
     the cap and the state handed to Newton matches the oracle bit for bit,
     with one, four or sixteen lanes per cell.  Then two Newton steps with two
     BLU-SGS sweeps each, whose same-colour half sweeps run merged in one
@@ -182,11 +183,12 @@ def test_step1_sweep_cap_and_merged_sweeps(nmg, monkeypatch, lanes, cap, graph):
 
 def test_step1_graph_replays_across_solves(nmg):
     """The Step 1 graphs are captured once per context and replayed by every
-    later solve: three solves on one context, with other GPU work and
+    later solve (two replays per level and solve with a cap of 200 sweeps):
+    three solves on one context, with other GPU work and
     synchronizations between them, each equal to the oracle bit for bit
     (sweep counts, Newton steps, state)."""
     prob = W.channel(64, 32, n_levels=3, mound_amp=0.3, gamma=2).with_params(
-        eps_p=1e-300, init_max_sweeps=45, max_newton=2)
+        eps_p=1e-300, init_max_sweeps=200, max_newton=2)
     Uo, so = oracle.newton_solve(prob, tol=0.0)
     ctx = nmg.Context.from_problem(prob)
     z = dev(prob.z)
@@ -194,7 +196,7 @@ def test_step1_graph_replays_across_solves(nmg):
         U = dev(prob.U0)
         st = ctx.newton_mg_solve(z, U, 0.0)
         say("graph replay", rep, st["init_level_sweeps"], st["newton_steps"])
-        assert st["init_level_sweeps"][:4] == [0, 45, 45, 45]
+        assert st["init_level_sweeps"][:4] == [0, 200, 200, 200]
         assert (st["init_sweeps"], st["newton_steps"]) == (so["init_sweeps"], so["newton_steps"])
         same(host(U), Uo, "U, solve %d" % rep)
         x = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
