@@ -181,6 +181,29 @@ def test_step1_sweep_cap_and_merged_sweeps(nmg, monkeypatch, lanes, cap, graph):
     assert st2["newton_steps"] == 2
 
 
+@pytest.mark.parametrize("lanes", ["default", "1", "4", "16"])
+@pytest.mark.parametrize("cap", [5, 70])
+def test_step1_odd_levels(nmg, monkeypatch, lanes, cap):
+    """Step 1 on a mesh whose coarse levels are odd (72 x 40: 36 x 20,
+    18 x 10, 9 x 5), where a slot of the colour-split order holds a cell of
+    one colour and not of the other, so the first launch of a sweep covers
+    residual cells the half sweep does not: sweep cap binding (eps_p far
+    below the residuals) and threshold stops at different sweeps per level
+    (eps_p at 0.5 and 2 times the initial residual: 8, 8, 65 and 2, 3, 28
+    sweeps under a cap of 70), against the oracle bit for bit."""
+    if lanes == "default":
+        monkeypatch.delenv("NMG_BLU_LANES", raising=False)
+    else:
+        monkeypatch.setenv("NMG_BLU_LANES", lanes)
+    base = W.channel(72, 40, n_levels=3, mound_amp=0.3, gamma=2)
+    r0 = oracle.residual(base, oracle.threshold(base, base.U0))[1]
+    for eps_p in (1e-300, 0.5 * r0, 2.0 * r0):
+        prob = base.with_params(eps_p=eps_p, init_max_sweeps=cap, max_newton=1)
+        say("step1 odd levels", lanes, cap, eps_p)
+        st = solve_both(nmg, prob, 0.0)
+        assert st["init_level_sweeps"][:4] == oracle.nested_init(prob)[1]
+
+
 def test_step1_graph_replays_across_solves(nmg):
     """The Step 1 graphs are captured once per context and replayed by every
     later solve (two replays per level and solve with a cap of 200 sweeps):
