@@ -213,7 +213,11 @@ int nmg_blu_sweep(nmg_ctx *ctx, const double *z, double *U);
  * returned iterate).  Each step: BLU-SGS sweeps, assembly, stop test
  * sum ||R_i||_1 < tol (the returned U is then the tested state), n_mg
  * V-cycles from dU = 0, relaxed update and dry threshold.  Returns OK,
- * NOT_CONVERGED, ENONFINITE, EDIVERGED or an error.  stats (host) nullable. */
+ * NOT_CONVERGED, ENONFINITE, EDIVERGED or an error.  stats (host) nullable.
+ * With Step 1 (eps_p > 0) and NMG_STEP1_GRAPH on, the first solve on a
+ * context also creates a capture stream and one HIP graph per coarse level
+ * (kept, and freed by nmg_destroy); the host synchronizes with the
+ * context's stream once per run of Step 1 sweeps. */
 int nmg_newton_mg_solve(nmg_ctx *ctx, const double *z, double *U, double tol,
                         nmg_stats *stats);
 
