@@ -149,8 +149,8 @@ constexpr long kBluQuadMaxCells = 1L << 16;
 constexpr long kBluX16MaxCells = 1L << 14;
 // Step 1 stop test done by a BLU-SGS launch before its stores (no launch of
 // its own): every block sums the n partials of the level's residual norm
-// (written by the launch before it) in sum_partials' order, as k_reduce
-// does, and the sweep stops if ctrl[0] is already set, the sum is below thr
+// (written by the launch before it) in one fixed order, the same in every
+// block, and the sweep stops if ctrl[0] is already set, the sum is below thr
 // (or not a number), or the sweeps done on the level, ctrl[2 + parity], are
 // max_sweeps.  Block 0 records a new stop (ctrl[0] = 1, ctrl[1] = sweeps
 // done) or counts the sweep in ctrl[2 + (parity ^ 1)], the slot the next

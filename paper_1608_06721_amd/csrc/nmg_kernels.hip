@@ -773,6 +773,27 @@ __device__ __forceinline__ void blu_cell(const Phys &P, const double *__restrict
     for (int c = 0; c < NC; ++c) U[c * N + idx] = q[c];
 }
 
+// Sum of one double per thread over the block for the Step 1 stop test:
+// each wave's lane 0 sums its wave by a butterfly of lane exchanges, then
+// every thread adds the waves' sums in wave order, so all threads hold the
+// same value.  Two barriers instead of block_sum's eight (the order of this
+// sum is the GPU's own: the oracle sums the cells in index order, and only
+// the comparison with the threshold uses it).
+__device__ __forceinline__ double block_sum_step1(double v)
+{
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double ws[kWaves];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) s = s + ws[w];
+    __syncthreads();
+    return s;
+}
+
 // This thread's share of the stop test's partials (the first stage of
 // sum_partials), loaded before the cell's arithmetic so their latency
 // overlaps it.
@@ -791,7 +812,7 @@ __device__ __forceinline__ bool stop_decision(const StopTest &st, double share)
     if (!st.partial) return false;
     const bool stopped = st.ctrl[0] != 0;
     const int done = st.ctrl[2 + st.parity];
-    const double s = block_sum(share);
+    const double s = block_sum_step1(share);
     const bool stop = stopped || !(s >= st.thr) || done >= st.max_sweeps;
     if (!stopped && blockIdx.x == 0 && threadIdx.x == 0) {
         if (stop) {
@@ -805,14 +826,11 @@ __device__ __forceinline__ bool stop_decision(const StopTest &st, double share)
 }
 
 // Block partial of a launch's residual output (res_partial[xb]): the sum of
-// its threads' norms.  Followed by a barrier, so that a later block_sum in
-// the same launch cannot overwrite the shared array before every thread
-// has read this one's result.
+// its threads' norms.
 __device__ __forceinline__ void residual_partial(double *res_partial, int xb, double nrm)
 {
-    const double s = block_sum(nrm);
+    const double s = block_sum_step1(nrm);
     if (threadIdx.x == 0) res_partial[xb] = s;
-    __syncthreads();
 }
 
 // A BLU-SGS half sweep: the cells of `color` read their own state from Uown
