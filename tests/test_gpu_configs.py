@@ -204,6 +204,29 @@ def test_step1_odd_levels(nmg, monkeypatch, lanes, cap):
         assert st["init_level_sweeps"][:4] == oracle.nested_init(prob)[1]
 
 
+@pytest.mark.parametrize("fp32", [0, 1])
+@pytest.mark.parametrize("lanes", ["default", "1", "4", "16"])
+@pytest.mark.parametrize("flux", ["HLL", "HLLC", "LLF"])
+def test_step1_fluxes_lanes_fp32(nmg, monkeypatch, flux, lanes, fp32):
+    """Step 1 and two Newton steps on a 48 x 24 channel with each numerical
+    flux (the ghost states, wave speeds and, for HLLC, the contact speed go
+    through every lane layout's edge terms and the first launch's residual
+    norms), each lane count, FP64 and FP32 inner cycles: per-level sweeps
+    (threshold at half the initial residual, cap 12), Newton steps and state
+    equal to the oracle bit for bit."""
+    if lanes == "default":
+        monkeypatch.delenv("NMG_BLU_LANES", raising=False)
+    else:
+        monkeypatch.setenv("NMG_BLU_LANES", lanes)
+    base = W.channel(48, 24, n_levels=3, mound_amp=0.3, gamma=2, flux=getattr(W, flux))
+    r0 = oracle.residual(base, oracle.threshold(base, base.U0))[1]
+    prob = base.with_params(eps_p=0.5 * r0, init_max_sweeps=12, max_newton=2, inner_fp32=fp32)
+    say("step1 flux", flux, "lanes", lanes, "fp32", fp32)
+    st = solve_both(nmg, prob, 0.0)
+    assert st["init_level_sweeps"][:4] == oracle.nested_init(prob)[1]
+    assert st["newton_steps"] == 2
+
+
 def test_step1_graph_replays_across_solves(nmg):
     """The Step 1 graphs are captured once per context and replayed by every
     later solve (two replays per level and solve with a cap of 200 sweeps):
