@@ -252,10 +252,10 @@ __device__ __forceinline__ double quad_bcast(double v)
 // Residual and forward-difference blocks of one cell.  D receives
 // sum_e |e| dT/dU_i, Off[f] receives |e| dT/dU_j for interior faces.
 // Off-diagonal blocks are handed to `off(f, r, k, value)` as soon as face f
-// is done (value 0 on boundary faces), so no per-face array is kept.  With
-// UNROLL the face loop is unrolled, so that each face's orientation (which
-// side is left, which momentum is normal) is fixed at compile time instead
-// of being selected per evaluation: about 30 % fewer instructions.
+// is done (value 0 on boundary faces), so no per-face array is kept.  The
+// face loop is unrolled, so that each face's orientation (which side is
+// left, which momentum is normal) is fixed at compile time instead of being
+// selected per evaluation: about 30 % fewer instructions.
 struct NoOff {
     __device__ void operator()(int, int, int, double) const {}
 };
@@ -303,7 +303,7 @@ __device__ __forceinline__ void load_nbrs(const Phys &P, const double *z, const 
 // cell_jacobian at the cell state qi (bed zi).  With PRE the neighbours come
 // from nb; otherwise each face loads its own (with the off-diagonal blocks,
 // loading them all first would take the kernel past 256 registers).
-template <int NC, bool WANT_OFF, bool UNROLL, bool PRE, class OffSink>
+template <int NC, bool WANT_OFF, bool PRE, class OffSink>
 __device__ __forceinline__ void cell_jacobian_at(const Phys &P, const double *z, const double *U,
                                                  int i, int j, const double *qi, double zi,
                                                  const Nbrs<NC> &nb, double *Rc, double (*D)[NC],
@@ -390,16 +390,11 @@ __device__ __forceinline__ void cell_jacobian_at(const Phys &P, const double *z,
             }
         }
     };
-    if constexpr (UNROLL) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) face(f);
-    } else {
-#pragma unroll 1
-        for (int f = 0; f < NF; ++f) face(f);
-    }
+    for (int f = 0; f < NF; ++f) face(f);
 }
 
-template <int NC, bool WANT_OFF, bool UNROLL, class OffSink>
+template <int NC, bool WANT_OFF, class OffSink>
 __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, const double *U, int i,
                                               int j, double *Rc, double (*D)[NC], const OffSink &off)
 {
@@ -407,7 +402,7 @@ __device__ __forceinline__ void cell_jacobian(const Phys &P, const double *z, co
     double qi[NC];
     load_state<NC>(P, U, idx, qi);
     Nbrs<NC> none;
-    cell_jacobian_at<NC, WANT_OFF, UNROLL, false>(P, z, U, i, j, qi, z[idx], none, Rc, D, off);
+    cell_jacobian_at<NC, WANT_OFF, false>(P, z, U, i, j, qi, z[idx], none, Rc, D, off);
 }
 
 template <int NC>
@@ -508,7 +503,7 @@ __device__ __forceinline__ double assemble_cell(const Phys &P, const LevelGeom &
             st.nb_iso[f] = f < NF && neighbour(P, i, j, f, ni, nj) && iso[(long)nj * P.nx + ni];
         }
         double Rc[NC], D[NC][NC];
-        cell_jacobian<NC, true, sizeof(T) == 8>(P, z, U, i, j, Rc, D, st);
+        cell_jacobian<NC, true>(P, z, U, i, j, Rc, D, st);
         if (R_out) {
 #pragma unroll
             for (int r = 0; r < NC; ++r) R_out[r * N + idx] = Rc[r];
@@ -754,7 +749,7 @@ __device__ __forceinline__ bool blu_cell_update(const Phys &P, const double *__r
     for (int rep = 0; rep < reps; ++rep) {
         opaque_nbrs<NC>(nb);
         double Rc[NC], D[NC][NC];
-        cell_jacobian_at<NC, false, true, true>(P, z, Unb, i, j, q, zi, nb, Rc, D, NoOff());
+        cell_jacobian_at<NC, false, true>(P, z, Unb, i, j, q, zi, nb, Rc, D, NoOff());
         const double nrm = blu_solve<NC>(P, Rc, D, q);
         if (rep == 0) nrm0 = nrm;
     }
