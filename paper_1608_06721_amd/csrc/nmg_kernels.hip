@@ -1374,7 +1374,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict_res(LevelGeom G, const T *_
 
 // Galerkin coarse blocks (eq:ProjectAR, left) with the child-pair order of
 // the definition: children of I (SW, SE, NW, NE), then children of J.
-template <class T, int NC>
+// STREAM: the fine blocks (each read once) are loaded with the non-temporal
+// hint.
+template <class T, int NC, bool STREAM = false>
 __device__ __forceinline__ void galerkin_cell(const LevelGeom &Gf, const T *__restrict__ Af,
                                               const LevelGeom &Gc, T *__restrict__ Ac, long t)
 {
@@ -1385,7 +1387,8 @@ __device__ __forceinline__ void galerkin_cell(const LevelGeom &Gf, const T *__re
     // child (ci, cj) block blk entry e -> pointer
     auto ent = [&](int ci, int cj, int blk, int e) -> T {
         int col = (ci + cj) & 1;
-        return Af[mat_off(Gf, NE, col, (long)cj * Gf.W + (ci >> 1)) + (blk * NN + e) * kTile];
+        return ld_once<T, STREAM>(
+            &Af[mat_off(Gf, NE, col, (long)cj * Gf.W + (ci >> 1)) + (blk * NN + e) * kTile]);
     };
     const int cc = (I + J) & 1;
     T *out = Ac + mat_off(Gc, NE, cc, (long)J * Gc.W + (I >> 1));
@@ -1435,13 +1438,13 @@ __device__ __forceinline__ void galerkin_cell(const LevelGeom &Gf, const T *__re
     }
 }
 
-template <class T, int NC>
+template <class T, int NC, bool STREAM = false>
 __global__ void __launch_bounds__(kBlock) k_galerkin(LevelGeom Gf, const T *__restrict__ Af,
                                                      LevelGeom Gc, T *__restrict__ Ac)
 {
     long t = (long)blockIdx.x * kBlock + threadIdx.x;
     if (t >= (long)Gc.nx * Gc.ny) return;
-    galerkin_cell<T, NC>(Gf, Af, Gc, Ac, t);
+    galerkin_cell<T, NC, STREAM>(Gf, Af, Gc, Ac, t);
 }
 
 template <class T, int NC>
@@ -3367,6 +3370,9 @@ hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *A
         NMG_LAUNCH((k_galerkin<float, 3>), g, Gf, (const float *)Af, Gc, (float *)Ac);
     }
     if (dim == 1) NMG_LAUNCH((k_galerkin<double, 2>), g, Gf, (const double *)Af, Gc, (double *)Ac);
+    // the finest level's blocks stream through once: non-temporal loads
+    if (Gf.planeP * 45L * 2 * 8 > (64L << 20))
+        NMG_LAUNCH((k_galerkin<double, 3, true>), g, Gf, (const double *)Af, Gc, (double *)Ac);
     NMG_LAUNCH((k_galerkin<double, 3>), g, Gf, (const double *)Af, Gc, (double *)Ac);
 }
 
