@@ -1387,8 +1387,9 @@ __device__ __forceinline__ void galerkin_cell(const LevelGeom &Gf, const T *__re
     // child (ci, cj) block blk entry e -> pointer
     auto ent = [&](int ci, int cj, int blk, int e) -> T {
         int col = (ci + cj) & 1;
-        return ld_once<T, STREAM>(
-            &Af[mat_off(Gf, NE, col, (long)cj * Gf.W + (ci >> 1)) + (blk * NN + e) * kTile]);
+        const T *p = &Af[mat_off(Gf, NE, col, (long)cj * Gf.W + (ci >> 1)) + (blk * NN + e) * kTile];
+        if constexpr (STREAM) return __builtin_nontemporal_load(p);
+        else return *p;
     };
     const int cc = (I + J) & 1;
     T *out = Ac + mat_off(Gc, NE, cc, (long)J * Gc.W + (I >> 1));
@@ -3367,6 +3368,8 @@ hipError_t launch_galerkin(int dim, bool f32, const LevelGeom &Gf, const void *A
     int g = nblocks((long)Gc.nx * Gc.ny);
     if (f32) {
         if (dim == 1) NMG_LAUNCH((k_galerkin<float, 2>), g, Gf, (const float *)Af, Gc, (float *)Ac);
+        if (Gf.planeP * 45L * 2 * 4 > (64L << 20))
+            NMG_LAUNCH((k_galerkin<float, 3, true>), g, Gf, (const float *)Af, Gc, (float *)Ac);
         NMG_LAUNCH((k_galerkin<float, 3>), g, Gf, (const float *)Af, Gc, (float *)Ac);
     }
     if (dim == 1) NMG_LAUNCH((k_galerkin<double, 2>), g, Gf, (const double *)Af, Gc, (double *)Ac);
