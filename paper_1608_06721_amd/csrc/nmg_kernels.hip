@@ -800,19 +800,27 @@ __device__ __forceinline__ double stop_share(const StopTest &st)
     return v;
 }
 
+// The Step 1 stop flag: block 0 of the launch that takes the decision sets it
+// while other blocks of that launch may read it, so it is accessed with
+// relaxed atomics (a set flag only ever agrees with their own decision).
+__device__ __forceinline__ bool flag_set(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
 // The stop decision of a launch with a stop test; every thread of the block
-// takes part (block_sum synchronizes) and gets the same answer.
+// takes part (block_sum_step1 synchronizes) and gets the same answer.
 __device__ __forceinline__ bool stop_decision(const StopTest &st, double share)
 {
     if (!st.partial) return false;
-    const bool stopped = st.ctrl[0] != 0;
+    const bool stopped = flag_set(st.ctrl);
     const int done = st.ctrl[2 + st.parity];
     const double s = block_sum_step1(share);
     const bool stop = stopped || !(s >= st.thr) || done >= st.max_sweeps;
     if (!stopped && blockIdx.x == 0 && threadIdx.x == 0) {
         if (stop) {
-            st.ctrl[0] = 1;
             st.ctrl[1] = done;
+            __hip_atomic_store(st.ctrl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             st.ctrl[2 + (st.parity ^ 1)] = done + 1;
         }
@@ -859,7 +867,7 @@ __global__ void __launch_bounds__(kBlock) k_blu_half(Phys P, const double *__res
         residual_partial(res_partial, xb, nrm);
     }
     const bool stop = stop_decision(st, share);
-    if (!cell || stop || (gate && *gate)) return;
+    if (!cell || stop || (gate && flag_set(gate))) return;
 #pragma unroll
     for (int c = 0; c < NC; ++c) Uout[c * N + idx] = q[c];
 }
@@ -1004,7 +1012,7 @@ __global__ void __launch_bounds__(kBlock) k_blu_half_quad(Phys P, const double *
         residual_partial(res_partial, xb, nrm + nrm1);
     }
     const bool stop = stop_decision(st, share);
-    if (!cell || k != 0 || stop || (gate && *gate)) return;
+    if (!cell || k != 0 || stop || (gate && flag_set(gate))) return;
 #pragma unroll
     for (int c = 0; c < NC; ++c) Uout[c * N + idx] = q[c];
 }
@@ -1154,7 +1162,7 @@ __global__ void __launch_bounds__(kBlock) k_blu_half_x16(Phys P, const double *_
         residual_partial(res_partial, xb, nrm);
     }
     const bool stop = stop_decision(st, share);
-    if (!cell || lane != 0 || stop || (gate && *gate)) return;
+    if (!cell || lane != 0 || stop || (gate && flag_set(gate))) return;
 #pragma unroll
     for (int c = 0; c < 3; ++c) Uout[c * N + idx] = q[c];
 }
