@@ -1054,9 +1054,16 @@ int nested_init(nmg_ctx *c, const double *z, double *U, int *sweeps, int *level_
             const long need = (long)c->prm.init_max_sweeps + 1 - queued;
             int n = (int)std::min<long>(ahead, std::max<long>(need, 1));
             n += n & 1;
-            if (n == kStep1Ahead && c->step1_graph) {
-                hipGraphExec_t g;
-                if ((rc = step1_graph(c, l, &g))) return rc;
+            hipGraphExec_t g = nullptr;
+            if (n == kStep1Ahead && c->step1_graph && step1_graph(c, l, &g) != NMG_OK) {
+                // no graph (capture or instantiation refused): enqueue the
+                // launches one by one from now on
+                c->step1_graph = 0;
+                c->err.clear();
+                (void)hipGetLastError();
+                g = nullptr;
+            }
+            if (g) {
                 HIPCHK(c, hipGraphLaunch(g, c->stream));
             } else if ((rc = step1_sweeps(c, l, n, c->stream))) {
                 return rc;
