@@ -156,7 +156,9 @@ typedef struct {
  *   NMG_STEP1_GRAPH   0: enqueue every Step 1 launch from the host; default
  *                     1: runs of 64 Step 1 sweeps on a level are captured
  *                     once per context as a HIP graph (on a stream of the
- *                     context's own) and replayed on the context's stream. */
+ *                     context's own) and replayed on the context's stream
+ *                     (if capture or instantiation fails, the context
+ *                     enqueues the launches one by one instead). */
 int nmg_create(const nmg_grid *grid, const nmg_bc *bc, const nmg_params *params,
                void *stream, nmg_ctx **out);
 void nmg_destroy(nmg_ctx *ctx);
